@@ -1,0 +1,65 @@
+"""Statistical pin of the oracle's block soft output against the paper's Fig. 2.
+
+The paper shows that the predicted probability that the transmitted codeword is
+not in the list (eq. app_approxlist) matches the empirical list-BLER for eBCH
+codes (L = 4, 2 dB).  The oracle's prediction, binned per half decade, must be
+as well calibrated as the paper's own points: a wrong hit probability phi, a
+dropped mass term or a wrong parity-class reading shifts the curve off the
+diagonal by a large factor.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig2_list_bler_calibration.txt")
+
+
+def paper_points():
+    pts = {}
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        nk, p, e = line.split()
+        pts.setdefault(tuple(int(x) for x in nk.split(",")), []).append((float(p), float(e)))
+    return pts
+
+
+def calibration(code, words, seed):
+    llr, cw, _ = synth.component_words(code, 2.0, seed, np.arange(words))
+    out = oracle.decode_component(code, llr, 4, 10 ** 5, want_z=True)
+    y = (llr < 0).astype(np.uint8)
+    in_list = np.zeros(words, dtype=bool)
+    for l in range(4):
+        ok = l < out["n_found"]
+        match = np.all((y ^ out["found_z"][:, l]) == cw, axis=1)
+        in_list |= ok & match
+    pred = out["p_notfound"]
+    bins = np.floor(-2 * np.log10(np.maximum(pred, 1e-300))).astype(int)
+    rows = []
+    for b in range(0, 8):
+        sel = bins == b
+        if sel.sum() == 0:
+            continue
+        errs = int((~in_list[sel]).sum())
+        rows.append((float(pred[sel].mean()), errs / sel.sum(), errs, int(sel.sum())))
+    return rows
+
+
+@pytest.mark.parametrize("nk,words", [((16, 11), 60000), ((32, 26), 60000), ((64, 57), 40000)])
+def test_list_bler_calibration_matches_fig2(nk, words):
+    pts = paper_points()[nk]
+    # the paper's own points lie within 25% of the diagonal
+    assert all(0.75 <= e / p <= 1.25 for p, e in pts)
+    rows = calibration(synth.ebch(*nk), words, seed=101)
+    checked = 0
+    for pred, emp, errs, cnt in rows:
+        if errs < 40:
+            continue
+        checked += 1
+        sd = np.sqrt(pred * (1 - pred) / cnt)
+        assert abs(emp - pred) <= 0.25 * pred + 4 * sd, (nk, pred, emp, errs, cnt)
+    assert checked >= 3
