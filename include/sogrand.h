@@ -1,0 +1,159 @@
+/*
+ * libsogrand -- soft-output GRAND (SOGRAND) decoding of product codes on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is that of Yuan, Medard, Galligan and Duffy, "Soft-output (SO)
+ * GRAND and iterative decoding to outperform LDPCs" (arXiv 2310.10737):
+ *   - GRAND list decoding: noise-effect patterns are queried in order and a
+ *     pattern is a hit when the corrected word passes H c = 0 (section
+ *     "Background on GRAND"); the list ends after L hits or a query cap;
+ *   - query order: basic ORBGRAND (bits ranked by |LLR|; patterns by
+ *     logistic weight = sum of ranks, then Hamming weight, then the rank
+ *     tuple in lexicographic order), with the even-code parity skip;
+ *   - block soft output: Corollary 1 (eqs. app_approx_correct and
+ *     app_approxlist), applied within the parity class for even codes;
+ *   - bitwise soft output: eq. (LLRi); L_E = L_APP - L_A - L_Ch (section
+ *     "Bitwise SO accuracy", SISO decoder);
+ *   - product codes: block turbo decoding with L_A = alpha L_E between row and
+ *     column passes and a stop when every row and column of the hard decision
+ *     is a codeword (section "Iterative decoding").
+ *
+ * Conventions used by every call:
+ *   - An LLR is log p(bit = 0) / p(bit = 1): positive means bit 0.  A zero LLR
+ *     decides bit 0.  BPSK maps bit 0 to +1.
+ *   - All functions return 0 (SOGRAND_OK) or a negative SOGRAND_E* code and
+ *     never throw; sogrand_last_error() gives a message for the calling thread.
+ *   - Buffers named "device" are device memory owned by the caller (for
+ *     example torch tensors' data_ptr()); the library never frees them and
+ *     never keeps a pointer to them after the call's stream work completes.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Decode calls are asynchronous on that stream: they enqueue kernels and
+ *     stream-ordered allocations and return without synchronising.  Calls on
+ *     different streams may run concurrently; a code handle may be shared.
+ *   - Sizes: 2 <= n <= 128, 1 <= n-k <= 32, 1 <= list_max <= 16,
+ *     1 <= query_cap <= 2^24.
+ */
+#ifndef SOGRAND_H
+#define SOGRAND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SOGRAND_OK 0
+#define SOGRAND_EINVAL (-1)    /* bad argument: size, range or NULL pointer      */
+#define SOGRAND_ENOMEM (-2)    /* host or device allocation failed               */
+#define SOGRAND_EDEVICE (-3)   /* a HIP runtime call or kernel launch failed     */
+#define SOGRAND_EAGAIN (-4)    /* serving: admission refused, retry later        */
+#define SOGRAND_ENOTFOUND (-5) /* serving: unknown request / nothing completed   */
+#define SOGRAND_ETIMEDOUT (-6) /* serving: poll deadline passed                  */
+
+#define SOGRAND_NMAX 128
+#define SOGRAND_LIST_MAX 16
+#define SOGRAND_QUERY_CAP_MAX (1u << 24)
+
+/* Storage precision of the LLR buffers of a call.  The decoder computes in
+   binary64 in both cases; SOGRAND_F32 only reads and writes binary32. */
+#define SOGRAND_F64 0
+#define SOGRAND_F32 1
+
+/* Message for the last failed call on this thread (never NULL). */
+const char *sogrand_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int sogrand_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Codes                                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct sogrand_code sogrand_code_t; /* opaque, immutable, library-owned */
+
+/* A binary linear [n, k] code given by its parity-check matrix: h_cols is a
+   HOST array of n entries, bit r of h_cols[j] is H[r][j], r < n-k; H must have
+   full rank n-k.  Whether the code is even (every codeword of even weight, so
+   that only one pattern parity is queried) is derived from H.  The library
+   copies h_cols; *out is released with sogrand_code_destroy.
+   Errors: EINVAL (sizes, rank), ENOMEM. */
+int sogrand_code_create(int n, int k, const uint32_t *h_cols, sogrand_code_t **out);
+
+/* Extended BCH codes of length 2^m: [8,4], [16,11], [32,26], [64,57],
+   [128,120] (extended Hamming) and [16,7] (t = 2), built from the primitive
+   polynomials x^3+x+1, x^4+x+1, x^5+x^2+1, x^6+x+1, x^7+x^3+1.  Any basis of
+   the dual code gives the same decoding.  Errors: EINVAL for other (n, k). */
+int sogrand_code_create_ebch(int n, int k, sogrand_code_t **out);
+
+/* n, k, evenness and the n parity-check columns (h_cols may be NULL). */
+int sogrand_code_info(const sogrand_code_t *code, int *n, int *k, int *is_even, uint32_t *h_cols);
+
+void sogrand_code_destroy(sogrand_code_t *code);
+
+/* ------------------------------------------------------------------------ */
+/* Parameters                                                               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int list_max;       /* L: stop after this many codewords, 1..16                */
+    uint32_t query_cap; /* stop after this many tested patterns, 1..2^24          */
+    double alpha;       /* product codes: L_A = alpha * L_E, > 0 (paper: 0.5)     */
+    int max_iter;       /* product codes: full row+column iterations, 1..1000     */
+    int early_stop;     /* product codes: stop once the hard decision is valid    */
+    int precision;      /* SOGRAND_F64 or SOGRAND_F32 LLR storage                 */
+} sogrand_params_t;
+
+/* Fills the paper's settings: L = 4, cap 1000, alpha 0.5, 4 iterations,
+   early stop on, binary64 storage. */
+void sogrand_params_default(sogrand_params_t *p);
+
+/* ------------------------------------------------------------------------ */
+/* Component SISO decoding (section "Bitwise SO accuracy", Fig. SISO)       */
+/* ------------------------------------------------------------------------ */
+/* Decodes nwords independent words.  llr_in is the SISO input
+   lambda = L_Ch + L_A, DEVICE, row-major [nwords][n], binary64 or binary32 per
+   params->precision.  Outputs, all DEVICE and each optional (NULL = not written):
+     llr_app  [nwords][n]            L_APP by eq. (LLRi), clamped to +-1000
+     llr_ext  [nwords][n]            L_E = L_APP - lambda
+     hard     [nwords][n]  uint8     1 iff L_APP < 0
+     n_queries[nwords]     uint32    patterns tested (the query count)
+     n_found  [nwords]     uint8     codewords in the list (<= list_max)
+     found_q  [nwords][list_max]     query number of each found codeword
+     p_found  [nwords][list_max]     APP of each found codeword (Corollary 1)
+     p_notfound [nwords]   double    probability the codeword is not in the list
+     found_z  [nwords][list_max][n]  uint8 error pattern of each found codeword
+   Entries of found_q / p_found / found_z past n_found are written as zero.
+   Errors: EINVAL (params, sizes, llr_in NULL), ENOMEM, EDEVICE. */
+int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t *params,
+                             size_t nwords, const void *llr_in, void *llr_app, void *llr_ext,
+                             uint8_t *hard, uint32_t *n_queries, uint8_t *n_found,
+                             uint32_t *found_q, double *p_found, double *p_notfound,
+                             uint8_t *found_z, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Product codes: block turbo decoding (section "Iterative decoding")       */
+/* ------------------------------------------------------------------------ */
+/* Decodes nframes frames of an (n^2, k^2) product code whose rows and columns
+   are words of `code`.  llr_ch: DEVICE [nframes][n][n] channel LLRs (row-major,
+   precision per params).  Half-iteration h = 1, 2, ... decodes every row (h
+   odd) or column (h even) of L_Ch + L_A; after each, the hard decision of
+   L_APP is tested (every row and column a codeword) and, unless the frame
+   stops, L_A = alpha * L_E.  Outputs (DEVICE):
+     hard      [nframes][n][n] uint8  final hard decision (required)
+     llr_app   [nframes][n][n]        final L_APP (optional, precision per params)
+     success   [nframes] uint8        1 iff the final hard decision is valid (required)
+     half_iters[nframes] uint16       half-iterations run (optional)
+     sum_queries     [nframes] uint64 patterns tested over all words (optional)
+     sum_max_queries [nframes] uint64 sum over half-iterations of the largest
+                                      per-word query count (optional)
+   The library allocates its work buffers stream-ordered on `stream`.
+   Errors: EINVAL, ENOMEM, EDEVICE. */
+int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *params,
+                           size_t nframes, const void *llr_ch, uint8_t *hard, void *llr_app,
+                           uint8_t *success, uint16_t *half_iters, uint64_t *sum_queries,
+                           uint64_t *sum_max_queries, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOGRAND_H */

@@ -1,0 +1,210 @@
+"""Python binding of libsogrand (SOGRAND decoding of product codes on MI355X).
+
+Argument marshalling only: every decoding step runs in the HIP kernels of
+``libsogrand.so`` behind the C ABI declared in ``include/sogrand.h``.  PyTorch
+provides device memory and the current HIP stream.  There is no fallback: if
+the shared library is missing, every call raises ``SograndError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "SograndError", "Code", "params", "lib", "library_path",
+    "sogrand_decode_component", "sogrand_decode_product",
+    "SOGRAND_F64", "SOGRAND_F32",
+]
+
+SOGRAND_F64 = 0
+SOGRAND_F32 = 1
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libsogrand.so")
+_lib = None
+
+EXPORTS = [
+    "sogrand_last_error", "sogrand_version", "sogrand_params_default",
+    "sogrand_code_create", "sogrand_code_create_ebch", "sogrand_code_info", "sogrand_code_destroy",
+    "sogrand_decode_component", "sogrand_decode_product",
+]
+
+
+class SograndError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libsogrand error {code}: {msg}")
+        self.code = code
+
+
+class sogrand_params_t(ctypes.Structure):
+    _fields_ = [
+        ("list_max", ctypes.c_int),
+        ("query_cap", ctypes.c_uint32),
+        ("alpha", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("early_stop", ctypes.c_int),
+        ("precision", ctypes.c_int),
+    ]
+
+
+def library_path() -> str:
+    return _LIBPATH
+
+
+def lib():
+    """The loaded libsogrand (raises SograndError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise SograndError(-3, f"{_LIBPATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(_LIBPATH)
+    P, I, U32, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t
+    L.sogrand_last_error.restype = ctypes.c_char_p
+    L.sogrand_version.restype = I
+    L.sogrand_params_default.argtypes = [P]
+    L.sogrand_code_create.argtypes = [I, I, P, P]
+    L.sogrand_code_create_ebch.argtypes = [I, I, P]
+    L.sogrand_code_info.argtypes = [P, P, P, P, P]
+    L.sogrand_code_destroy.argtypes = [P]
+    L.sogrand_code_destroy.restype = None
+    L.sogrand_decode_component.argtypes = [P, P, SZ] + [P] * 11
+    L.sogrand_decode_product.argtypes = [P, P, SZ] + [P] * 8
+    for name in EXPORTS:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise SograndError(rc, lib().sogrand_last_error().decode())
+
+
+class Code:
+    """A binary linear [n, k] code handle (library-owned, immutable)."""
+
+    def __init__(self, handle, n, k, even):
+        self._h = handle
+        self.n, self.k, self.is_even = n, k, bool(even)
+
+    @classmethod
+    def ebch(cls, n: int, k: int) -> "Code":
+        h = ctypes.c_void_p()
+        _check(lib().sogrand_code_create_ebch(n, k, ctypes.byref(h)))
+        return cls._wrap(h)
+
+    @classmethod
+    def from_hcols(cls, n: int, k: int, hcols) -> "Code":
+        arr = (ctypes.c_uint32 * n)(*[int(x) for x in hcols])
+        h = ctypes.c_void_p()
+        _check(lib().sogrand_code_create(n, k, arr, ctypes.byref(h)))
+        return cls._wrap(h)
+
+    @classmethod
+    def _wrap(cls, h):
+        n, k, ev = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().sogrand_code_info(h, ctypes.byref(n), ctypes.byref(k), ctypes.byref(ev), None))
+        return cls(h, n.value, k.value, ev.value)
+
+    def hcols(self):
+        arr = (ctypes.c_uint32 * self.n)()
+        _check(lib().sogrand_code_info(self._h, None, None, None, arr))
+        return [int(x) for x in arr]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.sogrand_code_destroy(self._h)
+            self._h = None
+
+
+def params(list_max=4, query_cap=1000, alpha=0.5, max_iter=4, early_stop=True, precision=SOGRAND_F64):
+    p = sogrand_params_t()
+    p.list_max, p.query_cap, p.alpha = int(list_max), int(query_cap), float(alpha)
+    p.max_iter, p.early_stop, p.precision = int(max_iter), int(bool(early_stop)), int(precision)
+    return p
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _precision_of(t):
+    import torch
+    if t.dtype == torch.float64:
+        return SOGRAND_F64
+    if t.dtype == torch.float32:
+        return SOGRAND_F32
+    raise TypeError("LLR tensors must be float64 or float32")
+
+
+def sogrand_decode_component(code: Code, llr_in, list_max=4, query_cap=1000, found_z=False,
+                             outputs=None, stream=None):
+    """Component SISO decode of llr_in (W, n) on its device; returns a dict of tensors.
+
+    ``outputs`` may pre-supply any output tensor by name (llr_app, llr_ext, hard,
+    n_queries, n_found, found_q, p_found, p_notfound, found_z); a name mapped to
+    None is not computed.
+    """
+    import torch
+    if not llr_in.is_cuda or not llr_in.is_contiguous() or llr_in.dim() != 2 or llr_in.shape[1] != code.n:
+        raise ValueError("llr_in must be a contiguous CUDA tensor of shape (W, n)")
+    W, n = llr_in.shape
+    dev, dt = llr_in.device, llr_in.dtype
+    L = int(list_max)
+    out = dict(
+        llr_app=torch.empty((W, n), dtype=dt, device=dev),
+        llr_ext=torch.empty((W, n), dtype=dt, device=dev),
+        hard=torch.empty((W, n), dtype=torch.uint8, device=dev),
+        n_queries=torch.empty(W, dtype=torch.int32, device=dev),
+        n_found=torch.empty(W, dtype=torch.uint8, device=dev),
+        found_q=torch.empty((W, L), dtype=torch.int32, device=dev),
+        p_found=torch.empty((W, L), dtype=torch.float64, device=dev),
+        p_notfound=torch.empty(W, dtype=torch.float64, device=dev),
+        found_z=torch.empty((W, L, n), dtype=torch.uint8, device=dev) if found_z else None,
+    )
+    if outputs:
+        out.update(outputs)
+    p = params(list_max=L, query_cap=query_cap, precision=_precision_of(llr_in))
+    _check(lib().sogrand_decode_component(
+        code.handle, ctypes.byref(p), W, _ptr(llr_in), _ptr(out["llr_app"]), _ptr(out["llr_ext"]),
+        _ptr(out["hard"]), _ptr(out["n_queries"]), _ptr(out["n_found"]), _ptr(out["found_q"]),
+        _ptr(out["p_found"]), _ptr(out["p_notfound"]), _ptr(out["found_z"]), _stream(stream)))
+    return out
+
+
+def sogrand_decode_product(code: Code, llr_ch, list_max=4, query_cap=1000, max_iter=4, alpha=0.5,
+                           early_stop=True, want_app=False, outputs=None, stream=None):
+    """Block-turbo decode of frames llr_ch (F, n, n); returns a dict of tensors."""
+    import torch
+    if not llr_ch.is_cuda or not llr_ch.is_contiguous() or llr_ch.dim() != 3 or \
+            llr_ch.shape[1] != code.n or llr_ch.shape[2] != code.n:
+        raise ValueError("llr_ch must be a contiguous CUDA tensor of shape (F, n, n)")
+    F, n = llr_ch.shape[0], code.n
+    dev, dt = llr_ch.device, llr_ch.dtype
+    out = dict(
+        hard=torch.empty((F, n, n), dtype=torch.uint8, device=dev),
+        llr_app=torch.empty((F, n, n), dtype=dt, device=dev) if want_app else None,
+        success=torch.empty(F, dtype=torch.uint8, device=dev),
+        half_iters=torch.empty(F, dtype=torch.int16, device=dev),
+        sum_queries=torch.empty(F, dtype=torch.int64, device=dev),
+        sum_max_queries=torch.empty(F, dtype=torch.int64, device=dev),
+    )
+    if outputs:
+        out.update(outputs)
+    p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
+               early_stop=early_stop, precision=_precision_of(llr_ch))
+    _check(lib().sogrand_decode_product(
+        code.handle, ctypes.byref(p), F, _ptr(llr_ch), _ptr(out["hard"]), _ptr(out["llr_app"]),
+        _ptr(out["success"]), _ptr(out["half_iters"]), _ptr(out["sum_queries"]),
+        _ptr(out["sum_max_queries"]), _stream(stream)))
+    return out

@@ -1,0 +1,83 @@
+// Internal declarations of libsogrand (not installed; the public API is include/sogrand.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sogrand.h"
+
+namespace sg {
+
+// ----------------------------------------------------------------------------
+// errors
+// ----------------------------------------------------------------------------
+int fail(int code, const char *fmt, ...);
+
+#define SG_HIP(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ::sg::fail(SOGRAND_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define SG_TRY(expr)                \
+    do {                            \
+        int rc_ = (expr);           \
+        if (rc_ != SOGRAND_OK) return rc_; \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// query schedule: the ORBGRAND order in rank space, shared by every word of a code
+// ----------------------------------------------------------------------------
+// Pattern t of parity class c is pat[c][t]: up to 16 ranks (1..n) as bytes,
+// ascending, zero padded.  wmax[c][t/64] is the largest Hamming weight among
+// patterns 64*(t/64) .. 64*(t/64)+63.  Even codes have two classes (even and
+// odd weights); other codes one class holding every weight.
+struct Schedule {
+    int device = -1;
+    uint32_t cap = 0;         // patterns requested per class
+    uint32_t len[2] = {0, 0}; // patterns stored per class (< cap only if the class is exhausted)
+    uint4 *pat[2] = {nullptr, nullptr};
+    uint8_t *wmax[2] = {nullptr, nullptr};
+};
+
+// Device-side view of a code and its schedule, passed by value to kernels.
+struct DevCode {
+    const uint32_t *hcol;   // [n] parity-check column of each bit
+    const uint4 *pat[2];
+    const uint8_t *wmax[2];
+    uint32_t len[2];
+    int n;
+    int even;
+    double phi;             // random-codebook hit probability used by Corollary 1
+};
+
+}  // namespace sg
+
+struct sogrand_code {
+    int n = 0, k = 0, r = 0, even = 0;
+    uint32_t hcol[SOGRAND_NMAX] = {};
+    double phi = 0.0;
+    std::mutex mu;
+    std::map<int, uint32_t *> d_hcol;                // per device
+    std::map<int, sg::Schedule *> sched;             // per device: largest cap built so far
+    std::vector<sg::Schedule *> retired;             // superseded schedules, freed at destroy
+};
+
+namespace sg {
+
+// Ensures the device copy of H and a schedule covering query_cap on the current
+// device, then fills *dc.  The first call for a (code, device, larger cap) builds
+// the schedule and waits for it.
+int prepare_code(sogrand_code_t *code, uint32_t query_cap, DevCode *dc);
+
+int check_params(const sogrand_params_t *p);
+
+void free_schedule(Schedule *s);
+
+}  // namespace sg

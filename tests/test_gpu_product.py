@@ -1,0 +1,125 @@
+"""GPU parity of block-turbo product decoding against the oracle (HIP kernels through the C ABI)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2310_10737_amd as sg
+    sg.lib()
+    return sg
+
+
+def gpu_product(sg, code, llr, L, qcap, iters, f32=False, early_stop=True):
+    import torch
+    gcode = sg.Code.from_hcols(code.n, code.k, code.hcols)
+    dt = torch.float32 if f32 else torch.float64
+    x = torch.from_numpy(llr).to(dtype=dt, device="cuda").contiguous()
+    out = sg.sogrand_decode_product(gcode, x, list_max=L, query_cap=qcap, max_iter=iters,
+                                    early_stop=early_stop, want_app=True)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+
+
+def compare_product(g, r, f32=False, label=""):
+    np.testing.assert_array_equal(g["success"], r["success"], err_msg=label)
+    np.testing.assert_array_equal(g["half_iters"].astype(np.int64), r["half_iters"].astype(np.int64), err_msg=label)
+    np.testing.assert_array_equal(g["sum_queries"].astype(np.int64), r["sum_queries"].astype(np.int64), err_msg=label)
+    np.testing.assert_array_equal(g["sum_max_queries"].astype(np.int64), r["sum_max_queries"].astype(np.int64),
+                                  err_msg=label)
+    np.testing.assert_array_equal(g["hard"], r["hard"], err_msg=label)
+    d = np.abs(g["llr_app"].astype(np.float64) - r["llr_app"])
+    scale = np.maximum(1.0, np.abs(r["llr_app"]))
+    rel = d / scale
+    # same trajectory: final L_APP agree to the binary64 (or binary32 storage) rounding of the last pass,
+    # except where the not-found mass is ill-conditioned
+    lim = 1e-4 if f32 else 1e-9
+    frac = float(np.mean(rel > lim))
+    assert frac < 1e-3, f"{label}: {frac:.2e} of L_APP beyond {lim}, worst {rel.max():.3e}"
+    return float(rel.max())
+
+
+CASES = [
+    ((16, 11), 2.0, 40, 4, 1000, 4),
+    ((32, 26), 3.0, 100, 4, 1000, 4),     # the small plain configuration: 100 frames, seed 0
+    ((32, 26), 2.5, 60, 4, 1000, 4),
+    ((64, 57), 2.5, 24, 4, 10000, 6),
+    ((64, 57), 3.0, 24, 4, 10000, 6),
+    ((128, 120), 3.0, 6, 4, 10000, 6),
+    ((16, 7), 1.0, 30, 4, 1000, 4),
+]
+
+
+@pytest.mark.parametrize("nk,ebn0,frames,L,qcap,iters", CASES)
+@pytest.mark.parametrize("f32", [False, True])
+def test_product_parity(sg, nk, ebn0, frames, L, qcap, iters, f32):
+    code = synth.ebch(*nk)
+    seed = 0 if nk == (32, 26) and ebn0 == 3.0 else 40 + nk[0]
+    llr, cw, _ = synth.product_frames(code, ebn0, seed, np.arange(frames))
+    if f32:
+        llr = llr.astype(np.float32).astype(np.float64)
+    label = f"{code.name}^2 @{ebn0}dB f32={f32}"
+    print(f"[gpu] product {label} frames={frames}", flush=True)
+    g = gpu_product(sg, code, llr, L, qcap, iters, f32=f32)
+    r = oracle.decode_product(code, llr, L, qcap, iters, store_f32=f32, want_app=True, nthreads=8)
+    worst = compare_product(g, r, f32, label)
+    print(f"[gpu]   ok; BLER {np.mean(np.any(g['hard'] != cw, axis=(1, 2))):.3f}, worst rel dL {worst:.2e}",
+          flush=True)
+
+
+def test_product_without_early_stop(sg):
+    code = synth.ebch(32, 26)
+    llr, _, _ = synth.product_frames(code, 3.0, 9, np.arange(20))
+    g = gpu_product(sg, code, llr, 4, 1000, 3, early_stop=False)
+    r = oracle.decode_product(code, llr, 4, 1000, 3, early_stop=False, want_app=True)
+    compare_product(g, r, label="no early stop")
+    assert np.all(g["half_iters"] == 6)
+
+
+def test_product_ragged_frame_counts(sg):
+    code = synth.ebch(64, 57)
+    for F in (1, 3, 5):
+        llr, _, _ = synth.product_frames(code, 3.0, 77 + F, np.arange(F))
+        g = gpu_product(sg, code, llr, 4, 2000, 3)
+        r = oracle.decode_product(code, llr, 4, 2000, 3, want_app=True)
+        compare_product(g, r, label=f"F={F}")
+
+
+def test_full_size_product_workload_sampled(sg):
+    """The [64,57]^2 workload at full size (1e4 frames per Eb/N0, L = 4, cap 1e4, 6 iterations),
+    decoded in the launch configuration the benchmark times; sampled frames vs the oracle."""
+    import torch
+    code = synth.ebch(64, 57)
+    gcode = sg.Code.ebch(64, 57)
+    rng = np.random.default_rng(1)
+    for snr, seed in ((2.5, 1), (3.0, 2), (3.5, 3)):
+        for f32 in (False, True):
+            print(f"[gpu] full product {snr} dB f32={f32}", flush=True)
+            llr, cw, _ = synth.product_frames(code, snr, seed, np.arange(10000))
+            dt = torch.float32 if f32 else torch.float64
+            x = torch.from_numpy(llr).to(dtype=dt, device="cuda")
+            out = sg.sogrand_decode_product(gcode, x, list_max=4, query_cap=10000, max_iter=6, want_app=False)
+            torch.cuda.synchronize()
+            sample = np.sort(rng.choice(10000, size=12, replace=False))
+            g = {k: v.cpu().numpy()[sample] for k, v in out.items() if v is not None}
+            ls = llr[sample].astype(np.float32).astype(np.float64) if f32 else llr[sample]
+            r = oracle.decode_product(code, ls, 4, 10000, 6, store_f32=f32, nthreads=8)
+            for key in ("success", "half_iters", "sum_queries", "sum_max_queries", "hard"):
+                np.testing.assert_array_equal(g[key].astype(np.int64), r[key].astype(np.int64), err_msg=key)
+            hard = out["hard"].cpu().numpy()
+            bler = np.mean(np.any(hard != cw, axis=(1, 2)))
+            print(f"[gpu]   BLER {bler:.4g}; mean half-iters {out['half_iters'].double().mean().item():.2f}",
+                  flush=True)
+            del x, out
