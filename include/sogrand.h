@@ -152,6 +152,30 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
                            uint8_t *success, uint16_t *half_iters, uint64_t *sum_queries,
                            uint64_t *sum_max_queries, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Measurement                                                              */
+/* ------------------------------------------------------------------------ */
+/* Per-kernel-family totals collected between sogrand_profile_begin and
+   sogrand_profile_end (process-wide, all devices and streams). */
+typedef struct {
+    char kernel[48];     /* family: "component", "product_pass", "product_check", ... */
+    uint64_t launches;   /* kernel launches recorded                                  */
+    double total_ms;     /* sum of HIP-event times around those launches              */
+    uint64_t words;      /* component words decoded (count_work only)                 */
+    uint64_t queries;    /* patterns tested (count_work only)                         */
+    uint64_t ranks;      /* sum of the Hamming weights of the tested patterns (count_work only) */
+} sogrand_kernel_stat_t;
+
+/* Starts recording: every decode kernel launched afterwards is bracketed by a
+   pair of HIP events on its stream.  With count_work != 0 the kernels also add
+   the words, queries and pattern weights they process to device counters
+   (this adds atomics; use a separate run for timing).  Errors: EDEVICE. */
+int sogrand_profile_begin(int count_work);
+
+/* Stops recording, waits for the recorded events and returns up to max_stats
+   families in stats (*n_stats set).  Errors: EINVAL, EDEVICE. */
+int sogrand_profile_end(sogrand_kernel_stat_t *stats, int max_stats, int *n_stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ import ctypes
 import os
 
 __all__ = [
-    "SograndError", "Code", "params", "lib", "library_path",
+    "SograndError", "Code", "params", "lib", "library_path", "profile_begin", "profile_end",
     "sogrand_decode_component", "sogrand_decode_product",
     "SOGRAND_F64", "SOGRAND_F32",
 ]
@@ -26,6 +26,7 @@ EXPORTS = [
     "sogrand_last_error", "sogrand_version", "sogrand_params_default",
     "sogrand_code_create", "sogrand_code_create_ebch", "sogrand_code_info", "sogrand_code_destroy",
     "sogrand_decode_component", "sogrand_decode_product",
+    "sogrand_profile_begin", "sogrand_profile_end",
 ]
 
 
@@ -33,6 +34,17 @@ class SograndError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libsogrand error {code}: {msg}")
         self.code = code
+
+
+class sogrand_kernel_stat_t(ctypes.Structure):
+    _fields_ = [
+        ("kernel", ctypes.c_char * 48),
+        ("launches", ctypes.c_uint64),
+        ("total_ms", ctypes.c_double),
+        ("words", ctypes.c_uint64),
+        ("queries", ctypes.c_uint64),
+        ("ranks", ctypes.c_uint64),
+    ]
 
 
 class sogrand_params_t(ctypes.Structure):
@@ -69,6 +81,8 @@ def lib():
     L.sogrand_code_destroy.restype = None
     L.sogrand_decode_component.argtypes = [P, P, SZ] + [P] * 11
     L.sogrand_decode_product.argtypes = [P, P, SZ] + [P] * 8
+    L.sogrand_profile_begin.argtypes = [I]
+    L.sogrand_profile_end.argtypes = [P, I, P]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -119,6 +133,20 @@ class Code:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.sogrand_code_destroy(self._h)
             self._h = None
+
+
+def profile_begin(count_work: bool = False):
+    """Bracket every decode kernel launched from now on with HIP events (and count work)."""
+    _check(lib().sogrand_profile_begin(int(bool(count_work))))
+
+
+def profile_end():
+    """Per-kernel-family totals since profile_begin: {name: dict(launches, total_ms, words, queries, ranks)}."""
+    arr = (sogrand_kernel_stat_t * 16)()
+    n = ctypes.c_int()
+    _check(lib().sogrand_profile_end(arr, 16, ctypes.byref(n)))
+    return {arr[i].kernel.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, words=arr[i].words,
+                                         queries=arr[i].queries, ranks=arr[i].ranks) for i in range(n.value)}
 
 
 def params(list_max=4, query_cap=1000, alpha=0.5, max_iter=4, early_stop=True, precision=SOGRAND_F64):

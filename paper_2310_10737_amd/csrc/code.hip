@@ -250,7 +250,7 @@ static int build_schedule(const sogrand_code_t *c, int dev, uint32_t cap, Schedu
     s->cap = cap;
     const int ncls = c->even ? 2 : 1;
     std::vector<ClassDesc> descs[2];
-    std::vector<uint8_t> wmax[2];
+    std::vector<uint32_t> wmax[2];
     for (int cl = 0; cl < ncls; cl++) {
         uint64_t off = 0;
         // patterns with more than 16 parts cannot be stored; in this class the first
@@ -288,11 +288,11 @@ static int build_schedule(const sogrand_code_t *c, int dev, uint32_t cap, Schedu
     for (int cl = 0; cl < ncls && rc == SOGRAND_OK; cl++) {
         size_t npat = s->len[cl] ? s->len[cl] : 1;
         if (hipMalloc(&s->pat[cl], npat * sizeof(uint4)) != hipSuccess ||
-            hipMalloc(&s->wmax[cl], wmax[cl].size()) != hipSuccess) {
+            hipMalloc(&s->wmax[cl], wmax[cl].size() * sizeof(uint32_t)) != hipSuccess) {
             rc = fail(SOGRAND_ENOMEM, "device allocation of the query schedule failed");
             break;
         }
-        if (hipMemcpyAsync(s->wmax[cl], wmax[cl].data(), wmax[cl].size(), hipMemcpyHostToDevice, st) != hipSuccess) {
+        if (hipMemcpyAsync(s->wmax[cl], wmax[cl].data(), wmax[cl].size() * sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess) {
             rc = fail(SOGRAND_EDEVICE, "copy of the schedule weights failed");
             break;
         }

@@ -26,13 +26,14 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 
 struct WaveLds {
-    double rho_r[SOGRAND_NMAX + 1];      // by rank (1..n); [0] = 1 for zero padding
-    double rho_b[SOGRAND_NMAX];          // by bit index
+    double rho_r[SOGRAND_NMAX + 1];      // rho by rank (1..n); [0] = 1 for zero padding
+    uint64_t key_b[SOGRAND_NMAX + 2];    // |lambda| bit patterns by bit index, padded with ~0
     double tau_l[SOGRAND_LIST_MAX];      // prod rho of each found pattern
-    uint64_t z_l[SOGRAND_LIST_MAX][2];   // found patterns as bit masks over bit indices
+    uint4 pat_l[SOGRAND_LIST_MAX];       // found patterns (ranks)
     uint32_t hs_r[SOGRAND_NMAX + 1];     // H column by rank; [0] = 0
     uint32_t q_l[SOGRAND_LIST_MAX];      // query number of each found codeword
-    uint8_t rank_b[SOGRAND_NMAX];        // rank of each bit index
+    uint8_t pi_r[SOGRAND_NMAX + 1];      // bit index of each rank
+    uint8_t zf[SOGRAND_NMAX];            // membership flags of one found pattern, by bit index
 };
 
 template <int NS>
@@ -45,7 +46,22 @@ struct WordStats {
     int found;       // codewords in the list
     double pnf;      // P(transmitted codeword not in the list)
     double D;        // normaliser: sum of found prod rho + not-found mass * phi (relative to p(0|r))
+    uint64_t ranks;  // sum of the Hamming weights of the tested patterns (only when counting)
 };
+
+// number of nonzero bytes of a packed pattern (its Hamming weight)
+__device__ __forceinline__ uint32_t pattern_weight(uint4 e) {
+    uint32_t w = 0;
+    const uint32_t d[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        uint32_t m = d[j] | (d[j] >> 4);
+        m |= m >> 2;
+        m |= m >> 1;
+        w += __popc(m & 0x01010101u);
+    }
+    return w;
+}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -53,15 +69,65 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// v from lane (lane ^ M), entirely in the VALU: DPP quad permutations for M = 1, 2,
+// row shifts with complementary bank masks for M = 4, 8, and the gfx950 permlane
+// swaps for M = 16, 32.
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+    if constexpr (M == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (M == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (M == 4) {
+        const int t = __builtin_amdgcn_update_dpp((int)v, (int)v, 0x104, 0xF, 0x5, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x114, 0xF, 0xA, false);
+    } else if constexpr (M == 8) {
+        const int t = __builtin_amdgcn_update_dpp((int)v, (int)v, 0x108, 0xF, 0x3, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x118, 0xF, 0xC, false);
+    } else if constexpr (M == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
+    } else {
+        static_assert(M == 32, "xor distance");
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? r[0] : r[1];
+    }
+}
+
+template <int M>
+__device__ __forceinline__ double xor_lane_f64(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = xor_lane<M>((uint32_t)u), hi = xor_lane<M>((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ uint32_t wave_xor(uint32_t v) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) v ^= __shfl_xor(v, d);
+    v ^= xor_lane<1>(v);
+    v ^= xor_lane<2>(v);
+    v ^= xor_lane<4>(v);
+    v ^= xor_lane<8>(v);
+    v ^= xor_lane<16>(v);
+    v ^= xor_lane<32>(v);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_add(uint32_t v) {
+    v += xor_lane<1>(v);
+    v += xor_lane<2>(v);
+    v += xor_lane<4>(v);
+    v += xor_lane<8>(v);
+    v += xor_lane<16>(v);
+    v += xor_lane<32>(v);
     return v;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d);
+    v += xor_lane_f64<1>(v);
+    v += xor_lane_f64<2>(v);
+    v += xor_lane_f64<4>(v);
+    v += xor_lane_f64<8>(v);
+    v += xor_lane_f64<16>(v);
+    v += xor_lane_f64<32>(v);
     return v;
 }
 
@@ -79,58 +145,38 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__device__ __forceinline__ bool key_less(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib) {
-    return ka < kb || (ka == kb && ia < ib);
+// parity-class masses of two disjoint bit sets combined (see decode_word step 3)
+template <int M>
+__device__ __forceinline__ void eo_combine(double &E, double &O) {
+    const double E2 = xor_lane_f64<M>(E), O2 = xor_lane_f64<M>(O);
+    const double nE = (E + E2) + (E * E2 + O * O2);
+    const double nO = (O + O2) + (E * O2 + O * E2);
+    E = nE;
+    O = nO;
 }
 
-// Bitonic sort of NS (key, index) pairs; element e = lane + 64*slot.  Keys are the
-// bit patterns of |lambda| (monotone for non-negative doubles); ties fall back to
-// the bit index.  Afterwards element e holds rank e+1.
-template <int NS>
-__device__ __forceinline__ void bitonic_sort(uint64_t (&key)[Lanes<NS>::NB], uint32_t (&idx)[Lanes<NS>::NB], int lane) {
-    constexpr int NB = Lanes<NS>::NB;
-#pragma unroll
-    for (int k = 2; k <= NS; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= kWave) {
-                // NS = 128, j = 64: the partner is the same lane's other slot; k = 128 sorts up
-                if constexpr (NB > 1) {
-                    if (key_less(key[NB - 1], idx[NB - 1], key[0], idx[0])) {
-                        uint64_t tk = key[0]; key[0] = key[NB - 1]; key[NB - 1] = tk;
-                        uint32_t ti = idx[0]; idx[0] = idx[NB - 1]; idx[NB - 1] = ti;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int b = 0; b < NB; b++) {
-                    const int e = lane + kWave * b;
-                    const uint64_t ok = __shfl_xor(key[b], j);
-                    const uint32_t oi = __shfl_xor(idx[b], j);
-                    const bool lower = (e & j) == 0;
-                    const bool up = (e & k) == 0;
-                    const bool other_less = key_less(ok, oi, key[b], idx[b]);
-                    // the lower element of an ascending pair keeps the minimum
-                    const bool take = (lower == up) ? other_less : !other_less;
-                    if (take) { key[b] = ok; idx[b] = oi; }
-                }
-            }
-        }
-    }
-}
+// One rank of a pattern: r is byte SH/8 of dword d.
+#define SG_RANK(d, SH)                                   \
+    do {                                                 \
+        const uint32_t r_ = ((d) >> (SH)) & 0xffu;       \
+        s ^= S.hs_r[r_];                                 \
+        tau *= S.rho_r[r_];                              \
+    } while (0)
 
 // Decodes one word held as lam[slot] at bit index lane + 64*slot (< n).
 // Writes the APP LLRs of the lane's bits into lapp; the list is left in S.
 template <int NS>
 __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32_t qcap,
                                                  const double (&lam)[Lanes<NS>::NB], WaveLds &S,
-                                                 double (&lapp)[Lanes<NS>::NB], int lane) {
+                                                 double (&lapp)[Lanes<NS>::NB], int lane, bool count) {
     constexpr int NB = Lanes<NS>::NB;
     const int n = c.n;
 
-    // 1. hard decision, syndrome and parity
+    // 1. hard decision, its syndrome and parity; keys |lambda| and rho = e^-|lambda| by bit
     bool valid[NB];
     int ybit[NB];
+    double rho[NB];
+    uint64_t key[NB];
     uint32_t spart = 0;
     int ycount = 0;
 #pragma unroll
@@ -140,43 +186,58 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
         ybit[b] = valid[b] && lam[b] < 0.0;
         if (ybit[b]) spart ^= c.hcol[i];
         ycount += __popcll(__ballot(ybit[b]));
+        const double a = fabs(lam[b]);
+        key[b] = valid[b] ? (uint64_t)__double_as_longlong(a) : ~0ull;
+        rho[b] = valid[b] ? exp(-a) : 0.0;
+        if (i < SOGRAND_NMAX + 2) S.key_b[i] = key[b];
     }
+    if (NB == 1 && lane < 2) S.key_b[kWave + lane] = ~0ull;
     const uint32_t s0 = wave_xor(spart);
     const int par = ycount & 1;
+    wave_sync();
 
-    // 2. rho by bit index, then the reliability sort
-    double rho[NB];
-    uint64_t key[NB];
-    uint32_t idx[NB];
+    // 2. reliability rank of each bit: the number of smaller keys (bit patterns of
+    //    non-negative doubles order like the values), ties broken by the bit index
+    uint32_t cnt[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) cnt[b] = 0;
+    for (int j = 0; j < n; j += 2) {
+        const uint64_t k0 = S.key_b[j], k1 = S.key_b[j + 1];
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            cnt[b] += (k0 < key[b]) ? 1u : 0u;
+            cnt[b] += (k1 < key[b]) ? 1u : 0u;
+        }
+    }
+    {
+        uint32_t part = 0;
+#pragma unroll
+        for (int b = 0; b < NB; b++) part += valid[b] ? cnt[b] : 0u;
+        const uint32_t tot = __builtin_amdgcn_readfirstlane(wave_add(part));
+        if (tot != (uint32_t)(n * (n - 1) / 2)) {
+            // equal keys share a count: order each group of equal keys by bit index
+            for (int j = 0; j < n; j++) {
+                const uint64_t kj = S.key_b[j];
+#pragma unroll
+                for (int b = 0; b < NB; b++) cnt[b] += (kj == key[b] && j < lane + kWave * b) ? 1u : 0u;
+            }
+        }
+    }
+    int myrank[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
-        const double a = fabs(lam[b]);
-        rho[b] = valid[b] ? exp(-a) : 0.0;
-        if (valid[b]) S.rho_b[i] = rho[b];
-        key[b] = valid[b] ? (uint64_t)__double_as_longlong(a) : ~0ull;
-        idx[b] = (uint32_t)i;
-    }
-    bitonic_sort<NS>(key, idx, lane);
-    wave_sync();
-#pragma unroll
-    for (int b = 0; b < NB; b++) {
-        const int e = lane + kWave * b;
-        if (e < n) {
-            const int r = e + 1;
-            S.hs_r[r] = c.hcol[idx[b]];
-            S.rho_r[r] = S.rho_b[idx[b]];
-            S.rank_b[idx[b]] = (uint8_t)r;
+        myrank[b] = valid[b] ? (int)cnt[b] + 1 : 0;
+        if (valid[b]) {
+            S.hs_r[myrank[b]] = c.hcol[i];
+            S.rho_r[myrank[b]] = rho[b];
+            S.pi_r[myrank[b]] = (uint8_t)i;
         }
     }
     if (lane == 0) {
         S.hs_r[0] = 0u;
         S.rho_r[0] = 1.0;
     }
-    wave_sync();
-    int myrank[NB];
-#pragma unroll
-    for (int b = 0; b < NB; b++) myrank[b] = valid[b] ? S.rank_b[lane + kWave * b] : 0;
 
     // 3. parity-class masses: adding bit i maps (E, O) to (E + O rho_i, O + (1 + E) rho_i);
     //    two disjoint bit sets combine as E = E1 + E2 + E1 E2 + O1 O2, O = O1 + O2 + E1 O2 + O1 E2
@@ -190,40 +251,62 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
             O = o2;
         }
     }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const double E2 = __shfl_xor(E, d), O2 = __shfl_xor(O, d);
-        const double nE = (E + E2) + (E * E2 + O * O2);
-        const double nO = (O + O2) + (E * O2 + O * E2);
-        E = nE;
-        O = nO;
-    }
+    eo_combine<1>(E, O);
+    eo_combine<2>(E, O);
+    eo_combine<4>(E, O);
+    eo_combine<8>(E, O);
+    eo_combine<16>(E, O);
+    eo_combine<32>(E, O);
     E = bcast0(E);
     O = bcast0(O);
+    wave_sync();
 
-    // 4. query loop over the schedule of the word's parity class
+    // 4. query loop over the schedule of the word's parity class; the next chunk's
+    //    patterns are fetched while the current one is tested
     const int cls = c.even ? par : 0;
     const uint4 *__restrict__ tab = c.pat[cls];
-    const uint8_t *__restrict__ wm = c.wmax[cls];
+    const uint32_t *__restrict__ wm = c.wmax[cls];
     const uint32_t limit = qcap < c.len[cls] ? qcap : c.len[cls];
     int found = 0;
     uint32_t Q = 0;
     double s_lane = 0.0;   // this lane's share of the tested nonzero-pattern mass (relative to p(0|r))
+    uint32_t w_lane = 0;   // this lane's share of the tested pattern weights (counting only)
+    uint4 e_next = make_uint4(0u, 0u, 0u, 0u);
+    if ((uint32_t)lane < limit) e_next = tab[lane];
+    uint32_t wm_next = wm[0];
     for (uint32_t base = 0; base < limit; base += kWave) {
-        const uint32_t g = base + (uint32_t)lane;
-        const bool act = g < limit;
-        uint4 e = make_uint4(0u, 0u, 0u, 0u);
-        if (act) e = tab[g];
-        const int wmx = wm[base >> 6];
-        const uint32_t wd[4] = {e.x, e.y, e.z, e.w};
+        const uint4 e = e_next;
+        const uint32_t wmx = wm_next;
+        const uint32_t nb = base + kWave;
+        if (nb < limit) {
+            e_next = make_uint4(0u, 0u, 0u, 0u);
+            if (nb + (uint32_t)lane < limit) e_next = tab[nb + lane];
+            wm_next = wm[nb >> 6];
+        }
+        const bool act = base + (uint32_t)lane < limit;
         uint32_t s = s0;
         double tau = 1.0;
-#pragma unroll
-        for (int j = 0; j < 16; j++) {
-            if (j >= wmx) break;
-            const uint32_t r = (wd[j >> 2] >> (8 * (j & 3))) & 0xffu;
-            s ^= S.hs_r[r];
-            tau *= S.rho_r[r];
+        if (wmx > 0) SG_RANK(e.x, 0);
+        if (wmx > 1) SG_RANK(e.x, 8);
+        if (wmx > 2) SG_RANK(e.x, 16);
+        if (wmx > 3) SG_RANK(e.x, 24);
+        if (wmx > 4) {
+            SG_RANK(e.y, 0);
+            if (wmx > 5) SG_RANK(e.y, 8);
+            if (wmx > 6) SG_RANK(e.y, 16);
+            if (wmx > 7) SG_RANK(e.y, 24);
+            if (wmx > 8) {
+                SG_RANK(e.z, 0);
+                if (wmx > 9) SG_RANK(e.z, 8);
+                if (wmx > 10) SG_RANK(e.z, 16);
+                if (wmx > 11) SG_RANK(e.z, 24);
+                if (wmx > 12) {
+                    SG_RANK(e.w, 0);
+                    if (wmx > 13) SG_RANK(e.w, 8);
+                    if (wmx > 14) SG_RANK(e.w, 16);
+                    if (wmx > 15) SG_RANK(e.w, 24);
+                }
+            }
         }
         uint64_t m = __ballot(act && s == 0u);
         int cut = kWave - 1;
@@ -235,41 +318,28 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
             const uint32_t hz = __builtin_amdgcn_readlane(e.z, h);
             const uint32_t hw = __builtin_amdgcn_readlane(e.w, h);
             const double th = readlane_f64(tau, h);
-            const uint32_t hd[4] = {hx, hy, hz, hw};
-            uint64_t zm[NB];
-#pragma unroll
-            for (int b = 0; b < NB; b++) {
-                bool in = false;
-#pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    if (j >= wmx) break;
-                    const int r = (int)((hd[j >> 2] >> (8 * (j & 3))) & 0xffu);
-                    in |= (r != 0) && (r == myrank[b]);
-                }
-                zm[b] = __ballot(in);
-            }
             if (lane == 0) {
                 S.tau_l[found] = th;
                 S.q_l[found] = base + (uint32_t)h + 1u;
-                S.z_l[found][0] = zm[0];
-                S.z_l[found][1] = NB > 1 ? zm[NB - 1] : 0ull;
+                S.pat_l[found] = make_uint4(hx, hy, hz, hw);
             }
             found++;
             if (found == L) cut = h;
         }
         const bool nonzero = (e.x & 0xffu) != 0u;
         if (act && nonzero && lane <= cut) s_lane += tau;
+        if (count && act && lane <= cut) w_lane += pattern_weight(e);
         if (found >= L) {
             Q = base + (uint32_t)cut + 1u;
             break;
         }
-        Q = limit < base + kWave ? limit : base + kWave;
+        Q = limit < nb ? limit : nb;
     }
-    wave_sync();
     const double Snz = bcast0(wave_sum(s_lane));
 
     // 5. Corollary 1 inside the parity class: not-found mass M = (class mass) - (tested mass),
     //    both relative to p(0|r); the zero pattern (first in its class) cancels exactly.
+    wave_sync();
     const double T = c.even ? (par ? O : E) : (E + O);
     double M = T - Snz;
     if (!(M > 0.0)) M = 0.0;
@@ -280,27 +350,43 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
     if (degenerate) pnf = 1.0;   // every probability underflowed: keep the soft input
 
     // eq. (LLRi): list codewords weighted by their APPs, plus the soft input weighted by P_nf
+    double N0[NB], N1[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        double N0 = 0.0, N1 = 0.0;
-        if (!degenerate) {
-            for (int l = 0; l < found; l++) {
-                const double P = S.tau_l[l] / D;
-                const int z = (int)((S.z_l[l][b] >> lane) & 1ull);
-                if (ybit[b] ^ z) N1 += P;
-                else N0 += P;
-            }
-        }
         const double qs = 1.0 / (1.0 + rho[b]);   // p(bit = y | soft input)
         const double qf = rho[b] * qs;            // p(bit != y | soft input)
-        if (ybit[b]) {
-            N1 += pnf * qs;
-            N0 += pnf * qf;
-        } else {
-            N0 += pnf * qs;
-            N1 += pnf * qf;
+        N0[b] = pnf * (ybit[b] ? qf : qs);
+        N1[b] = pnf * (ybit[b] ? qs : qf);
+    }
+    if (!degenerate) {
+        const double invD = 1.0 / D;
+        for (int l = 0; l < found; l++) {
+            // membership flags of pattern l: clear, then mark the bits of its ranks
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+                if (lane + kWave * b < SOGRAND_NMAX) S.zf[lane + kWave * b] = 0;
+            wave_sync();
+            const uint4 pl = S.pat_l[l];
+            if (lane < 16) {
+                const uint32_t d = lane < 4 ? pl.x : (lane < 8 ? pl.y : (lane < 12 ? pl.z : pl.w));
+                const uint32_t r = (d >> (8 * (lane & 3))) & 0xffu;
+                if (r) S.zf[S.pi_r[r]] = 1;
+            }
+            wave_sync();
+            const double P = S.tau_l[l] * invD;
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                const int i = lane + kWave * b;
+                const int z = i < SOGRAND_NMAX ? S.zf[i] : 0;
+                if (ybit[b] ^ z) N1[b] += P;
+                else N0[b] += P;
+            }
+            wave_sync();
         }
-        double la = log(N0) - log(N1);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        double la = log(N0[b] / N1[b]);
         if (!(la <= 1000.0)) la = 1000.0;
         if (!(la >= -1000.0)) la = -1000.0;
         lapp[b] = la;
@@ -310,6 +396,8 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
     st.found = found;
     st.pnf = pnf;
     st.D = D;
+    st.ranks = 0;
+    if (count) st.ranks = wave_add(w_lane);
     return st;
 }
 
@@ -331,7 +419,14 @@ struct ComponentArgs {
     double *p_found;
     double *p_notfound;
     uint8_t *found_z;
+    ProfCounters *prof;
 };
+
+__device__ __forceinline__ void prof_add(ProfCounters *p, const WordStats &st) {
+    atomicAdd(&p->words, 1ull);
+    atomicAdd(&p->queries, (unsigned long long)st.Q);
+    atomicAdd(&p->ranks, (unsigned long long)st.ranks);
+}
 
 template <typename T, int NS>
 __global__ __launch_bounds__(kBlock) void k_component(ComponentArgs a) {
@@ -351,7 +446,8 @@ __global__ __launch_bounds__(kBlock) void k_component(ComponentArgs a) {
         lam[b] = i < n ? (double)in[i] : 0.0;
     }
     double lapp[NB];
-    const WordStats st = decode_word<NS>(a.code, a.L, a.qcap, lam, S, lapp, lane);
+    const WordStats st = decode_word<NS>(a.code, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    if (a.prof && lane == 0) prof_add(a.prof, st);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
@@ -373,13 +469,27 @@ __global__ __launch_bounds__(kBlock) void k_component(ComponentArgs a) {
     }
     if (a.found_z) {
         for (int l = 0; l < a.L; l++) {
+            if (l < st.found) {
+#pragma unroll
+                for (int b = 0; b < NB; b++)
+                    if (lane + kWave * b < SOGRAND_NMAX) S.zf[lane + kWave * b] = 0;
+                wave_sync();
+                const uint4 pl = S.pat_l[l];
+                if (lane < 16) {
+                    const uint32_t d = lane < 4 ? pl.x : (lane < 8 ? pl.y : (lane < 12 ? pl.z : pl.w));
+                    const uint32_t r = (d >> (8 * (lane & 3))) & 0xffu;
+                    if (r) S.zf[S.pi_r[r]] = 1;
+                }
+                wave_sync();
+            }
 #pragma unroll
             for (int b = 0; b < NB; b++) {
                 const int i = lane + kWave * b;
                 if (i >= n) continue;
-                const uint8_t z = l < st.found ? (uint8_t)((S.z_l[l][b] >> lane) & 1ull) : 0;
+                const uint8_t z = l < st.found ? S.zf[i] : 0;
                 a.found_z[(wid * a.L + l) * n + i] = z;
             }
+            wave_sync();
         }
     }
 }
@@ -405,6 +515,7 @@ struct ProductArgs {
     uint8_t *success;       // [F]
     uint16_t *half_iters;   // [F]
     int early_stop;
+    ProfCounters *prof;
 };
 
 template <typename T>
@@ -449,7 +560,8 @@ __global__ __launch_bounds__(kBlock) void k_product_pass(ProductArgs a) {
         lam[b] = i < n ? (double)ch[pos[b]] + (double)la[pos[b]] : 0.0;
     }
     double lapp[NB];
-    const WordStats st = decode_word<NS>(a.code, a.L, a.qcap, lam, S, lapp, lane);
+    const WordStats st = decode_word<NS>(a.code, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    if (a.prof && lane == 0) prof_add(a.prof, st);
     uint64_t hm[2] = {0ull, 0ull};
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -560,12 +672,15 @@ int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t 
     a.p_found = p_found;
     a.p_notfound = p_notfound;
     a.found_z = found_z;
+    a.prof = prof_counters(PK_COMPONENT);
     const size_t blocks = (nwords + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 0x7fffffffull) return fail(SOGRAND_EINVAL, "nwords too large for one launch");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int ns = sort_width(code->n);
+    const int tok = prof_start(PK_COMPONENT, st);
     if (params->precision == SOGRAND_F64) launch_component<double>(a, ns, dim3((unsigned)blocks), st);
     else launch_component<float>(a, ns, dim3((unsigned)blocks), st);
+    prof_stop(tok, st);
     SG_HIP(hipGetLastError());
     return SOGRAND_OK;
 }
@@ -616,17 +731,21 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
     a.success = success;
     a.half_iters = half_iters ? half_iters : reinterpret_cast<uint16_t *>(ws + off_hi);
     a.early_stop = params->early_stop ? 1 : 0;
+    a.prof = prof_counters(PK_PASS);
     const int ns = sort_width(n);
     const bool f64 = params->precision == SOGRAND_F64;
     int rc = SOGRAND_OK;
     {
         const size_t ib = (nframes * n * n + kBlock - 1) / kBlock;
         const unsigned ig = (unsigned)(ib < 65536 ? ib : 65536);
+        int tok = prof_start(PK_INIT, st);
         if (f64) hipLaunchKernelGGL(k_product_init<double>, dim3(ig), dim3(kBlock), 0, st, a);
         else hipLaunchKernelGGL(k_product_init<float>, dim3(ig), dim3(kBlock), 0, st, a);
+        prof_stop(tok, st);
         const unsigned cg = (unsigned)((nframes + kWavesPerBlock - 1) / kWavesPerBlock);
         for (int h = 1; h <= 2 * params->max_iter; h++) {
             const bool rows = (h & 1) != 0;
+            tok = prof_start(PK_PASS, st);
             if (f64) {
                 if (rows) launch_pass<double, true>(a, ns, dim3((unsigned)blocks), st);
                 else launch_pass<double, false>(a, ns, dim3((unsigned)blocks), st);
@@ -634,7 +753,10 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
                 if (rows) launch_pass<float, true>(a, ns, dim3((unsigned)blocks), st);
                 else launch_pass<float, false>(a, ns, dim3((unsigned)blocks), st);
             }
+            prof_stop(tok, st);
+            tok = prof_start(PK_CHECK, st);
             hipLaunchKernelGGL(k_product_check, dim3(cg), dim3(kBlock), 0, st, a, h, h == 2 * params->max_iter ? 1 : 0);
+            prof_stop(tok, st);
         }
         if (hipGetLastError() != hipSuccess) rc = fail(SOGRAND_EDEVICE, "product kernel launch failed");
     }

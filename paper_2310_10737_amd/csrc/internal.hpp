@@ -43,14 +43,14 @@ struct Schedule {
     uint32_t cap = 0;         // patterns requested per class
     uint32_t len[2] = {0, 0}; // patterns stored per class (< cap only if the class is exhausted)
     uint4 *pat[2] = {nullptr, nullptr};
-    uint8_t *wmax[2] = {nullptr, nullptr};
+    uint32_t *wmax[2] = {nullptr, nullptr};
 };
 
 // Device-side view of a code and its schedule, passed by value to kernels.
 struct DevCode {
     const uint32_t *hcol;   // [n] parity-check column of each bit
     const uint4 *pat[2];
-    const uint8_t *wmax[2];
+    const uint32_t *wmax[2];
     uint32_t len[2];
     int n;
     int even;
@@ -77,6 +77,21 @@ namespace sg {
 int prepare_code(sogrand_code_t *code, uint32_t query_cap, DevCode *dc);
 
 int check_params(const sogrand_params_t *p);
+
+// ----------------------------------------------------------------------------
+// measurement hooks
+// ----------------------------------------------------------------------------
+enum ProfKind { PK_COMPONENT = 0, PK_PASS, PK_CHECK, PK_INIT, PK_BATCHED, PK_SERVE, PK_COUNT };
+
+struct ProfCounters {
+    unsigned long long words, queries, ranks, pad;
+};
+
+// Device counters for `kind` while work counting is on, else nullptr.
+ProfCounters *prof_counters(ProfKind kind);
+// Returns an opaque token (or -1 when profiling is off) after recording a start event.
+int prof_start(ProfKind kind, hipStream_t st);
+void prof_stop(int token, hipStream_t st);
 
 void free_schedule(Schedule *s);
 
