@@ -57,6 +57,10 @@ def main() -> int:
     ap.add_argument("--cpu-frames", type=int, default=600, help="oracle sample: frames per Eb/N0")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="plain_f64,plain_f32")
+    ap.add_argument("--no-count", action="store_true",
+                    help="skip the work-counting run (for profiler runs that average kernel durations)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a device copy of this many MiB (HBM byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -111,10 +115,12 @@ def main() -> int:
             step()
         torch.cuda.synchronize()
         # work counted once in a separate run (the counters add atomics); decoding is deterministic
-        sg.profile_begin(count_work=True)
-        step()
-        torch.cuda.synchronize()
-        work = sg.profile_end()
+        work = {}
+        if not args.no_count:
+            sg.profile_begin(count_work=True)
+            step()
+            torch.cuda.synchronize()
+            work = sg.profile_end()
         sg.profile_begin(count_work=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -157,7 +163,7 @@ def main() -> int:
     kp = best["kernels"].get("product_pass", {})
     wk = best["work"].get("product_pass", {})
     roof = None
-    if kp.get("launches"):
+    if kp.get("launches") and wk:
         avg_ms = kp["total_ms"] / kp["launches"]
         launches_per_step = kp["launches"] / args.steps
         ops_step = wk["words"] * ops_per_word(N, L) + 2 * wk["queries"] + 2 * wk["ranks"]
@@ -168,7 +174,15 @@ def main() -> int:
                     kernel="k_product_pass (row and column instantiations)",
                     avg_launch_ms=avg_ms, ops_per_launch=ops_launch,
                     words_per_step=wk["words"], queries_per_step=wk["queries"],
-                    ranks_per_step=wk["ranks"])
+                    ranks_per_step=wk["ranks"], exact_rank_words_per_step=wk.get("exact_rank"))
+
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu and args.cpu_frames > 0:

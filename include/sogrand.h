@@ -164,6 +164,7 @@ typedef struct {
     uint64_t words;      /* component words decoded (count_work only)                 */
     uint64_t queries;    /* patterns tested (count_work only)                         */
     uint64_t ranks;      /* sum of the Hamming weights of the tested patterns (count_work only) */
+    uint64_t exact_rank; /* words whose ranks needed the exact tie-resolving pass (count_work only) */
 } sogrand_kernel_stat_t;
 
 /* Starts recording: every decode kernel launched afterwards is bracketed by a

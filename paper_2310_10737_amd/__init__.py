@@ -19,7 +19,8 @@ __all__ = [
 SOGRAND_F64 = 0
 SOGRAND_F32 = 1
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIBPATH = os.path.join(_HERE, "libsogrand.so")
+# SOGRAND_LIB selects another build of the library (A/B measurements of two builds)
+_LIBPATH = os.environ.get("SOGRAND_LIB") or os.path.join(_HERE, "libsogrand.so")
 _lib = None
 
 EXPORTS = [
@@ -44,6 +45,7 @@ class sogrand_kernel_stat_t(ctypes.Structure):
         ("words", ctypes.c_uint64),
         ("queries", ctypes.c_uint64),
         ("ranks", ctypes.c_uint64),
+        ("exact_rank", ctypes.c_uint64),
     ]
 
 
@@ -146,7 +148,8 @@ def profile_end():
     n = ctypes.c_int()
     _check(lib().sogrand_profile_end(arr, 16, ctypes.byref(n)))
     return {arr[i].kernel.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, words=arr[i].words,
-                                         queries=arr[i].queries, ranks=arr[i].ranks) for i in range(n.value)}
+                                         queries=arr[i].queries, ranks=arr[i].ranks,
+                                         exact_rank=arr[i].exact_rank) for i in range(n.value)}
 
 
 def params(list_max=4, query_cap=1000, alpha=0.5, max_iter=4, early_stop=True, precision=SOGRAND_F64):

@@ -16,30 +16,57 @@
 // All probabilities are binary64; p(0|r) cancels in every ratio and is never
 // formed.
 #include <cmath>
+#include <cstdlib>
 
 #include "internal.hpp"
 
 namespace sg {
 
 constexpr int kWave = 64;
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = 4;            // init and check kernels
 constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kXcds = 8;                     // MI355X: workgroups are dealt to 8 XCDs in turn
 
+// Per-wave scratch.  The rank tables hs_r, rlo_r and rhi_r share one 4-byte
+// stride, so a rank's three lookups use one address register, and ranks below 32
+// fall in distinct LDS banks.
 struct WaveLds {
-    double rho_r[SOGRAND_NMAX + 1];      // rho by rank (1..n); [0] = 1 for zero padding
+    uint32_t hs_r[SOGRAND_NMAX + 4];     // H column by rank (1..n); [0] = 0 for zero padding
+    uint32_t rlo_r[SOGRAND_NMAX + 4];    // low and high words of rho by rank; [0] = 1.0
+    uint32_t rhi_r[SOGRAND_NMAX + 4];
     uint64_t key_b[SOGRAND_NMAX + 2];    // |lambda| bit patterns by bit index, padded with ~0
     double tau_l[SOGRAND_LIST_MAX];      // prod rho of each found pattern
     uint4 pat_l[SOGRAND_LIST_MAX];       // found patterns (ranks)
-    uint32_t hs_r[SOGRAND_NMAX + 1];     // H column by rank; [0] = 0
     uint32_t q_l[SOGRAND_LIST_MAX];      // query number of each found codeword
+    uint32_t zmask[SOGRAND_NMAX];        // bit l set iff the bit lies in found pattern l
     uint8_t pi_r[SOGRAND_NMAX + 1];      // bit index of each rank
-    uint8_t zf[SOGRAND_NMAX];            // membership flags of one found pattern, by bit index
+    uint8_t rank_b[SOGRAND_NMAX];        // rank of each bit index
 };
+
+// Logical index of this workgroup.  With xcd set, consecutive logical indices (the
+// lines of one frame) go to the same XCD and share its L2; the grid is then a
+// multiple of 8.
+__device__ __forceinline__ size_t logical_block(bool xcd) {
+    if (!xcd) return blockIdx.x;
+    const size_t per = gridDim.x / kXcds;
+    return (size_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
 
 template <int NS>
 struct Lanes {
     static constexpr int NB = NS > 64 ? 2 : 1;   // elements held per lane
 };
+
+#ifdef SOGRAND_PHASE_TIMING
+// Experiment builds only: cycles spent per phase of decode_word, summed over words.
+__device__ unsigned long long g_phase_cycles[8];
+#define SG_STAMP(v) const long long v = clock64()
+#define SG_PHASE(i, a, b) \
+    if (lane == 0) atomicAdd(&g_phase_cycles[i], (unsigned long long)((b) - (a)))
+#else
+#define SG_STAMP(v)
+#define SG_PHASE(i, a, b)
+#endif
 
 struct WordStats {
     uint32_t Q;      // patterns tested
@@ -47,6 +74,7 @@ struct WordStats {
     double pnf;      // P(transmitted codeword not in the list)
     double D;        // normaliser: sum of found prod rho + not-found mass * phi (relative to p(0|r))
     uint64_t ranks;  // sum of the Hamming weights of the tested patterns (only when counting)
+    int exact_rank;  // the ranks needed the exact (counting) pass
 };
 
 // number of nonzero bytes of a packed pattern (its Hamming weight)
@@ -75,9 +103,9 @@ __device__ __forceinline__ void wave_sync() {
 template <int M>
 __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
     if constexpr (M == 1) {
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);
     } else if constexpr (M == 2) {
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false);
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);
     } else if constexpr (M == 4) {
         const int t = __builtin_amdgcn_update_dpp((int)v, (int)v, 0x104, 0xF, 0x5, false);
         return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x114, 0xF, 0xA, false);
@@ -145,14 +173,200 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// parity-class masses of two disjoint bit sets combined (see decode_word step 3)
+// parity-class masses of two disjoint bit sets combined (see decode_word step 3):
+// E = E1 + E2 (1 + E1) + O1 O2 and O = O1 (1 + E2) + O2 (1 + E1), sums of positive terms
 template <int M>
 __device__ __forceinline__ void eo_combine(double &E, double &O) {
     const double E2 = xor_lane_f64<M>(E), O2 = xor_lane_f64<M>(O);
-    const double nE = (E + E2) + (E * E2 + O * O2);
-    const double nO = (O + O2) + (E * O2 + O * E2);
+    const double t1 = 1.0 + E, t2 = 1.0 + E2;
+    const double nE = fma(O, O2, fma(E2, t1, E));
+    const double nO = fma(O, t2, O2 * t1);
     E = nE;
     O = nO;
+}
+
+// v from lane (lane ^ (K-1)), the mirror image inside aligned blocks of K lanes:
+// quad_perm [3,2,1,0], row_half_mirror and row_mirror, composed with the permlane
+// swaps for blocks of 32 and 64 lanes
+// full-mask DPP permutation (every lane reads a lane of its own row)
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_perm(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t flip_lane(uint32_t v) {
+    if constexpr (K == 2) {
+        return dpp_perm<0xB1>(v);
+    } else if constexpr (K == 4) {
+        return dpp_perm<0x1B>(v);
+    } else if constexpr (K == 8) {
+        return dpp_perm<0x141>(v);
+    } else if constexpr (K == 16) {
+        return dpp_perm<0x140>(v);
+    } else if constexpr (K == 32) {
+        return dpp_perm<0x140>(xor_lane<16>(v));
+    } else {
+        static_assert(K == 64, "block size");
+        return dpp_perm<0x140>(xor_lane<16>(xor_lane<32>(v)));
+    }
+}
+
+template <int K>
+__device__ __forceinline__ uint64_t flip_lane64(uint64_t v) {
+    return ((uint64_t)flip_lane<K>((uint32_t)(v >> 32)) << 32) | flip_lane<K>((uint32_t)v);
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v) {
+    return ((uint64_t)xor_lane<M>((uint32_t)(v >> 32)) << 32) | xor_lane<M>((uint32_t)v);
+}
+
+// compare-exchange in an ascending network: the lower position keeps the minimum
+__device__ __forceinline__ void cas64(uint64_t &k, uint64_t p, bool lower) {
+    const bool lt = p < k;
+    const uint64_t mn = lt ? p : k, mx = lt ? k : p;
+    k = lower ? mn : mx;
+}
+
+// Bitonic network with ascending comparators only: for each block size K the
+// first step compares mirror images inside the block, the next ones compare
+// positions J = K/4, ..., 1 apart.
+template <int K, int J>
+__device__ __forceinline__ void merge64x2(uint64_t (&k)[2], int lane) {
+    if constexpr (J >= 1) {
+        cas64(k[0], xor_lane64<J>(k[0]), (lane & J) == 0);
+        cas64(k[1], xor_lane64<J>(k[1]), (lane & J) == 0);
+        merge64x2<K, J / 2>(k, lane);
+    }
+}
+
+// 128 keys, element e = lane + 64*slot
+template <int K>
+__device__ __forceinline__ void sort64x2(uint64_t (&k)[2], int lane) {
+    if constexpr (K <= 64) {
+        cas64(k[0], flip_lane64<K>(k[0]), (lane & (K / 2)) == 0);
+        cas64(k[1], flip_lane64<K>(k[1]), (lane & (K / 2)) == 0);
+        merge64x2<K, K / 4>(k, lane);
+        sort64x2<K * 2>(k, lane);
+    } else if constexpr (K == 128) {
+        // mirror of element lane (slot 0) is element 127 - lane = slot 1 of lane 63 - lane
+        const uint64_t f0 = flip_lane64<64>(k[0]), f1 = flip_lane64<64>(k[1]);
+        k[0] = f1 < k[0] ? f1 : k[0];
+        k[1] = f0 > k[1] ? f0 : k[1];
+        merge64x2<128, 32>(k, lane);
+    }
+}
+
+// ---- binary64 elementary functions for the per-bit work ----
+constexpr double kLn2Hi = 0x1.62e42fefa2000p-1;   // ln 2 to 40 bits: k * kLn2Hi is exact for |k| < 2^13
+constexpr double kLn2Lo = 0x1.9ef35793c7673p-41;  // ln 2 - kLn2Hi
+constexpr double kInvLn2 = 1.4426950408889634;
+
+// 1/x for positive normal x: hardware reciprocal and two Newton steps
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// e^{-a}, a >= 0: Cody-Waite reduction a = k ln2 + r with |r| <= ln2/2, then the
+// degree-13 Taylor polynomial of e^{-r} (truncation below 2^-57 relative)
+__device__ __forceinline__ double exp_neg(double a) {
+    const double ac = a < 1100.0 ? a : 1100.0;
+    const double k = rint(ac * kInvLn2);
+    double r = fma(-k, kLn2Hi, ac);
+    r = fma(-k, kLn2Lo, r);
+    const double x = -r;
+    double p = 1.0 / 6227020800.0;
+    p = fma(p, x, 1.0 / 479001600.0);
+    p = fma(p, x, 1.0 / 39916800.0);
+    p = fma(p, x, 1.0 / 3628800.0);
+    p = fma(p, x, 1.0 / 362880.0);
+    p = fma(p, x, 1.0 / 40320.0);
+    p = fma(p, x, 1.0 / 5040.0);
+    p = fma(p, x, 1.0 / 720.0);
+    p = fma(p, x, 1.0 / 120.0);
+    p = fma(p, x, 1.0 / 24.0);
+    p = fma(p, x, 1.0 / 6.0);
+    p = fma(p, x, 0.5);
+    p = fma(p, x, 1.0);
+    p = fma(p, x, 1.0);
+    return ldexp(p, -(int)k);
+}
+
+// ln x for finite x > 0 of normal magnitude: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
+// ln m = 2 atanh(s) = 2 s sum_j s^{2j} / (2j + 1) with s = (m - 1)/(m + 1), |s| < 0.1716
+__device__ __forceinline__ double log_pos(double x) {
+    double m = __builtin_amdgcn_frexp_mant(x);
+    int e = __builtin_amdgcn_frexp_exp(x);
+    if (m < 0.70710678118654752) {
+        m = m + m;
+        e -= 1;
+    }
+    const double num = m - 1.0, den = m + 1.0;
+    const double rd = rcp_nr(den);
+    double s = num * rd;
+    s = fma(fma(-den, s, num), rd, s);
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    p = fma(p, z, 1.0);
+    const double lm = (s + s) * p;
+    const double de = (double)e;
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+}
+
+// ln(N0 / N1) for N0, N1 >= 0 not both zero: the mantissas' ratio (in (1/2, 2)) goes
+// through ln, the exponents' difference is added as a multiple of ln 2
+__device__ __forceinline__ double log_ratio(double n0, double n1) {
+    const double m0 = __builtin_amdgcn_frexp_mant(n0), m1 = __builtin_amdgcn_frexp_mant(n1);
+    const int e0 = __builtin_amdgcn_frexp_exp(n0), e1 = __builtin_amdgcn_frexp_exp(n1);
+    const double r = rcp_nr(m1);
+    double q = m0 * r;
+    q = fma(fma(-m1, q, m0), r, q);
+    const double de = (double)(e0 - e1);
+    double la = fma(de, kLn2Hi, fma(de, kLn2Lo, log_pos(q)));
+    if (n1 == 0.0) la = 1000.0;
+    if (n0 == 0.0) la = -1000.0;
+    return la;
+}
+
+// zmask[bit] |= 1 << l for every bit of found pattern l: lane t handles byte t % 16
+// of pattern t / 16 (+ 4 per round); rank r maps back to its bit through pi_r.
+__device__ __forceinline__ void mark_found(WaveLds &S, int found, int lane) {
+    for (int g = 0; g < found; g += 4) {
+        const int l = g + (lane >> 4);
+        if (l < found) {
+            const uint4 pl = S.pat_l[l];
+            const int j = lane & 15;
+            const uint32_t d = j < 4 ? pl.x : (j < 8 ? pl.y : (j < 12 ? pl.z : pl.w));
+            const uint32_t r = (d >> (8 * (j & 3))) & 0xffu;
+            if (r) atomicOr(&S.zmask[S.pi_r[r]], 1u << l);
+        }
+    }
+    wave_sync();
+}
+
+__device__ __forceinline__ double rho_at(const WaveLds &S, int r) {
+    return __longlong_as_double((long long)(((uint64_t)S.rhi_r[r] << 32) | S.rlo_r[r]));
+}
+
+__device__ __forceinline__ void put_rho(WaveLds &S, int r, double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    S.rlo_r[r] = (uint32_t)u;
+    S.rhi_r[r] = (uint32_t)(u >> 32);
 }
 
 // One rank of a pattern: r is byte SH/8 of dword d.
@@ -160,7 +374,7 @@ __device__ __forceinline__ void eo_combine(double &E, double &O) {
     do {                                                 \
         const uint32_t r_ = ((d) >> (SH)) & 0xffu;       \
         s ^= S.hs_r[r_];                                 \
-        tau *= S.rho_r[r_];                              \
+        tau *= rho_at(S, r_);                            \
     } while (0)
 
 // Decodes one word held as lam[slot] at bit index lane + 64*slot (< n).
@@ -171,6 +385,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
                                                  double (&lapp)[Lanes<NS>::NB], int lane, bool count) {
     constexpr int NB = Lanes<NS>::NB;
     const int n = c.n;
+    SG_STAMP(t0);
 
     // 1. hard decision, its syndrome and parity; keys |lambda| and rho = e^-|lambda| by bit
     bool valid[NB];
@@ -188,78 +403,113 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
         ycount += __popcll(__ballot(ybit[b]));
         const double a = fabs(lam[b]);
         key[b] = valid[b] ? (uint64_t)__double_as_longlong(a) : ~0ull;
-        rho[b] = valid[b] ? exp(-a) : 0.0;
-        if (i < SOGRAND_NMAX + 2) S.key_b[i] = key[b];
+        rho[b] = valid[b] ? exp_neg(a) : 0.0;
     }
-    if (NB == 1 && lane < 2) S.key_b[kWave + lane] = ~0ull;
     const uint32_t s0 = wave_xor(spart);
     const int par = ycount & 1;
-    wave_sync();
+    SG_STAMP(t1);
 
-    // 2. reliability rank of each bit: the number of smaller keys (bit patterns of
-    //    non-negative doubles order like the values), ties broken by the bit index
-    uint32_t cnt[NB];
-#pragma unroll
-    for (int b = 0; b < NB; b++) cnt[b] = 0;
-    for (int j = 0; j < n; j += 2) {
-        const uint64_t k0 = S.key_b[j], k1 = S.key_b[j + 1];
-#pragma unroll
-        for (int b = 0; b < NB; b++) {
-            cnt[b] += (k0 < key[b]) ? 1u : 0u;
-            cnt[b] += (k1 < key[b]) ? 1u : 0u;
+    // 2. reliability ranks (|lambda| ascending, ties by bit index)
+    int myrank[NB];
+    bool exact_pass = false;
+    if constexpr (NB == 1) {
+        // rank = number of smaller keys (bit patterns of non-negative doubles order like
+        // the values); the ranks sum to n(n-1)/2 unless equal keys exist, and then each
+        // group of equal keys is ordered by bit index
+        S.key_b[lane] = key[0];
+        if (lane < 2) S.key_b[kWave + lane] = ~0ull;
+        wave_sync();
+        uint32_t cnt = 0;
+        for (int j = 0; j < n; j += 2) {
+            const uint64_t k0 = S.key_b[j], k1 = S.key_b[j + 1];
+            cnt += (k0 < key[0]) ? 1u : 0u;
+            cnt += (k1 < key[0]) ? 1u : 0u;
         }
-    }
-    {
-        uint32_t part = 0;
-#pragma unroll
-        for (int b = 0; b < NB; b++) part += valid[b] ? cnt[b] : 0u;
-        const uint32_t tot = __builtin_amdgcn_readfirstlane(wave_add(part));
+        const uint32_t tot = __builtin_amdgcn_readfirstlane(wave_add(valid[0] ? cnt : 0u));
         if (tot != (uint32_t)(n * (n - 1) / 2)) {
-            // equal keys share a count: order each group of equal keys by bit index
+            exact_pass = true;
+            for (int j = 0; j < n; j++) {
+                const uint64_t kj = S.key_b[j];
+                cnt += (kj == key[0] && j < lane) ? 1u : 0u;
+            }
+        }
+        myrank[0] = valid[0] ? (int)cnt + 1 : 0;
+    } else {
+        // 128 keys whose low 7 bits are replaced by the bit index, sorted by a bitonic
+        // network; if two neighbours then agree in every remaining key bit the truncation
+        // may have decided their order, and the ranks are recomputed by counting
+        uint64_t k64[2];
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            const uint64_t id = (uint64_t)(lane + kWave * b);
+            k64[b] = valid[b] ? ((key[b] & ~127ull) | id) : (~127ull | id);
+        }
+        sort64x2<2>(k64, lane);
+        const uint64_t n0 = __shfl_down(k64[0], 1), n1 = __shfl_down(k64[1], 1);
+        const uint64_t first1 = __shfl(k64[1], 0);
+        const uint64_t nx0 = lane == kWave - 1 ? first1 : n0;
+        bool amb = lane + 1 < n && (k64[0] >> 7) == (nx0 >> 7);
+        amb |= lane + kWave + 1 < n && (k64[1] >> 7) == (n1 >> 7);
+        exact_pass = __ballot(amb) != 0ull;
+        if (!exact_pass) {
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+                if (lane + kWave * b < n) S.rank_b[k64[b] & 127ull] = (uint8_t)(lane + kWave * b + 1);
+            wave_sync();
+#pragma unroll
+            for (int b = 0; b < 2; b++) myrank[b] = valid[b] ? S.rank_b[lane + kWave * b] : 0;
+        } else {
+#pragma unroll
+            for (int b = 0; b < 2; b++) S.key_b[lane + kWave * b] = key[b];
+            wave_sync();
+            uint32_t cnt[2] = {0u, 0u};
             for (int j = 0; j < n; j++) {
                 const uint64_t kj = S.key_b[j];
 #pragma unroll
-                for (int b = 0; b < NB; b++) cnt[b] += (kj == key[b] && j < lane + kWave * b) ? 1u : 0u;
+                for (int b = 0; b < 2; b++)
+                    cnt[b] += (kj < key[b] || (kj == key[b] && j < lane + kWave * b)) ? 1u : 0u;
             }
+#pragma unroll
+            for (int b = 0; b < 2; b++) myrank[b] = valid[b] ? (int)cnt[b] + 1 : 0;
         }
     }
-    int myrank[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
-        myrank[b] = valid[b] ? (int)cnt[b] + 1 : 0;
         if (valid[b]) {
             S.hs_r[myrank[b]] = c.hcol[i];
-            S.rho_r[myrank[b]] = rho[b];
+            put_rho(S, myrank[b], rho[b]);
             S.pi_r[myrank[b]] = (uint8_t)i;
         }
+        if (i < SOGRAND_NMAX) S.zmask[i] = 0u;
     }
     if (lane == 0) {
         S.hs_r[0] = 0u;
-        S.rho_r[0] = 1.0;
+        put_rho(S, 0, 1.0);
     }
+    wave_sync();
 
+    SG_STAMP(t2);
     // 3. parity-class masses: adding bit i maps (E, O) to (E + O rho_i, O + (1 + E) rho_i);
-    //    two disjoint bit sets combine as E = E1 + E2 + E1 E2 + O1 O2, O = O1 + O2 + E1 O2 + O1 E2
+    //    two disjoint bit sets combine as E = E1 + E2 + E1 E2 + O1 O2, O = O1 + O2 + E1 O2 + O1 E2.
+    //    Lane t folds ranks 8t+1 .. 8t+8 in turn, then NS/8 lanes combine pairwise.
     double E = 0.0, O = 0.0;
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
-        if (valid[b]) {
-            const double e2 = E + O * rho[b];
-            const double o2 = O + (1.0 + E) * rho[b];
-            E = e2;
-            O = o2;
-        }
+    for (int j = 0; j < 8; j++) {
+        const int r = 8 * lane + j + 1;
+        const double rr = r <= n ? rho_at(S, r < SOGRAND_NMAX ? r : SOGRAND_NMAX) : 0.0;
+        const double e2 = E + O * rr;
+        const double o2 = O + (1.0 + E) * rr;
+        E = e2;
+        O = o2;
     }
     eo_combine<1>(E, O);
     eo_combine<2>(E, O);
-    eo_combine<4>(E, O);
-    eo_combine<8>(E, O);
-    eo_combine<16>(E, O);
-    eo_combine<32>(E, O);
+    if constexpr (NS >= 64) eo_combine<4>(E, O);
+    if constexpr (NS >= 128) eo_combine<8>(E, O);
     E = bcast0(E);
     O = bcast0(O);
-    wave_sync();
+    SG_STAMP(t3);
 
     // 4. query loop over the schedule of the word's parity class; the next chunk's
     //    patterns are fetched while the current one is tested
@@ -271,40 +521,52 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
     uint32_t Q = 0;
     double s_lane = 0.0;   // this lane's share of the tested nonzero-pattern mass (relative to p(0|r))
     uint32_t w_lane = 0;   // this lane's share of the tested pattern weights (counting only)
-    uint4 e_next = make_uint4(0u, 0u, 0u, 0u);
+    // patterns of the next two chunks are in flight while a chunk is tested
+    uint4 e_next = make_uint4(0u, 0u, 0u, 0u), e_next2 = make_uint4(0u, 0u, 0u, 0u);
     if ((uint32_t)lane < limit) e_next = tab[lane];
+    if ((uint32_t)lane + kWave < limit) e_next2 = tab[kWave + lane];
     uint32_t wm_next = wm[0];
+    uint32_t wm_next2 = limit > (uint32_t)kWave ? wm[1] : 0u;
     for (uint32_t base = 0; base < limit; base += kWave) {
         const uint4 e = e_next;
         const uint32_t wmx = wm_next;
         const uint32_t nb = base + kWave;
-        if (nb < limit) {
-            e_next = make_uint4(0u, 0u, 0u, 0u);
-            if (nb + (uint32_t)lane < limit) e_next = tab[nb + lane];
-            wm_next = wm[nb >> 6];
+        e_next = e_next2;
+        wm_next = wm_next2;
+        const uint32_t nb2 = nb + kWave;
+        if (nb2 < limit) {
+            e_next2 = make_uint4(0u, 0u, 0u, 0u);
+            if (nb2 + (uint32_t)lane < limit) e_next2 = tab[nb2 + lane];
+            wm_next2 = wm[nb2 >> 6];
         }
         const bool act = base + (uint32_t)lane < limit;
         uint32_t s = s0;
         double tau = 1.0;
-        if (wmx > 0) SG_RANK(e.x, 0);
-        if (wmx > 1) SG_RANK(e.x, 8);
-        if (wmx > 2) SG_RANK(e.x, 16);
-        if (wmx > 3) SG_RANK(e.x, 24);
-        if (wmx > 4) {
-            SG_RANK(e.y, 0);
-            if (wmx > 5) SG_RANK(e.y, 8);
-            if (wmx > 6) SG_RANK(e.y, 16);
-            if (wmx > 7) SG_RANK(e.y, 24);
-            if (wmx > 8) {
-                SG_RANK(e.z, 0);
-                if (wmx > 9) SG_RANK(e.z, 8);
-                if (wmx > 10) SG_RANK(e.z, 16);
-                if (wmx > 11) SG_RANK(e.z, 24);
-                if (wmx > 12) {
-                    SG_RANK(e.w, 0);
-                    if (wmx > 13) SG_RANK(e.w, 8);
-                    if (wmx > 14) SG_RANK(e.w, 16);
-                    if (wmx > 15) SG_RANK(e.w, 24);
+        // ranks in straight-line pairs (rank 0 pads: hs 0, rho 1), so that both
+        // lookups of a pair are in flight together
+        SG_RANK(e.x, 0);
+        SG_RANK(e.x, 8);
+        if (wmx > 2) {
+            SG_RANK(e.x, 16);
+            SG_RANK(e.x, 24);
+            if (wmx > 4) {
+                SG_RANK(e.y, 0);
+                SG_RANK(e.y, 8);
+                if (wmx > 6) {
+                    SG_RANK(e.y, 16);
+                    SG_RANK(e.y, 24);
+                    if (wmx > 8) {
+                        SG_RANK(e.z, 0);
+                        SG_RANK(e.z, 8);
+                        SG_RANK(e.z, 16);
+                        SG_RANK(e.z, 24);
+                        if (wmx > 12) {
+                            SG_RANK(e.w, 0);
+                            SG_RANK(e.w, 8);
+                            SG_RANK(e.w, 16);
+                            SG_RANK(e.w, 24);
+                        }
+                    }
                 }
             }
         }
@@ -335,7 +597,9 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
         }
         Q = limit < nb ? limit : nb;
     }
+
     const double Snz = bcast0(wave_sum(s_lane));
+    SG_STAMP(t4);
 
     // 5. Corollary 1 inside the parity class: not-found mass M = (class mass) - (tested mass),
     //    both relative to p(0|r); the zero pattern (first in its class) cancels exactly.
@@ -349,54 +613,56 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
     const bool degenerate = !(D > 0.0) || !isfinite(D);
     if (degenerate) pnf = 1.0;   // every probability underflowed: keep the soft input
 
+    SG_STAMP(t5);
     // eq. (LLRi): list codewords weighted by their APPs, plus the soft input weighted by P_nf
     double N0[NB], N1[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const double qs = 1.0 / (1.0 + rho[b]);   // p(bit = y | soft input)
+        const double qs = rcp_nr(1.0 + rho[b]);   // p(bit = y | soft input)
         const double qf = rho[b] * qs;            // p(bit != y | soft input)
         N0[b] = pnf * (ybit[b] ? qf : qs);
         N1[b] = pnf * (ybit[b] ? qs : qf);
     }
     if (!degenerate) {
         const double invD = 1.0 / D;
-        for (int l = 0; l < found; l++) {
-            // membership flags of pattern l: clear, then mark the bits of its ranks
+        mark_found(S, found, lane);
+        uint32_t zm[NB];
 #pragma unroll
-            for (int b = 0; b < NB; b++)
-                if (lane + kWave * b < SOGRAND_NMAX) S.zf[lane + kWave * b] = 0;
-            wave_sync();
-            const uint4 pl = S.pat_l[l];
-            if (lane < 16) {
-                const uint32_t d = lane < 4 ? pl.x : (lane < 8 ? pl.y : (lane < 12 ? pl.z : pl.w));
-                const uint32_t r = (d >> (8 * (lane & 3))) & 0xffu;
-                if (r) S.zf[S.pi_r[r]] = 1;
-            }
-            wave_sync();
+        for (int b = 0; b < NB; b++) {
+            const int i = lane + kWave * b;
+            zm[b] = i < SOGRAND_NMAX ? S.zmask[i] : 0u;
+        }
+        for (int l = 0; l < found; l++) {
             const double P = S.tau_l[l] * invD;
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                const int i = lane + kWave * b;
-                const int z = i < SOGRAND_NMAX ? S.zf[i] : 0;
-                if (ybit[b] ^ z) N1[b] += P;
-                else N0[b] += P;
+                const bool one = (ybit[b] ^ (int)((zm[b] >> l) & 1u)) != 0;
+                N1[b] += one ? P : 0.0;
+                N0[b] += one ? 0.0 : P;
             }
-            wave_sync();
         }
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        double la = log(N0[b] / N1[b]);
+        double la = log_ratio(N0[b], N1[b]);
         if (!(la <= 1000.0)) la = 1000.0;
         if (!(la >= -1000.0)) la = -1000.0;
         lapp[b] = la;
     }
+    SG_STAMP(t6);
+    SG_PHASE(0, t0, t1);
+    SG_PHASE(1, t1, t2);
+    SG_PHASE(2, t2, t3);
+    SG_PHASE(3, t3, t4);
+    SG_PHASE(4, t4, t5);
+    SG_PHASE(5, t5, t6);
     WordStats st;
     st.Q = Q;
     st.found = found;
     st.pnf = pnf;
     st.D = D;
     st.ranks = 0;
+    st.exact_rank = exact_pass ? 1 : 0;
     if (count) st.ranks = wave_add(w_lane);
     return st;
 }
@@ -420,23 +686,26 @@ struct ComponentArgs {
     double *p_notfound;
     uint8_t *found_z;
     ProfCounters *prof;
+    int xcd;
 };
 
 __device__ __forceinline__ void prof_add(ProfCounters *p, const WordStats &st) {
+    p += blockIdx.x % kProfSlots;
     atomicAdd(&p->words, 1ull);
     atomicAdd(&p->queries, (unsigned long long)st.Q);
     atomicAdd(&p->ranks, (unsigned long long)st.ranks);
+    if (st.exact_rank) atomicAdd(&p->exact_rank, 1ull);
 }
 
-template <typename T, int NS>
-__global__ __launch_bounds__(kBlock) void k_component(ComponentArgs a) {
+template <typename T, int NS, int WPB>
+__global__ __launch_bounds__(kWave * WPB) void k_component(ComponentArgs a) {
     constexpr int NB = Lanes<NS>::NB;
-    __shared__ WaveLds lds[kWavesPerBlock];
+    __shared__ WaveLds lds[WPB];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    const size_t wid = (size_t)blockIdx.x * kWavesPerBlock + wave;
-    if (wid >= a.nwords) return;
+    const int wave = WPB == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     WaveLds &S = lds[wave];
+    const size_t wid = logical_block(a.xcd) * WPB + wave;
+    if (wid >= a.nwords) return;
     const int n = a.code.n;
     const T *in = static_cast<const T *>(a.llr_in) + wid * n;
     double lam[NB];
@@ -468,28 +737,16 @@ __global__ __launch_bounds__(kBlock) void k_component(ComponentArgs a) {
         if (a.p_found) a.p_found[wid * a.L + lane] = f ? S.tau_l[lane] / st.D : 0.0;
     }
     if (a.found_z) {
+        // zmask was filled by the soft-output step unless every probability underflowed
+        if (!(st.D > 0.0) || !isfinite(st.D)) mark_found(S, st.found, lane);
         for (int l = 0; l < a.L; l++) {
-            if (l < st.found) {
-#pragma unroll
-                for (int b = 0; b < NB; b++)
-                    if (lane + kWave * b < SOGRAND_NMAX) S.zf[lane + kWave * b] = 0;
-                wave_sync();
-                const uint4 pl = S.pat_l[l];
-                if (lane < 16) {
-                    const uint32_t d = lane < 4 ? pl.x : (lane < 8 ? pl.y : (lane < 12 ? pl.z : pl.w));
-                    const uint32_t r = (d >> (8 * (lane & 3))) & 0xffu;
-                    if (r) S.zf[S.pi_r[r]] = 1;
-                }
-                wave_sync();
-            }
 #pragma unroll
             for (int b = 0; b < NB; b++) {
                 const int i = lane + kWave * b;
                 if (i >= n) continue;
-                const uint8_t z = l < st.found ? S.zf[i] : 0;
+                const uint8_t z = l < st.found ? (uint8_t)((S.zmask[i] >> l) & 1u) : 0;
                 a.found_z[(wid * a.L + l) * n + i] = z;
             }
-            wave_sync();
         }
     }
 }
@@ -516,6 +773,7 @@ struct ProductArgs {
     uint16_t *half_iters;   // [F]
     int early_stop;
     ProfCounters *prof;
+    int xcd;
 };
 
 template <typename T>
@@ -536,21 +794,23 @@ __global__ __launch_bounds__(kBlock) void k_product_init(ProductArgs a) {
 }
 
 // One wave per line: ROWS decodes row `line` of L_Ch + L_A, otherwise column `line`.
-template <typename T, int NS, bool ROWS>
-__global__ __launch_bounds__(kBlock) void k_product_pass(ProductArgs a) {
+template <typename T, int NS, bool ROWS, int WPB>
+__global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
     constexpr int NB = Lanes<NS>::NB;
-    __shared__ WaveLds lds[kWavesPerBlock];
+    __shared__ WaveLds lds[WPB];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    const int n = a.code.n;
-    const size_t wid = (size_t)blockIdx.x * kWavesPerBlock + wave;
-    const size_t f = wid / n;
-    const int line = (int)(wid % n);
+    const int wave = WPB == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    WaveLds &S = lds[wave];
+    const uint32_t n = (uint32_t)a.code.n;
+    // the host keeps nframes * n below 2^31
+    const uint32_t wid = (uint32_t)logical_block(a.xcd) * WPB + (uint32_t)wave;
+    const uint32_t f = wid / n;
+    const int line = (int)(wid - f * n);
     if (f >= a.nframes) return;
     if (a.done[f]) return;
-    WaveLds &S = lds[wave];
-    const T *ch = static_cast<const T *>(a.llr_ch) + f * n * n;
-    T *la = static_cast<T *>(a.la) + f * n * n;
+    const size_t fo = (size_t)f * n * n;   // element offset of frame f
+    const T *ch = static_cast<const T *>(a.llr_ch) + fo;
+    T *la = static_cast<T *>(a.la) + fo;
     double lam[NB];
     int pos[NB];
 #pragma unroll
@@ -572,12 +832,12 @@ __global__ __launch_bounds__(kBlock) void k_product_pass(ProductArgs a) {
         if (!v) continue;
         const double le = lapp[b] - lam[b];
         la[pos[b]] = (T)(a.alpha * le);
-        if (a.llr_app) static_cast<T *>(a.llr_app)[f * n * n + pos[b]] = (T)lapp[b];
-        a.hard[f * n * n + pos[b]] = neg;
+        if (a.llr_app) static_cast<T *>(a.llr_app)[fo + pos[b]] = (T)lapp[b];
+        a.hard[fo + pos[b]] = neg;
     }
     if (lane == 0) {
-        a.masks[(f * n + line) * 2 + 0] = hm[0];
-        a.masks[(f * n + line) * 2 + 1] = hm[1];
+        a.masks[((size_t)f * n + line) * 2 + 0] = hm[0];
+        a.masks[((size_t)f * n + line) * 2 + 1] = hm[1];
         atomicAdd(reinterpret_cast<unsigned long long *>(&a.sumq[f]), (unsigned long long)st.Q);
         atomicMax(&a.halfmax[f], st.Q);
     }
@@ -629,23 +889,77 @@ __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, 
 // ----------------------------------------------------------------------------
 static int sort_width(int n) { return n <= 32 ? 32 : (n <= 64 ? 64 : 128); }
 
+// Launch shape of the decode kernels: waves per workgroup and the XCD-aware
+// workgroup order.  Defaults come from measurement on MI355X; SOGRAND_WPB (1, 2
+// or 4) and SOGRAND_XCD (0 or 1) override them.
+struct LaunchShape {
+    int wpb;
+    int xcd;
+};
+
+static LaunchShape launch_shape() {
+    static const LaunchShape shape = [] {
+        LaunchShape s{4, 0};
+        if (const char *e = getenv("SOGRAND_WPB")) {
+            const int v = atoi(e);
+            if (v == 1 || v == 2 || v == 4) s.wpb = v;
+        }
+        if (const char *e = getenv("SOGRAND_XCD")) s.xcd = atoi(e) != 0;
+        return s;
+    }();
+    return shape;
+}
+
+// workgroups covering `words` words, rounded up to a multiple of the XCD count when
+// the XCD-aware order is on
+static size_t word_grid(size_t words, const LaunchShape &ls) {
+    size_t g = (words + ls.wpb - 1) / ls.wpb;
+    if (ls.xcd) g = (g + kXcds - 1) / kXcds * kXcds;
+    return g;
+}
+
+template <typename T, int WPB>
+static void launch_component_w(const ComponentArgs &a, int ns, dim3 g, hipStream_t st) {
+    if (ns == 32) hipLaunchKernelGGL((k_component<T, 32, WPB>), g, dim3(kWave * WPB), 0, st, a);
+    else if (ns == 64) hipLaunchKernelGGL((k_component<T, 64, WPB>), g, dim3(kWave * WPB), 0, st, a);
+    else hipLaunchKernelGGL((k_component<T, 128, WPB>), g, dim3(kWave * WPB), 0, st, a);
+}
+
 template <typename T>
-static void launch_component(const ComponentArgs &a, int ns, dim3 g, hipStream_t st) {
-    if (ns == 32) hipLaunchKernelGGL((k_component<T, 32>), g, dim3(kBlock), 0, st, a);
-    else if (ns == 64) hipLaunchKernelGGL((k_component<T, 64>), g, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_component<T, 128>), g, dim3(kBlock), 0, st, a);
+static void launch_component(const ComponentArgs &a, int ns, int wpb, dim3 g, hipStream_t st) {
+    if (wpb == 1) launch_component_w<T, 1>(a, ns, g, st);
+    else if (wpb == 2) launch_component_w<T, 2>(a, ns, g, st);
+    else launch_component_w<T, 4>(a, ns, g, st);
+}
+
+template <typename T, bool ROWS, int WPB>
+static void launch_pass_w(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
+    if (ns == 32) hipLaunchKernelGGL((k_product_pass<T, 32, ROWS, WPB>), g, dim3(kWave * WPB), 0, st, a);
+    else if (ns == 64) hipLaunchKernelGGL((k_product_pass<T, 64, ROWS, WPB>), g, dim3(kWave * WPB), 0, st, a);
+    else hipLaunchKernelGGL((k_product_pass<T, 128, ROWS, WPB>), g, dim3(kWave * WPB), 0, st, a);
 }
 
 template <typename T, bool ROWS>
-static void launch_pass(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
-    if (ns == 32) hipLaunchKernelGGL((k_product_pass<T, 32, ROWS>), g, dim3(kBlock), 0, st, a);
-    else if (ns == 64) hipLaunchKernelGGL((k_product_pass<T, 64, ROWS>), g, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_product_pass<T, 128, ROWS>), g, dim3(kBlock), 0, st, a);
+static void launch_pass(const ProductArgs &a, int ns, int wpb, dim3 g, hipStream_t st) {
+    if (wpb == 1) launch_pass_w<T, ROWS, 1>(a, ns, g, st);
+    else if (wpb == 2) launch_pass_w<T, ROWS, 2>(a, ns, g, st);
+    else launch_pass_w<T, ROWS, 4>(a, ns, g, st);
 }
 
 }  // namespace sg
 
 extern "C" {
+
+#ifdef SOGRAND_PHASE_TIMING
+// Experiment builds only: copies and clears the per-phase cycle totals.
+int sogrand_debug_phase_cycles(unsigned long long *out) {
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(sg::g_phase_cycles), sizeof(unsigned long long) * 8) != hipSuccess)
+        return SOGRAND_EDEVICE;
+    unsigned long long z[8] = {};
+    if (hipMemcpyToSymbol(HIP_SYMBOL(sg::g_phase_cycles), z, sizeof z) != hipSuccess) return SOGRAND_EDEVICE;
+    return SOGRAND_OK;
+}
+#endif
 
 int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t *params, size_t nwords,
                              const void *llr_in, void *llr_app, void *llr_ext, uint8_t *hard,
@@ -673,13 +987,15 @@ int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t 
     a.p_notfound = p_notfound;
     a.found_z = found_z;
     a.prof = prof_counters(PK_COMPONENT);
-    const size_t blocks = (nwords + kWavesPerBlock - 1) / kWavesPerBlock;
+    const LaunchShape ls = launch_shape();
+    a.xcd = ls.xcd;
+    const size_t blocks = word_grid(nwords, ls);
     if (blocks > 0x7fffffffull) return fail(SOGRAND_EINVAL, "nwords too large for one launch");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int ns = sort_width(code->n);
     const int tok = prof_start(PK_COMPONENT, st);
-    if (params->precision == SOGRAND_F64) launch_component<double>(a, ns, dim3((unsigned)blocks), st);
-    else launch_component<float>(a, ns, dim3((unsigned)blocks), st);
+    if (params->precision == SOGRAND_F64) launch_component<double>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
+    else launch_component<float>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
     prof_stop(tok, st);
     SG_HIP(hipGetLastError());
     return SOGRAND_OK;
@@ -696,8 +1012,10 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
     if (!llr_ch || !hard || !success) return fail(SOGRAND_EINVAL, "llr_ch, hard and success are required");
     const int n = code->n;
     const size_t words = nframes * (size_t)n;
-    if (nframes > ((size_t)1 << 34) / ((size_t)n * n)) return fail(SOGRAND_EINVAL, "nframes too large");
-    const size_t blocks = (words + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (nframes > ((size_t)1 << 34) / ((size_t)n * n) || words >= ((size_t)1 << 31))
+        return fail(SOGRAND_EINVAL, "nframes too large");
+    const LaunchShape ls = launch_shape();
+    const size_t blocks = word_grid(words, ls);
     if (blocks > 0x7fffffffull) return fail(SOGRAND_EINVAL, "nframes too large for one launch");
     ProductArgs a;
     SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &a.code));
@@ -732,6 +1050,7 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
     a.half_iters = half_iters ? half_iters : reinterpret_cast<uint16_t *>(ws + off_hi);
     a.early_stop = params->early_stop ? 1 : 0;
     a.prof = prof_counters(PK_PASS);
+    a.xcd = ls.xcd;
     const int ns = sort_width(n);
     const bool f64 = params->precision == SOGRAND_F64;
     int rc = SOGRAND_OK;
@@ -747,11 +1066,11 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
             const bool rows = (h & 1) != 0;
             tok = prof_start(PK_PASS, st);
             if (f64) {
-                if (rows) launch_pass<double, true>(a, ns, dim3((unsigned)blocks), st);
-                else launch_pass<double, false>(a, ns, dim3((unsigned)blocks), st);
+                if (rows) launch_pass<double, true>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
+                else launch_pass<double, false>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
             } else {
-                if (rows) launch_pass<float, true>(a, ns, dim3((unsigned)blocks), st);
-                else launch_pass<float, false>(a, ns, dim3((unsigned)blocks), st);
+                if (rows) launch_pass<float, true>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
+                else launch_pass<float, false>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
             }
             prof_stop(tok, st);
             tok = prof_start(PK_CHECK, st);

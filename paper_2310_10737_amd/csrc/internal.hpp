@@ -84,10 +84,13 @@ int check_params(const sogrand_params_t *p);
 enum ProfKind { PK_COMPONENT = 0, PK_PASS, PK_CHECK, PK_INIT, PK_BATCHED, PK_SERVE, PK_COUNT };
 
 struct ProfCounters {
-    unsigned long long words, queries, ranks, pad;
+    unsigned long long words, queries, ranks, exact_rank;   // exact_rank: words that needed the exact ranking pass
 };
+// Each kernel family owns kProfSlots counter slots; a workgroup adds to slot
+// blockIdx.x % kProfSlots so that the atomics do not contend on one address.
+constexpr int kProfSlots = 256;
 
-// Device counters for `kind` while work counting is on, else nullptr.
+// First of the kProfSlots device counters for `kind` while work counting is on, else nullptr.
 ProfCounters *prof_counters(ProfKind kind);
 // Returns an opaque token (or -1 when profiling is off) after recording a start event.
 int prof_start(ProfKind kind, hipStream_t st);

@@ -20,7 +20,7 @@ struct ProfState {
     bool active = false;
     bool count = false;
     int device = -1;
-    ProfCounters *d_counters = nullptr;   // [PK_COUNT]
+    ProfCounters *d_counters = nullptr;   // [PK_COUNT][kProfSlots]
     std::vector<EventPair> pairs;
     std::vector<hipEvent_t> pool;
 };
@@ -49,7 +49,7 @@ ProfCounters *prof_counters(ProfKind kind) {
     if (!s.active || !s.count || !s.d_counters) return nullptr;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != s.device) return nullptr;
-    return s.d_counters + kind;
+    return s.d_counters + (size_t)kind * kProfSlots;
 }
 
 int prof_start(ProfKind kind, hipStream_t st) {
@@ -86,8 +86,8 @@ int sogrand_profile_begin(int count_work) {
     SG_HIP(hipGetDevice(&s.device));
     s.count = count_work != 0;
     if (s.count) {
-        if (!s.d_counters) SG_HIP(hipMalloc(&s.d_counters, sizeof(ProfCounters) * PK_COUNT));
-        SG_HIP(hipMemset(s.d_counters, 0, sizeof(ProfCounters) * PK_COUNT));
+        if (!s.d_counters) SG_HIP(hipMalloc(&s.d_counters, sizeof(ProfCounters) * PK_COUNT * kProfSlots));
+        SG_HIP(hipMemset(s.d_counters, 0, sizeof(ProfCounters) * PK_COUNT * kProfSlots));
         SG_HIP(hipDeviceSynchronize());
     }
     s.active = true;
@@ -110,14 +110,17 @@ int sogrand_profile_end(sogrand_kernel_stat_t *stats, int max_stats, int *n_stat
         acc[p.kind].total_ms += ms;
     }
     if (s.count && s.d_counters) {
-        ProfCounters h[PK_COUNT];
+        std::vector<ProfCounters> h((size_t)PK_COUNT * kProfSlots);
         SG_HIP(hipDeviceSynchronize());
-        SG_HIP(hipMemcpy(h, s.d_counters, sizeof h, hipMemcpyDeviceToHost));
-        for (int k = 0; k < PK_COUNT; k++) {
-            acc[k].words = h[k].words;
-            acc[k].queries = h[k].queries;
-            acc[k].ranks = h[k].ranks;
-        }
+        SG_HIP(hipMemcpy(h.data(), s.d_counters, sizeof(ProfCounters) * h.size(), hipMemcpyDeviceToHost));
+        for (int k = 0; k < PK_COUNT; k++)
+            for (int j = 0; j < kProfSlots; j++) {
+                const ProfCounters &c = h[(size_t)k * kProfSlots + j];
+                acc[k].words += c.words;
+                acc[k].queries += c.queries;
+                acc[k].ranks += c.ranks;
+                acc[k].exact_rank += c.exact_rank;
+            }
     }
     int n = 0;
     for (int k = 0; k < PK_COUNT; k++) {
