@@ -153,6 +153,41 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
                            uint64_t *sum_max_queries, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batched product decoding: mixed codes, one persistent launch             */
+/* ------------------------------------------------------------------------ */
+/* Launch shape of the persistent kernel.  Each workgroup (waves_per_group
+   waves) keeps frames_per_group frames in flight and its waves take
+   steal_chunk rows or columns at a time from whichever of them has lines left
+   in its current half-iteration; groups_per_cu workgroups run per compute unit.
+   Every frame is decoded exactly as by sogrand_decode_product, so results do not
+   depend on the shape. */
+typedef struct {
+    int waves_per_group;   /* 4, 8 or 16 */
+    int frames_per_group;  /* 1..8 */
+    int steal_chunk;       /* 1..128 */
+    int groups_per_cu;     /* 1..64 */
+} sogrand_sched_t;
+
+/* A measured default (8 waves, 4 frames, 1 line, 2 groups per CU). */
+void sogrand_sched_default(sogrand_sched_t *s);
+
+/* Block turbo decoding (section "Iterative decoding") of nframes frames whose
+   codes may differ.  codes: HOST array of ncodes (1..8) code handles.
+   frame_code[f] (DEVICE, uint8) indexes codes; frame_offset[f] (DEVICE) is the
+   element offset of frame f's n x n row-major block in llr_ch (DEVICE, llr_len
+   elements, precision per params) and in hard (DEVICE, llr_len bytes).  Per-frame
+   outputs (DEVICE) as in sogrand_decode_product; success is required, the others
+   may be NULL.  status (DEVICE, optional) receives 0, or bit 0 if a wave gave up
+   waiting (not expected) and bit 1 if a frame descriptor was out of range (that
+   frame is skipped with success 0 and half_iters 0).  sched NULL = default.
+   Errors: EINVAL, ENOMEM, EDEVICE. */
+int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                           size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
+                           uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                           uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
+                           uint32_t *status, const sogrand_sched_t *sched, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Measurement                                                              */
 /* ------------------------------------------------------------------------ */
 /* Per-kernel-family totals collected between sogrand_profile_begin and

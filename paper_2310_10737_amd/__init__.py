@@ -11,8 +11,8 @@ import ctypes
 import os
 
 __all__ = [
-    "SograndError", "Code", "params", "lib", "library_path", "profile_begin", "profile_end",
-    "sogrand_decode_component", "sogrand_decode_product",
+    "SograndError", "Code", "params", "sched", "lib", "library_path", "profile_begin", "profile_end",
+    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_batched", "pack_frames",
     "SOGRAND_F64", "SOGRAND_F32",
 ]
 
@@ -27,6 +27,7 @@ EXPORTS = [
     "sogrand_last_error", "sogrand_version", "sogrand_params_default",
     "sogrand_code_create", "sogrand_code_create_ebch", "sogrand_code_info", "sogrand_code_destroy",
     "sogrand_decode_component", "sogrand_decode_product",
+    "sogrand_sched_default", "sogrand_decode_batched",
     "sogrand_profile_begin", "sogrand_profile_end",
 ]
 
@@ -46,6 +47,15 @@ class sogrand_kernel_stat_t(ctypes.Structure):
         ("queries", ctypes.c_uint64),
         ("ranks", ctypes.c_uint64),
         ("exact_rank", ctypes.c_uint64),
+    ]
+
+
+class sogrand_sched_t(ctypes.Structure):
+    _fields_ = [
+        ("waves_per_group", ctypes.c_int),
+        ("frames_per_group", ctypes.c_int),
+        ("steal_chunk", ctypes.c_int),
+        ("groups_per_cu", ctypes.c_int),
     ]
 
 
@@ -83,6 +93,9 @@ def lib():
     L.sogrand_code_destroy.restype = None
     L.sogrand_decode_component.argtypes = [P, P, SZ] + [P] * 11
     L.sogrand_decode_product.argtypes = [P, P, SZ] + [P] * 8
+    L.sogrand_sched_default.argtypes = [P]
+    L.sogrand_sched_default.restype = None
+    L.sogrand_decode_batched.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 9
     L.sogrand_profile_begin.argtypes = [I]
     L.sogrand_profile_end.argtypes = [P, I, P]
     for name in EXPORTS:
@@ -238,4 +251,63 @@ def sogrand_decode_product(code: Code, llr_ch, list_max=4, query_cap=1000, max_i
         code.handle, ctypes.byref(p), F, _ptr(llr_ch), _ptr(out["hard"]), _ptr(out["llr_app"]),
         _ptr(out["success"]), _ptr(out["half_iters"]), _ptr(out["sum_queries"]),
         _ptr(out["sum_max_queries"]), _stream(stream)))
+    return out
+
+
+def sched(waves_per_group=None, frames_per_group=None, steal_chunk=None, groups_per_cu=None):
+    """Launch shape of the batched kernel; unspecified fields take the library default."""
+    sc = sogrand_sched_t()
+    lib().sogrand_sched_default(ctypes.byref(sc))
+    for k, v in (("waves_per_group", waves_per_group), ("frames_per_group", frames_per_group),
+                 ("steal_chunk", steal_chunk), ("groups_per_cu", groups_per_cu)):
+        if v is not None:
+            setattr(sc, k, int(v))
+    return sc
+
+
+def pack_frames(frames):
+    """Packs a list of (n, n) LLR tensors into one flat tensor plus element offsets (int64)."""
+    import torch
+    sizes = [f.numel() for f in frames]
+    offs = [0]
+    for z in sizes[:-1]:
+        offs.append(offs[-1] + z)
+    flat = torch.cat([f.reshape(-1) for f in frames])
+    return flat, torch.tensor(offs, dtype=torch.int64, device=flat.device)
+
+
+def sogrand_decode_batched(codes, frame_code, frame_offset, llr, list_max=4, query_cap=1000, max_iter=4,
+                           alpha=0.5, early_stop=True, sched_=None, outputs=None, stream=None):
+    """Batched decode of product frames of mixed codes in one persistent launch.
+
+    codes: list of Code; frame_code: (F,) uint8 CUDA tensor of indices into codes;
+    frame_offset: (F,) int64 CUDA tensor of element offsets into llr (flat CUDA
+    tensor, float64 or float32).  Returns a dict with hard (flat uint8 like llr),
+    success, half_iters, sum_queries, sum_max_queries and status.
+    """
+    import torch
+    if not (llr.is_cuda and llr.is_contiguous() and llr.dim() == 1):
+        raise ValueError("llr must be a contiguous 1-D CUDA tensor")
+    F = frame_code.shape[0]
+    if frame_offset.shape[0] != F or frame_code.dtype != torch.uint8 or frame_offset.dtype != torch.int64:
+        raise ValueError("frame_code must be uint8 and frame_offset int64, one per frame")
+    dev = llr.device
+    out = dict(
+        hard=torch.empty(llr.shape, dtype=torch.uint8, device=dev),
+        success=torch.empty(F, dtype=torch.uint8, device=dev),
+        half_iters=torch.empty(F, dtype=torch.int16, device=dev),
+        sum_queries=torch.empty(F, dtype=torch.int64, device=dev),
+        sum_max_queries=torch.empty(F, dtype=torch.int64, device=dev),
+        status=torch.zeros(1, dtype=torch.int32, device=dev),
+    )
+    if outputs:
+        out.update(outputs)
+    handles = (ctypes.c_void_p * len(codes))(*[c.handle for c in codes])
+    p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
+               early_stop=early_stop, precision=_precision_of(llr))
+    sc = sched_ if sched_ is not None else sched()
+    _check(lib().sogrand_decode_batched(
+        handles, len(codes), ctypes.byref(p), F, _ptr(frame_code), _ptr(frame_offset), llr.numel(),
+        _ptr(llr), _ptr(out["hard"]), _ptr(out["success"]), _ptr(out["half_iters"]), _ptr(out["sum_queries"]),
+        _ptr(out["sum_max_queries"]), _ptr(out["status"]), ctypes.byref(sc), _stream(stream)))
     return out

@@ -1,0 +1,402 @@
+// Batched block-turbo decoding of product frames of mixed codes in one
+// persistent launch.
+//
+// Each workgroup owns up to `slots` frames at a time (frame slots in LDS).  Its
+// waves steal ranges of `chunk` lines of the current half-iteration of any of
+// those frames through LDS atomics, decode them (one wave per line, as in the
+// plain path), and report.  The wave that finishes the last line of a half
+// tests the hard decision (every row and column a codeword, section "Iterative
+// decoding"), then either opens the next half-iteration or writes the frame's
+// results and refills the slot from one global frame counter.  All
+// coordination is workgroup-local, so no cache maintenance across XCDs is
+// needed; frames are independent, so the result of a frame does not depend on
+// the schedule.
+#include "word.hpp"
+
+namespace sg {
+
+constexpr int kMaxCodes = 8;
+constexpr int kMaxSlots = 8;
+constexpr uint32_t kSpinLimit = 1u << 26;   // idle scans before a wave reports a stall
+
+struct BatchArgs {
+    DevCode codes[kMaxCodes];
+    int ncodes;
+    int L;
+    uint32_t qcap;
+    double alpha;
+    int max_iter;
+    int early_stop;
+    uint32_t nframes;
+    const uint8_t *frame_code;      // [F]
+    const uint64_t *frame_offset;   // [F] element offset of the frame's n x n block
+    uint64_t llr_len;               // elements of llr_ch / hard
+    const void *llr_ch;
+    uint8_t *hard;
+    uint8_t *success;
+    uint16_t *half_iters;
+    uint64_t *sumq;
+    uint64_t *summax;
+    void *la;                       // [grid][slots][nmax * nmax]
+    int nmax;
+    int slots;
+    int chunk;
+    uint32_t *next_frame;           // global frame counter
+    uint32_t *error;                // bit 0: a wave stopped waiting; bit 1: a frame descriptor was invalid
+    uint32_t *status;               // caller's copy of the error bits, or NULL
+    ProfCounters *prof;
+};
+
+struct SlotLds {
+    uint64_t masks[SOGRAND_NMAX][2];   // hard decision of each line of the current half
+    unsigned long long sumq, summax;
+    // claim word: generation (bits 63..40), lines of the half n (39..32) and the next
+    // unclaimed line (31..0).  A claim and the n it is judged against come from one
+    // atomic; the generation changes whenever the slot opens a new half-iteration.
+    unsigned long long ctl;
+    int frame;       // frame index; -1: no frame left (retired)
+    int code;
+    int n;
+    int h;           // current half-iteration, 1 .. 2 max_iter
+    int done;        // lines of this half finished
+    unsigned int halfmax;
+};
+
+__device__ __forceinline__ unsigned long long ctl_word(unsigned long long gen, int n) {
+    return (gen << 40) | ((unsigned long long)(n & 0xff) << 32);
+}
+
+__device__ __forceinline__ int lds_load(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_store(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ unsigned long long lds_load64(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Opens the slot's next half-iteration (or retires it) after its fields are set.
+__device__ __forceinline__ void slot_publish(SlotLds &sl) {
+    const unsigned long long gen = (sl.ctl >> 40) + 1;
+    const int n = sl.frame >= 0 ? sl.n : 0;
+    __hip_atomic_store(&sl.ctl, ctl_word(gen, n), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Takes the next frame for slot `sl` (single lane).  Invalid descriptors are
+// reported and the frame is skipped with success 0 and zero half-iterations.
+__device__ void slot_refill(const BatchArgs &a, SlotLds &sl) {
+    for (;;) {
+        const uint32_t f = atomicAdd(a.next_frame, 1u);
+        if (f >= a.nframes) {
+            sl.frame = -1;
+            return;
+        }
+        const int code = a.frame_code[f];
+        const int n = code < a.ncodes ? a.codes[code].n : 0;
+        const uint64_t off = a.frame_offset[f];
+        if (code >= a.ncodes || off > a.llr_len || a.llr_len - off < (uint64_t)n * n) {
+            atomicOr(a.error, 2u);
+            a.success[f] = 0;
+            if (a.half_iters) a.half_iters[f] = 0;
+            if (a.sumq) a.sumq[f] = 0;
+            if (a.summax) a.summax[f] = 0;
+            continue;
+        }
+        sl.frame = (int)f;
+        sl.code = code;
+        sl.n = n;
+        sl.h = 1;
+        sl.done = 0;
+        sl.halfmax = 0;
+        sl.sumq = 0;
+        sl.summax = 0;
+        return;
+    }
+}
+
+// Validity of the frame's hard decision after a half-iteration: every line of
+// the last pass and every cross line has a zero syndrome.
+__device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, int lane) {
+    const int n = sl.n;
+    bool bad = false;
+    for (int b = 0; b < 2; b++) {
+        const int x = lane + kWave * b;
+        if (x >= n) continue;
+        const uint64_t m0 = sl.masks[x][0], m1 = sl.masks[x][1];
+        uint32_t s = 0;
+        for (int i = 0; i < n; i++) {
+            const uint64_t bit = i < 64 ? (m0 >> i) & 1ull : (m1 >> (i - 64)) & 1ull;
+            if (bit) s ^= c.hcol[i];
+        }
+        uint32_t t = 0;
+        for (int l = 0; l < n; l++) {
+            const uint64_t w = x < 64 ? sl.masks[l][0] : sl.masks[l][1];
+            if ((w >> (x & 63)) & 1ull) t ^= c.hcol[l];
+        }
+        bad |= (s != 0u) || (t != 0u);
+    }
+    return __ballot(bad) == 0ull;
+}
+
+// Decodes line `line` of the slot's frame in half-iteration h (rows for odd h).
+template <typename T, int NS>
+__device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl, const DevCode &c, int frame,
+                                                int h, int line, T *la, WaveLds &S, int lane) {
+    constexpr int NB = Lanes<NS>::NB;
+    const int n = c.n;
+    const bool rows = (h & 1) != 0;
+    const uint64_t off = a.frame_offset[frame];
+    const T *ch = static_cast<const T *>(a.llr_ch) + off;
+    double lam[NB];
+    int pos[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int i = lane + kWave * b;
+        pos[b] = rows ? line * n + i : i * n + line;
+        // the a-priori LLRs are zero in the first half-iteration
+        lam[b] = i < n ? (double)ch[pos[b]] + (h > 1 ? (double)la[pos[b]] : 0.0) : 0.0;
+    }
+    double lapp[NB];
+    const WordStats st = decode_word<NS>(c, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    uint64_t hm[2] = {0ull, 0ull};
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int i = lane + kWave * b;
+        const bool v = i < n;
+        const bool neg = v && lapp[b] < 0.0;
+        hm[b] = __ballot(neg);
+        if (!v) continue;
+        la[pos[b]] = (T)(a.alpha * (lapp[b] - lam[b]));
+        a.hard[off + pos[b]] = neg;
+    }
+    if (lane == 0) {
+        sl.masks[line][0] = hm[0];
+        sl.masks[line][1] = hm[1];
+    }
+    return st;
+}
+
+template <typename T, int WPB>
+__global__ __launch_bounds__(kWave * WPB) void k_batched(BatchArgs a) {
+    __shared__ WaveLds wl[WPB];
+    extern __shared__ SlotLds slot_dyn[];
+    SlotLds *sls = slot_dyn;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = WPB == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    WaveLds &S = wl[wave];
+    const int nslots = a.slots;
+    if (threadIdx.x == 0)
+        for (int s = 0; s < nslots; s++) {
+            sls[s].ctl = 0ull;
+            slot_refill(a, sls[s]);
+            slot_publish(sls[s]);
+        }
+    __syncthreads();
+    T *la_base = static_cast<T *>(a.la) + (size_t)blockIdx.x * nslots * a.nmax * a.nmax;
+    uint32_t idle = 0;
+    int start = wave % nslots;
+    for (;;) {
+        // steal a range of lines from any slot with unclaimed lines
+        int sel = -1, first = 0;
+        bool live = false;
+        for (int k = 0; k < nslots; k++) {
+            const int s = (start + k) % nslots;
+            SlotLds &sl = sls[s];
+            if (lds_load(&sl.frame) < 0) continue;
+            live = true;
+            const unsigned long long c0 = lds_load64(&sl.ctl);
+            if ((uint32_t)c0 >= (uint32_t)((c0 >> 32) & 0xff)) continue;   // nothing left to claim
+            unsigned long long got = 0;
+            if (lane == 0)
+                got = __hip_atomic_fetch_add(&sl.ctl, (unsigned long long)a.chunk, __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
+            if (lo < (hi & 0xffu)) {
+                sel = s;
+                first = (int)lo;
+                break;
+            }
+        }
+        if (sel < 0) {
+            if (!live) break;
+            if (++idle > kSpinLimit) {
+                if (lane == 0) atomicOr(a.error, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        idle = 0;
+        start = sel;
+        SlotLds &sl = sls[sel];
+        // a valid claim sees the fields written before its generation was published
+        const int frame = __builtin_amdgcn_readfirstlane(lds_load(&sl.frame));
+        const int code = __builtin_amdgcn_readfirstlane(sl.code);
+        const int h = __builtin_amdgcn_readfirstlane(sl.h);
+        const DevCode &c = a.codes[code];
+        const int n = c.n;
+        const int last = first + a.chunk < n ? first + a.chunk : n;
+        T *la = la_base + (size_t)sel * a.nmax * a.nmax;
+        unsigned long long qsum = 0;
+        uint32_t qmax = 0;
+        for (int line = first; line < last; line++) {
+            WordStats st;
+            if (n <= 32) st = batch_line<T, 32>(a, sl, c, frame, h, line, la, S, lane);
+            else if (n <= 64) st = batch_line<T, 64>(a, sl, c, frame, h, line, la, S, lane);
+            else st = batch_line<T, 128>(a, sl, c, frame, h, line, la, S, lane);
+            if (a.prof && lane == 0) prof_add(a.prof, st);
+            qsum += st.Q;
+            qmax = st.Q > qmax ? st.Q : qmax;
+        }
+        // the lines' global writes complete before they are counted as done
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        int d = 0;
+        if (lane == 0) {
+            atomicAdd(&sl.sumq, qsum);
+            atomicMax(&sl.halfmax, qmax);
+            d = atomicAdd(&sl.done, last - first) + (last - first);
+        }
+        d = __builtin_amdgcn_readfirstlane(d);
+        if (d != n) continue;
+
+        // this wave finished the half-iteration
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const bool valid = slot_valid(sl, c, lane);
+        if (lane == 0) {
+            sl.summax += sl.halfmax;
+            sl.halfmax = 0;
+            if ((valid && a.early_stop) || h == 2 * a.max_iter) {
+                a.success[frame] = valid;
+                if (a.half_iters) a.half_iters[frame] = (uint16_t)h;
+                if (a.sumq) a.sumq[frame] = sl.sumq;
+                if (a.summax) a.summax[frame] = sl.summax;
+                slot_refill(a, sl);
+            } else {
+                sl.h = h + 1;
+                sl.done = 0;
+            }
+            slot_publish(sl);
+        }
+    }
+}
+
+__global__ void k_batched_init(uint32_t *counters) {
+    if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
+}
+
+__global__ void k_batched_status(const uint32_t *error, uint32_t *status) {
+    if (threadIdx.x == 0) *status = *error;
+}
+
+template <typename T, int WPB>
+static void launch_batched_w(const BatchArgs &a, int grid, hipStream_t st) {
+    const size_t dyn = sizeof(SlotLds) * a.slots;
+    hipLaunchKernelGGL((k_batched<T, WPB>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
+}
+
+template <typename T>
+static void launch_batched(const BatchArgs &a, int wpb, int grid, hipStream_t st) {
+    if (wpb == 4) launch_batched_w<T, 4>(a, grid, st);
+    else if (wpb == 8) launch_batched_w<T, 8>(a, grid, st);
+    else launch_batched_w<T, 16>(a, grid, st);
+}
+
+static int check_sched(const sogrand_sched_t *s) {
+    if (s->waves_per_group != 4 && s->waves_per_group != 8 && s->waves_per_group != 16)
+        return fail(SOGRAND_EINVAL, "waves_per_group must be 4, 8 or 16");
+    if (s->frames_per_group < 1 || s->frames_per_group > kMaxSlots)
+        return fail(SOGRAND_EINVAL, "frames_per_group outside 1..%d", kMaxSlots);
+    if (s->steal_chunk < 1 || s->steal_chunk > SOGRAND_NMAX) return fail(SOGRAND_EINVAL, "steal_chunk outside 1..128");
+    if (s->groups_per_cu < 1 || s->groups_per_cu > 64) return fail(SOGRAND_EINVAL, "groups_per_cu outside 1..64");
+    return SOGRAND_OK;
+}
+
+}  // namespace sg
+
+extern "C" {
+
+void sogrand_sched_default(sogrand_sched_t *s) {
+    if (!s) return;
+    s->waves_per_group = 8;
+    s->frames_per_group = 4;
+    s->steal_chunk = 1;
+    s->groups_per_cu = 2;
+}
+
+int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                           size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
+                           uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                           uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
+                           uint32_t *status, const sogrand_sched_t *sched, void *stream) {
+    using namespace sg;
+    SG_TRY(check_params(params));
+    if (!codes || ncodes < 1 || ncodes > kMaxCodes) return fail(SOGRAND_EINVAL, "ncodes outside 1..%d", kMaxCodes);
+    if (nframes == 0) return SOGRAND_OK;
+    if (nframes >= (1ull << 31)) return fail(SOGRAND_EINVAL, "nframes too large");
+    if (!frame_code || !frame_offset || !llr_ch || !hard || !success)
+        return fail(SOGRAND_EINVAL, "frame_code, frame_offset, llr_ch, hard and success are required");
+    sogrand_sched_t sc;
+    sogrand_sched_default(&sc);
+    if (sched) sc = *sched;
+    SG_TRY(check_sched(&sc));
+    BatchArgs a{};
+    int nmax = 0;
+    for (int i = 0; i < ncodes; i++) {
+        if (!codes[i]) return fail(SOGRAND_EINVAL, "codes[%d] is NULL", i);
+        SG_TRY(prepare_code(const_cast<sogrand_code_t *>(codes[i]), params->query_cap, &a.codes[i]));
+        nmax = codes[i]->n > nmax ? codes[i]->n : nmax;
+    }
+    int dev = 0, cus = 0;
+    SG_HIP(hipGetDevice(&dev));
+    SG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const size_t want = (nframes + sc.frames_per_group - 1) / sc.frames_per_group;
+    const size_t cap = (size_t)cus * sc.groups_per_cu;
+    const int grid = (int)(want < cap ? want : cap);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t esz = params->precision == SOGRAND_F64 ? sizeof(double) : sizeof(float);
+    const size_t la_bytes = (size_t)grid * sc.frames_per_group * nmax * nmax * esz;
+    char *ws = nullptr;
+    const size_t total = 256 + la_bytes;
+    if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
+        return fail(SOGRAND_ENOMEM, "work buffer allocation of %zu bytes failed", total);
+    a.ncodes = ncodes;
+    a.L = params->list_max;
+    a.qcap = params->query_cap;
+    a.alpha = params->alpha;
+    a.max_iter = params->max_iter;
+    a.early_stop = params->early_stop ? 1 : 0;
+    a.nframes = (uint32_t)nframes;
+    a.frame_code = frame_code;
+    a.frame_offset = frame_offset;
+    a.llr_len = llr_len;
+    a.llr_ch = llr_ch;
+    a.hard = hard;
+    a.success = success;
+    a.half_iters = half_iters;
+    a.sumq = sum_queries;
+    a.summax = sum_max_queries;
+    a.la = ws + 256;
+    a.nmax = nmax;
+    a.slots = sc.frames_per_group;
+    a.chunk = sc.steal_chunk;
+    a.next_frame = reinterpret_cast<uint32_t *>(ws);
+    a.error = reinterpret_cast<uint32_t *>(ws) + 1;
+    a.prof = prof_counters(PK_BATCHED);
+    hipLaunchKernelGGL(k_batched_init, dim3(1), dim3(64), 0, st, a.next_frame);
+    const int tok = prof_start(PK_BATCHED, st);
+    if (params->precision == SOGRAND_F64) launch_batched<double>(a, sc.waves_per_group, grid, st);
+    else launch_batched<float>(a, sc.waves_per_group, grid, st);
+    prof_stop(tok, st);
+    a.status = status;
+    if (status) hipLaunchKernelGGL(k_batched_status, dim3(1), dim3(64), 0, st, a.error, status);
+    int rc = SOGRAND_OK;
+    if (hipGetLastError() != hipSuccess) rc = fail(SOGRAND_EDEVICE, "batched kernel launch failed");
+    (void)hipFreeAsync(ws, st);
+    return rc;
+}
+
+}  // extern "C"

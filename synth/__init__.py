@@ -424,3 +424,37 @@ def component_words(code: Code, ebn0_db, seed: int, word_ids, batch: int = 1 << 
         cw[s:s + batch] = c
         info[s:s + batch] = u
     return llr, cw, info
+
+
+def mixed_product_frames(codes, ebn0_lo: float, ebn0_hi: float, seed: int, frame_ids):
+    """Product frames whose code and Eb/N0 are drawn per frame.
+
+    Frame f takes code index floor(u0 * len(codes)) and Eb/N0 = lo + (hi - lo) u1,
+    with (u0, u1) the first two outputs of stream 2 of (seed, f) mapped to [0, 1)
+    by (o >> 11) 2^-53; its bits and noise are those of product_frames(code, ...,
+    seed, [f]).  Returns (code_idx (F,) uint8, ebn0 (F,), offsets (F,) int64,
+    llr flat float64, codewords flat uint8), frames packed row-major one after the
+    other.
+    """
+    frame_ids = np.asarray(frame_ids, dtype=np.uint64)
+    F = frame_ids.shape[0]
+    u = (splitmix_stream(seed, frame_ids, 2, 2) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    cidx = np.minimum((u[:, 0] * len(codes)).astype(np.int64), len(codes) - 1).astype(np.uint8)
+    ebn0 = ebn0_lo + (ebn0_hi - ebn0_lo) * u[:, 1]
+    sizes = np.array([codes[c].n ** 2 for c in cidx], dtype=np.int64)
+    offsets = np.zeros(F, dtype=np.int64)
+    if F:
+        offsets[1:] = np.cumsum(sizes)[:-1]
+    total = int(sizes.sum())
+    llr = np.empty(total, dtype=np.float64)
+    cw = np.empty(total, dtype=np.uint8)
+    for c, code in enumerate(codes):
+        sel = np.nonzero(cidx == c)[0]
+        if sel.size == 0:
+            continue
+        l, w, _ = product_frames(code, ebn0[sel], seed, frame_ids[sel])
+        nn = code.n * code.n
+        idx = offsets[sel][:, None] + np.arange(nn)[None, :]
+        llr[idx] = l.reshape(-1, nn)
+        cw[idx] = w.reshape(-1, nn)
+    return cidx, ebn0, offsets, llr, cw

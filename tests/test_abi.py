@@ -116,3 +116,31 @@ def test_decode_rejects_null_buffers_and_accepts_empty_batches(sg):
     assert L.sogrand_decode_product(code.handle, ctypes.byref(p), 3, ctypes.c_void_p(1), None, None,
                                     ctypes.c_void_p(1), None, None, None, None) == -1
     assert L.sogrand_decode_component(None, ctypes.byref(p), 1, ctypes.c_void_p(1), *([None] * 9), None) == -1
+
+
+def test_batched_rejects_bad_arguments_before_device_work(sg):
+    code = sg.Code.ebch(32, 26)
+    L = sg.lib()
+    p = sg.params()
+    one = (ctypes.c_void_p * 1)(code.handle)
+    sc = sg.sched()
+    args = [one, 1, ctypes.byref(p), 4, ctypes.c_void_p(1), ctypes.c_void_p(1), 4096, ctypes.c_void_p(1),
+            ctypes.c_void_p(1), ctypes.c_void_p(1), None, None, None, None, ctypes.byref(sc), None]
+    bad_ncodes = list(args)
+    bad_ncodes[1] = 0
+    assert L.sogrand_decode_batched(*bad_ncodes) == -1
+    bad_ncodes[1] = 9
+    assert L.sogrand_decode_batched(*bad_ncodes) == -1
+    no_success = list(args)
+    no_success[9] = None
+    assert L.sogrand_decode_batched(*no_success) == -1
+    for field, value in (("waves_per_group", 5), ("frames_per_group", 0), ("frames_per_group", 9),
+                         ("steal_chunk", 0), ("groups_per_cu", 0)):
+        bad = sg.sched()
+        setattr(bad, field, value)
+        a = list(args)
+        a[14] = ctypes.byref(bad)
+        assert L.sogrand_decode_batched(*a) == -1, field
+    empty = list(args)
+    empty[3] = 0
+    assert L.sogrand_decode_batched(*empty) == 0

@@ -1,0 +1,136 @@
+"""Batched persistent decoding of mixed-code product frames: identical per-frame results to the
+plain path, parity with the oracle on a sample, independence of the launch shape, and the
+handling of invalid frame descriptors."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+NK = [(32, 26), (64, 57), (128, 120)]
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2310_10737_amd as sg
+    sg.lib()
+    return sg
+
+
+def mixed(F, seed, lo=2.0, hi=4.0, nks=NK):
+    codes = [synth.ebch(*nk) for nk in nks]
+    cidx, eb, offs, llr, cw = synth.mixed_product_frames(codes, lo, hi, seed, np.arange(F))
+    return codes, cidx, eb, offs, llr, cw
+
+
+def run_batched(sg, codes, cidx, offs, llr, f32=False, sched=None, L=4, qcap=10000, iters=6):
+    import torch
+    gcodes = [sg.Code.ebch(c.n, c.k) for c in codes]
+    dt = torch.float32 if f32 else torch.float64
+    x = torch.from_numpy(llr).to(dtype=dt, device="cuda")
+    fc = torch.from_numpy(cidx).cuda()
+    fo = torch.from_numpy(offs).cuda()
+    out = sg.sogrand_decode_batched(gcodes, fc, fo, x, list_max=L, query_cap=qcap, max_iter=iters, sched_=sched)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def run_plain_per_code(sg, codes, cidx, offs, llr, f32=False, L=4, qcap=10000, iters=6):
+    import torch
+    F = cidx.shape[0]
+    res = dict(success=np.zeros(F, np.uint8), half_iters=np.zeros(F, np.int64), sum_queries=np.zeros(F, np.int64),
+               sum_max_queries=np.zeros(F, np.int64), hard=np.zeros(llr.shape, np.uint8))
+    dt = torch.float32 if f32 else torch.float64
+    for c, code in enumerate(codes):
+        sel = np.nonzero(cidx == c)[0]
+        if sel.size == 0:
+            continue
+        nn = code.n * code.n
+        frames = np.stack([llr[o:o + nn] for o in offs[sel]]).reshape(-1, code.n, code.n)
+        g = sg.Code.ebch(code.n, code.k)
+        out = sg.sogrand_decode_product(g, torch.from_numpy(frames).to(dtype=dt, device="cuda"), list_max=L,
+                                        query_cap=qcap, max_iter=iters)
+        torch.cuda.synchronize()
+        for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
+            res[key][sel] = out[key].cpu().numpy()
+        hard = out["hard"].cpu().numpy().reshape(-1, nn)
+        for j, o in enumerate(offs[sel]):
+            res["hard"][o:o + nn] = hard[j]
+    return res
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_batched_equals_plain_per_frame(sg, f32):
+    codes, cidx, eb, offs, llr, cw = mixed(600, seed=4)
+    print(f"[gpu] batched vs plain, 600 mixed frames, f32={f32}", flush=True)
+    b = run_batched(sg, codes, cidx, offs, llr, f32=f32)
+    p = run_plain_per_code(sg, codes, cidx, offs, llr, f32=f32)
+    assert int(b["status"][0]) == 0
+    for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
+        np.testing.assert_array_equal(b[key].astype(np.int64), p[key].astype(np.int64), err_msg=key)
+    np.testing.assert_array_equal(b["hard"], p["hard"])
+
+
+def test_batched_matches_oracle_on_sample(sg):
+    codes, cidx, eb, offs, llr, cw = mixed(240, seed=7, lo=2.5, hi=3.5)
+    b = run_batched(sg, codes, cidx, offs, llr, qcap=3000, iters=4)
+    rng = np.random.default_rng(3)
+    for c, code in enumerate(codes):
+        sel = np.nonzero(cidx == c)[0]
+        pick = rng.choice(sel, size=min(6, sel.size), replace=False)
+        nn = code.n * code.n
+        frames = np.stack([llr[o:o + nn] for o in offs[pick]]).reshape(-1, code.n, code.n)
+        r = oracle.decode_product(code, frames, 4, 3000, 4, nthreads=8)
+        for j, f in enumerate(pick):
+            o = offs[f]
+            assert b["success"][f] == r["success"][j]
+            assert int(b["half_iters"][f]) == int(r["half_iters"][j])
+            assert int(b["sum_queries"][f]) == int(r["sum_queries"][j])
+            assert int(b["sum_max_queries"][f]) == int(r["sum_max_queries"][j])
+            np.testing.assert_array_equal(b["hard"][o:o + nn], r["hard"][j].reshape(-1))
+
+
+def test_batched_result_independent_of_launch_shape(sg):
+    codes, cidx, eb, offs, llr, cw = mixed(300, seed=9)
+    ref = None
+    for w, fpg, ch, gpc in [(8, 4, 1, 2), (4, 1, 1, 1), (16, 8, 3, 1), (4, 2, 64, 4), (8, 3, 2, 3)]:
+        print(f"[gpu] batched shape w={w} f={fpg} chunk={ch} gpc={gpc}", flush=True)
+        out = run_batched(sg, codes, cidx, offs, llr, f32=True, sched=sg.sched(w, fpg, ch, gpc))
+        assert int(out["status"][0]) == 0
+        if ref is None:
+            ref = out
+            continue
+        for key in ("success", "half_iters", "sum_queries", "sum_max_queries", "hard"):
+            np.testing.assert_array_equal(out[key], ref[key], err_msg=key)
+
+
+def test_batched_skips_invalid_descriptors(sg):
+    import torch
+    codes, cidx, eb, offs, llr, cw = mixed(40, seed=11)
+    cidx = cidx.copy()
+    offs = offs.copy()
+    cidx[5] = 7                      # no such code
+    offs[9] = llr.shape[0] - 10      # block runs past the buffer
+    out = run_batched(sg, codes, cidx, offs, llr, f32=True, qcap=1000, iters=2)
+    assert int(out["status"][0]) & 2
+    assert out["success"][5] == 0 and out["half_iters"][5] == 0
+    assert out["success"][9] == 0 and out["half_iters"][9] == 0
+    good = np.ones(40, bool)
+    good[[5, 9]] = False
+    assert np.all(out["half_iters"][good] >= 1)
+
+
+def test_batched_single_frame_and_empty(sg):
+    codes, cidx, eb, offs, llr, cw = mixed(1, seed=12)
+    b = run_batched(sg, codes, cidx, offs, llr)
+    p = run_plain_per_code(sg, codes, cidx, offs, llr)
+    np.testing.assert_array_equal(b["hard"], p["hard"])
