@@ -56,7 +56,9 @@ def main() -> int:
     ap.add_argument("--frames", type=int, default=10000, help="frames per Eb/N0")
     ap.add_argument("--cpu-frames", type=int, default=600, help="oracle sample: frames per Eb/N0")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="plain_f64,plain_f32")
+    ap.add_argument("--forms", default="plain_f64,plain_f32,batched_f64,batched_f32")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick the batched launch shape by timing a few candidates on a sample first")
     ap.add_argument("--no-count", action="store_true",
                     help="skip the work-counting run (for profiler runs that average kernel durations)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -101,6 +103,32 @@ def main() -> int:
     def run_plain(x, out):
         sg.sogrand_decode_product(gcode, x, list_max=L, query_cap=QCAP, max_iter=ITERS, outputs=out)
 
+    fcode = torch.zeros(total, dtype=torch.uint8, device=dev)
+    foff = torch.arange(total, dtype=torch.int64, device=dev) * (N * N)
+    shape = sg.sched()
+
+    def run_batched(x, out, sc):
+        sg.sogrand_decode_batched([gcode], fcode, foff, x.view(-1), list_max=L, query_cap=QCAP, max_iter=ITERS,
+                                  sched_=sc, outputs=out)
+
+    def tune(x):
+        """Times candidate launch shapes on the first 3000 frames; returns the fastest."""
+        m = min(3000, total)
+        xs = x[:m].contiguous().view(-1)
+        fc, fo = fcode[:m], foff[:m]
+        best = None
+        for w, f, ch, g in [(16, 2, 1, 1), (8, 2, 1, 4), (8, 4, 1, 2), (4, 2, 1, 8), (16, 4, 1, 1), (16, 1, 1, 1)]:
+            sc = sg.sched(w, f, ch, g)
+            sg.sogrand_decode_batched([gcode], fc, fo, xs, L, QCAP, ITERS, sched_=sc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sg.sogrand_decode_batched([gcode], fc, fo, xs, L, QCAP, ITERS, sched_=sc)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, sc)
+        return best[1]
+
     forms = {}
     for form in args.forms.split(","):
         if form == "plain_f64":
@@ -109,6 +137,13 @@ def main() -> int:
         elif form == "plain_f32":
             x, out = x32, outputs(torch.float32)
             step = lambda: run_plain(x32, out)  # noqa: E731
+        elif form in ("batched_f64", "batched_f32"):
+            x = x64 if form == "batched_f64" else x32
+            out = outputs(x.dtype)
+            out["hard"] = out["hard"].view(-1)
+            out["status"] = torch.zeros(1, dtype=torch.int32, device=dev)
+            sc = tune(x) if args.tune else shape
+            step = lambda: run_batched(x, out, sc)  # noqa: E731
         else:
             raise SystemExit(f"unknown form {form}")
         for _ in range(args.warmup):
@@ -130,7 +165,9 @@ def main() -> int:
         t1 = time.perf_counter()
         kern = sg.profile_end()
         ms = (t1 - t0) * 1e3 / args.steps
-        err = torch.any((out["hard"] != cw_all).view(total, -1), dim=1).cpu().numpy()
+        if "status" in out and int(out["status"].item()) != 0:
+            raise SystemExit(f"{form}: batched kernel reported status {int(out['status'].item())}")
+        err = torch.any((out["hard"].view(total, N, N) != cw_all).view(total, -1), dim=1).cpu().numpy()
         hi = out["half_iters"].double().cpu().numpy()
         sq = out["sum_queries"].double().cpu().numpy()
         smq = out["sum_max_queries"].double().cpu().numpy()
@@ -144,6 +181,9 @@ def main() -> int:
                 parallel_queries_per_bit=float(smq[sl].mean() / (N * N)))
         forms[form] = dict(ms_per_step=ms, info_bits_per_s=info_bits_per_step / (ms / 1e3),
                            per_snr=per_snr, kernels=kern, work=work)
+        if form.startswith("batched"):
+            forms[form]["sched"] = dict(waves_per_group=sc.waves_per_group, frames_per_group=sc.frames_per_group,
+                                        steal_chunk=sc.steal_chunk, groups_per_cu=sc.groups_per_cu)
 
     # matched BLER: every Eb/N0 inside the plain binary64 form's 95% interval
     base = forms.get("plain_f64")
@@ -159,9 +199,11 @@ def main() -> int:
         if ok and (best is None or f["info_bits_per_s"] > best["info_bits_per_s"]):
             best_name, best = name, f
 
-    # roofline of the dominant kernel: the row/column pass kernel of the chosen form
-    kp = best["kernels"].get("product_pass", {})
-    wk = best["work"].get("product_pass", {})
+    # roofline of the dominant kernel of the chosen form: the row/column pass kernel of the
+    # plain forms, the persistent kernel of the batched forms
+    kname = "batched" if best_name.startswith("batched") else "product_pass"
+    kp = best["kernels"].get(kname, {})
+    wk = best["work"].get(kname, {})
     roof = None
     if kp.get("launches") and wk:
         avg_ms = kp["total_ms"] / kp["launches"]
@@ -171,7 +213,8 @@ def main() -> int:
         achieved = ops_launch / (avg_ms / 1e3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_ALU_TOPS, unit="Top/s",
                     frac=achieved / PEAK_ALU_TOPS, traffic=None,
-                    kernel="k_product_pass (row and column instantiations)",
+                    kernel="k_batched (persistent)" if kname == "batched" else
+                    "k_product_pass (row and column instantiations)",
                     avg_launch_ms=avg_ms, ops_per_launch=ops_launch,
                     words_per_step=wk["words"], queries_per_step=wk["queries"],
                     ranks_per_step=wk["ranks"], exact_rank_words_per_step=wk.get("exact_rank"))

@@ -19,8 +19,12 @@ constexpr int kMaxCodes = 8;
 constexpr int kMaxSlots = 8;
 constexpr uint32_t kSpinLimit = 1u << 26;   // idle scans before a wave reports a stall
 
-struct BatchArgs {
+struct CodeTable {
     DevCode codes[kMaxCodes];
+};
+
+struct BatchArgs {
+    const DevCode *codes;           // [ncodes], in device memory
     int ncodes;
     int L;
     uint32_t qcap;
@@ -179,8 +183,11 @@ __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl,
     return st;
 }
 
-template <typename T, int WPB>
-__global__ __launch_bounds__(kWave * WPB) void k_batched(BatchArgs a) {
+// NSMAX: the largest word width of the batch's codes (32, 64 or 128); narrower
+// batches compile without the wide-word path and keep more waves resident.
+template <typename T, int WPB, int NSMAX>
+__global__ __launch_bounds__(kWave * WPB)
+void k_batched(BatchArgs a) {
     __shared__ WaveLds wl[WPB];
     extern __shared__ SlotLds slot_dyn[];
     SlotLds *sls = slot_dyn;
@@ -245,8 +252,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_batched(BatchArgs a) {
         uint32_t qmax = 0;
         for (int line = first; line < last; line++) {
             WordStats st;
-            if (n <= 32) st = batch_line<T, 32>(a, sl, c, frame, h, line, la, S, lane);
-            else if (n <= 64) st = batch_line<T, 64>(a, sl, c, frame, h, line, la, S, lane);
+            if (NSMAX == 32 || n <= 32) st = batch_line<T, 32>(a, sl, c, frame, h, line, la, S, lane);
+            else if (NSMAX == 64 || n <= 64) st = batch_line<T, (NSMAX > 64 ? 64 : NSMAX)>(a, sl, c, frame, h, line, la, S, lane);
             else st = batch_line<T, 128>(a, sl, c, frame, h, line, la, S, lane);
             if (a.prof && lane == 0) prof_add(a.prof, st);
             qsum += st.Q;
@@ -284,25 +291,35 @@ __global__ __launch_bounds__(kWave * WPB) void k_batched(BatchArgs a) {
     }
 }
 
-__global__ void k_batched_init(uint32_t *counters) {
+// Zeroes the frame counter and error bits and stores the code table where the
+// persistent kernel reads it.
+__global__ void k_batched_init(uint32_t *counters, CodeTable table, DevCode *dst, int ncodes) {
     if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
+    if (threadIdx.x < (unsigned)ncodes) dst[threadIdx.x] = table.codes[threadIdx.x];
 }
 
 __global__ void k_batched_status(const uint32_t *error, uint32_t *status) {
     if (threadIdx.x == 0) *status = *error;
 }
 
-template <typename T, int WPB>
+template <typename T, int WPB, int NSMAX>
 static void launch_batched_w(const BatchArgs &a, int grid, hipStream_t st) {
     const size_t dyn = sizeof(SlotLds) * a.slots;
-    hipLaunchKernelGGL((k_batched<T, WPB>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
+    hipLaunchKernelGGL((k_batched<T, WPB, NSMAX>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
+}
+
+template <typename T, int NSMAX>
+static void launch_batched_n(const BatchArgs &a, int wpb, int grid, hipStream_t st) {
+    if (wpb == 4) launch_batched_w<T, 4, NSMAX>(a, grid, st);
+    else if (wpb == 8) launch_batched_w<T, 8, NSMAX>(a, grid, st);
+    else launch_batched_w<T, 16, NSMAX>(a, grid, st);
 }
 
 template <typename T>
 static void launch_batched(const BatchArgs &a, int wpb, int grid, hipStream_t st) {
-    if (wpb == 4) launch_batched_w<T, 4>(a, grid, st);
-    else if (wpb == 8) launch_batched_w<T, 8>(a, grid, st);
-    else launch_batched_w<T, 16>(a, grid, st);
+    if (a.nmax <= 32) launch_batched_n<T, 32>(a, wpb, grid, st);
+    else if (a.nmax <= 64) launch_batched_n<T, 64>(a, wpb, grid, st);
+    else launch_batched_n<T, 128>(a, wpb, grid, st);
 }
 
 static int check_sched(const sogrand_sched_t *s) {
@@ -321,10 +338,10 @@ extern "C" {
 
 void sogrand_sched_default(sogrand_sched_t *s) {
     if (!s) return;
-    s->waves_per_group = 8;
-    s->frames_per_group = 4;
+    s->waves_per_group = 16;
+    s->frames_per_group = 2;
     s->steal_chunk = 1;
-    s->groups_per_cu = 2;
+    s->groups_per_cu = 1;
 }
 
 int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
@@ -344,10 +361,11 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
     if (sched) sc = *sched;
     SG_TRY(check_sched(&sc));
     BatchArgs a{};
+    CodeTable table{};
     int nmax = 0;
     for (int i = 0; i < ncodes; i++) {
         if (!codes[i]) return fail(SOGRAND_EINVAL, "codes[%d] is NULL", i);
-        SG_TRY(prepare_code(const_cast<sogrand_code_t *>(codes[i]), params->query_cap, &a.codes[i]));
+        SG_TRY(prepare_code(const_cast<sogrand_code_t *>(codes[i]), params->query_cap, &table.codes[i]));
         nmax = codes[i]->n > nmax ? codes[i]->n : nmax;
     }
     int dev = 0, cus = 0;
@@ -360,7 +378,8 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
     const size_t esz = params->precision == SOGRAND_F64 ? sizeof(double) : sizeof(float);
     const size_t la_bytes = (size_t)grid * sc.frames_per_group * nmax * nmax * esz;
     char *ws = nullptr;
-    const size_t total = 256 + la_bytes;
+    const size_t head = 256 + ((sizeof(DevCode) * kMaxCodes + 255) & ~(size_t)255);
+    const size_t total = head + la_bytes;
     if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
         return fail(SOGRAND_ENOMEM, "work buffer allocation of %zu bytes failed", total);
     a.ncodes = ncodes;
@@ -379,14 +398,16 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
     a.half_iters = half_iters;
     a.sumq = sum_queries;
     a.summax = sum_max_queries;
-    a.la = ws + 256;
+    a.codes = reinterpret_cast<const DevCode *>(ws + 256);
+    a.la = ws + head;
     a.nmax = nmax;
     a.slots = sc.frames_per_group;
     a.chunk = sc.steal_chunk;
     a.next_frame = reinterpret_cast<uint32_t *>(ws);
     a.error = reinterpret_cast<uint32_t *>(ws) + 1;
     a.prof = prof_counters(PK_BATCHED);
-    hipLaunchKernelGGL(k_batched_init, dim3(1), dim3(64), 0, st, a.next_frame);
+    hipLaunchKernelGGL(k_batched_init, dim3(1), dim3(64), 0, st, a.next_frame, table,
+                       reinterpret_cast<DevCode *>(ws + 256), ncodes);
     const int tok = prof_start(PK_BATCHED, st);
     if (params->precision == SOGRAND_F64) launch_batched<double>(a, sc.waves_per_group, grid, st);
     else launch_batched<float>(a, sc.waves_per_group, grid, st);
