@@ -54,7 +54,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--frames", type=int, default=10000, help="frames per Eb/N0")
-    ap.add_argument("--cpu-frames", type=int, default=600, help="oracle sample: frames per Eb/N0")
+    ap.add_argument("--cpu-frames", type=int, default=10000, help="oracle sample: frames per Eb/N0")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="plain_f64,plain_f32,batched_f64,batched_f32")
     ap.add_argument("--tune", action="store_true",
@@ -117,7 +117,7 @@ def main() -> int:
         xs = x[:m].contiguous().view(-1)
         fc, fo = fcode[:m], foff[:m]
         best = None
-        for w, f, ch, g in [(16, 2, 1, 1), (8, 2, 1, 4), (8, 4, 1, 2), (4, 2, 1, 8), (16, 4, 1, 1), (16, 1, 1, 1)]:
+        for w, f, ch, g in [(8, 2, 1, 3), (4, 2, 1, 6), (8, 3, 1, 3), (4, 2, 1, 8), (8, 2, 2, 3), (4, 1, 1, 6)]:
             sc = sg.sched(w, f, ch, g)
             sg.sogrand_decode_batched([gcode], fc, fo, xs, L, QCAP, ITERS, sched_=sc)
             torch.cuda.synchronize()

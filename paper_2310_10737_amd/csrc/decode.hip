@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_component(ComponentArgs a) {
         lam[b] = i < n ? (double)in[i] : 0.0;
     }
     double lapp[NB];
-    const WordStats st = decode_word<NS>(a.code, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    const WordStats st = decode_word<NS>(a.code, nullptr, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
     if (a.prof && lane == 0) prof_add(a.prof, st);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
         lam[b] = i < n ? (double)ch[pos[b]] + (double)la[pos[b]] : 0.0;
     }
     double lapp[NB];
-    const WordStats st = decode_word<NS>(a.code, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    const WordStats st = decode_word<NS>(a.code, nullptr, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
     if (a.prof && lane == 0) prof_add(a.prof, st);
     uint64_t hm[2] = {0ull, 0ull};
 #pragma unroll

@@ -262,9 +262,60 @@ __device__ __forceinline__ void sort64x2(uint64_t (&k)[2], int lane) {
 }
 
 // ---- binary64 elementary functions for the per-bit work ----
-constexpr double kLn2Hi = 0x1.62e42fefa2000p-1;   // ln 2 to 40 bits: k * kLn2Hi is exact for |k| < 2^13
-constexpr double kLn2Lo = 0x1.9ef35793c7673p-41;  // ln 2 - kLn2Hi
-constexpr double kInvLn2 = 1.4426950408889634;
+// Loads a value every lane of the wave agrees on into scalar registers.  Inside
+// a loop that also stores to device memory the compiler cannot prove such a load
+// constant and would keep the value (and all addresses derived from it) per lane.
+template <typename V>
+__device__ __forceinline__ V load_uniform(const V *p) {
+    static_assert(sizeof(V) % 4 == 0, "whole 32-bit words");
+    uint32_t w[sizeof(V) / 4];
+    __builtin_memcpy(w, p, sizeof(V));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(V) / 4); i++) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    V v;
+    __builtin_memcpy(&v, w, sizeof(V));
+    return v;
+}
+
+// Coefficients of the elementary functions below.  A kernel that loops over
+// words (the persistent kernel) reads them through a pointer the compiler
+// cannot see through (TABLE = true), so that each use is a scalar load: as
+// literals, the loop would hoist all of them into registers for its whole
+// length and cost a fifth of the register file.  A kernel that decodes one word
+// takes them as literals (TABLE = false).
+struct CoefSet {
+    double v[29];
+};
+constexpr int kInvLn2At = 0, kLn2HiAt = 1, kLn2LoAt = 2;
+constexpr int kExpAt = 3, kExpTerms = 14;                    // 1/13!, 1/12!, ..., 1/1!, 1
+constexpr int kLogAt = kExpAt + kExpTerms, kLogTerms = 12;   // 1/23, 1/21, ..., 1/3, 1
+constexpr CoefSet kCoefV = {{
+    1.4426950408889634,                 // 1 / ln 2
+    0x1.62e42fefa2000p-1,               // ln 2 to 40 bits: k * this is exact for |k| < 2^13
+    0x1.9ef35793c7673p-41,              // ln 2 minus the above
+    1.0 / 6227020800.0, 1.0 / 479001600.0, 1.0 / 39916800.0, 1.0 / 3628800.0, 1.0 / 362880.0,
+    1.0 / 40320.0, 1.0 / 5040.0, 1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0, 0.5, 1.0, 1.0,
+    1.0 / 23.0, 1.0 / 21.0, 1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0, 1.0 / 9.0,
+    1.0 / 7.0, 1.0 / 5.0, 1.0 / 3.0, 1.0,
+}};
+static_assert(kLogAt + kLogTerms == 29, "coefficient count");
+static __constant__ CoefSet kCoefTable = kCoefV;
+typedef __attribute__((address_space(4))) const CoefSet ccoef;
+
+template <bool TABLE>
+struct Coef {
+    const ccoef *t;
+    __device__ __forceinline__ Coef() {
+        if constexpr (TABLE) {
+            t = (const ccoef *)&kCoefTable;
+            asm volatile("" : "+s"(t));
+        }
+    }
+    __device__ __forceinline__ double operator[](int j) const {
+        if constexpr (TABLE) return t->v[j];
+        else return kCoefV.v[j];
+    }
+};
 
 // 1/x for positive normal x: hardware reciprocal and two Newton steps
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -277,31 +328,23 @@ __device__ __forceinline__ double rcp_nr(double x) {
 
 // e^{-a}, a >= 0: Cody-Waite reduction a = k ln2 + r with |r| <= ln2/2, then the
 // degree-13 Taylor polynomial of e^{-r} (truncation below 2^-57 relative)
+template <bool TABLE>
 __device__ __forceinline__ double exp_neg(double a) {
+    const Coef<TABLE> t;
     const double ac = a < 1100.0 ? a : 1100.0;
-    const double k = rint(ac * kInvLn2);
-    double r = fma(-k, kLn2Hi, ac);
-    r = fma(-k, kLn2Lo, r);
+    const double k = rint(ac * t[kInvLn2At]);
+    double r = fma(-k, t[kLn2HiAt], ac);
+    r = fma(-k, t[kLn2LoAt], r);
     const double x = -r;
-    double p = 1.0 / 6227020800.0;
-    p = fma(p, x, 1.0 / 479001600.0);
-    p = fma(p, x, 1.0 / 39916800.0);
-    p = fma(p, x, 1.0 / 3628800.0);
-    p = fma(p, x, 1.0 / 362880.0);
-    p = fma(p, x, 1.0 / 40320.0);
-    p = fma(p, x, 1.0 / 5040.0);
-    p = fma(p, x, 1.0 / 720.0);
-    p = fma(p, x, 1.0 / 120.0);
-    p = fma(p, x, 1.0 / 24.0);
-    p = fma(p, x, 1.0 / 6.0);
-    p = fma(p, x, 0.5);
-    p = fma(p, x, 1.0);
-    p = fma(p, x, 1.0);
+    double p = t[kExpAt];
+#pragma unroll
+    for (int j = 1; j < kExpTerms; j++) p = fma(p, x, t[kExpAt + j]);
     return ldexp(p, -(int)k);
 }
 
 // ln x for finite x > 0 of normal magnitude: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
 // ln m = 2 atanh(s) = 2 s sum_j s^{2j} / (2j + 1) with s = (m - 1)/(m + 1), |s| < 0.1716
+template <bool TABLE>
 __device__ __forceinline__ double log_pos(double x) {
     double m = __builtin_amdgcn_frexp_mant(x);
     int e = __builtin_amdgcn_frexp_exp(x);
@@ -314,25 +357,18 @@ __device__ __forceinline__ double log_pos(double x) {
     double s = num * rd;
     s = fma(fma(-den, s, num), rd, s);
     const double z = s * s;
-    double p = 1.0 / 23.0;
-    p = fma(p, z, 1.0 / 21.0);
-    p = fma(p, z, 1.0 / 19.0);
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
-    p = fma(p, z, 1.0);
+    const Coef<TABLE> t;
+    double p = t[kLogAt];
+#pragma unroll
+    for (int j = 1; j < kLogTerms; j++) p = fma(p, z, t[kLogAt + j]);
     const double lm = (s + s) * p;
     const double de = (double)e;
-    return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+    return fma(de, t[kLn2HiAt], fma(de, t[kLn2LoAt], lm));
 }
 
 // ln(N0 / N1) for N0, N1 >= 0 not both zero: the mantissas' ratio (in (1/2, 2)) goes
 // through ln, the exponents' difference is added as a multiple of ln 2
+template <bool TABLE>
 __device__ __forceinline__ double log_ratio(double n0, double n1) {
     const double m0 = __builtin_amdgcn_frexp_mant(n0), m1 = __builtin_amdgcn_frexp_mant(n1);
     const int e0 = __builtin_amdgcn_frexp_exp(n0), e1 = __builtin_amdgcn_frexp_exp(n1);
@@ -340,7 +376,8 @@ __device__ __forceinline__ double log_ratio(double n0, double n1) {
     double q = m0 * r;
     q = fma(fma(-m1, q, m0), r, q);
     const double de = (double)(e0 - e1);
-    double la = fma(de, kLn2Hi, fma(de, kLn2Lo, log_pos(q)));
+    const Coef<TABLE> t;
+    double la = fma(de, t[kLn2HiAt], fma(de, t[kLn2LoAt], log_pos<TABLE>(q)));
     if (n1 == 0.0) la = 1000.0;
     if (n0 == 0.0) la = -1000.0;
     return la;
@@ -382,8 +419,8 @@ __device__ __forceinline__ void put_rho(WaveLds &S, int r, double v) {
 
 // Decodes one word held as lam[slot] at bit index lane + 64*slot (< n).
 // Writes the APP LLRs of the lane's bits into lapp; the list is left in S.
-template <int NS>
-__device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32_t qcap,
+template <int NS, bool TABLE = false>
+__device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode *cdev, int L, uint32_t qcap,
                                                  const double (&lam)[Lanes<NS>::NB], WaveLds &S,
                                                  double (&lapp)[Lanes<NS>::NB], int lane, bool count) {
     constexpr int NB = Lanes<NS>::NB;
@@ -406,7 +443,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
         ycount += __popcll(__ballot(ybit[b]));
         const double a = fabs(lam[b]);
         key[b] = valid[b] ? (uint64_t)__double_as_longlong(a) : ~0ull;
-        rho[b] = valid[b] ? exp_neg(a) : 0.0;
+        rho[b] = valid[b] ? exp_neg<TABLE>(a) : 0.0;
     }
     const uint32_t s0 = wave_xor(spart);
     const int par = ycount & 1;
@@ -517,9 +554,22 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
     // 4. query loop over the schedule of the word's parity class; the next chunk's
     //    patterns are fetched while the current one is tested
     const int cls = c.even ? par : 0;
-    const uint4 *__restrict__ tab = c.pat[cls];
-    const uint32_t *__restrict__ wm = c.wmax[cls];
-    const uint32_t limit = qcap < c.len[cls] ? qcap : c.len[cls];
+    // The persistent kernel holds its DevCode in registers, where a dynamic index
+    // would move it to scratch memory: it reads the class's table fields from the
+    // device copy instead.  A kernel argument is indexed in place.
+    const uint4 *__restrict__ tab;
+    const uint32_t *__restrict__ wm;
+    uint32_t len;
+    if constexpr (TABLE) {
+        tab = load_uniform(&cdev->pat[cls]);
+        wm = load_uniform(&cdev->wmax[cls]);
+        len = load_uniform(&cdev->len[cls]);
+    } else {
+        tab = c.pat[cls];
+        wm = c.wmax[cls];
+        len = c.len[cls];
+    }
+    const uint32_t limit = qcap < len ? qcap : len;
     int found = 0;
     uint32_t Q = 0;
     double s_lane = 0.0;   // this lane's share of the tested nonzero-pattern mass (relative to p(0|r))
@@ -647,7 +697,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, int L, uint32
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        double la = log_ratio(N0[b], N1[b]);
+        double la = log_ratio<TABLE>(N0[b], N1[b]);
         if (!(la <= 1000.0)) la = 1000.0;
         if (!(la >= -1000.0)) la = -1000.0;
         lapp[b] = la;
