@@ -188,6 +188,71 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
                            uint32_t *status, const sogrand_sched_t *sched, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of product-frame decode requests            */
+/* ------------------------------------------------------------------------ */
+/* A server owns a pool of frame slots in device memory (hbm_budget_bytes) and
+   a host thread that advances every admitted frame by one half-iteration per
+   step (section "Iterative decoding"): the row or column pass of all admitted
+   frames, whatever their codes, runs in one set of launches, followed by the
+   validity check.  Frames that finish leave, and requests submitted meanwhile
+   join at the next step, so new work overlaps with frames already in flight.
+   Each frame is decoded exactly as sogrand_decode_product decodes it alone.
+
+   A slot holds the frame's channel LLRs, a-priori LLRs, hard decision and
+   line syndromes; its size is set by the code length rounded up to 32, 64 or
+   128.  A host copy of equal size (pinned memory) carries the LLRs in and the
+   hard decisions out.  The server decodes on the device current at creation. */
+typedef struct sogrand_server sogrand_server_t;
+
+typedef struct {
+    uint64_t request_id;
+    uint64_t user_tag;
+    int32_t status;          /* 0, or SOGRAND_EDEVICE if the device failed       */
+    uint8_t success;         /* hard decision is a product codeword              */
+    uint16_t half_iters;     /* half-iterations run                              */
+    uint16_t n;              /* code length: the result's hard decision is n*n bytes */
+    uint64_t queries;        /* patterns tested over all words and half-iterations */
+    uint64_t hard_offset;    /* byte offset of the hard decision in hard_out_host */
+    uint64_t t_submit_ns;    /* sogrand_clock_ns() at submission                 */
+    uint64_t t_admit_ns;     /* ... when the frame entered its first step        */
+    uint64_t t_done_ns;      /* ... when its last step completed                 */
+} sogrand_result_t;
+
+/* CLOCK_MONOTONIC in nanoseconds: the clock of the result timestamps. */
+uint64_t sogrand_clock_ns(void);
+
+/* params as for sogrand_decode_product (precision sets the LLR storage of the
+   slots and of llr_ch_host).  hbm_budget_bytes: device memory for slots, at
+   least 1 MiB; the same amount of pinned host memory is allocated.
+   Errors: EINVAL, ENOMEM, EDEVICE. */
+int sogrand_serve_create(const sogrand_params_t *params, size_t hbm_budget_bytes, sogrand_server_t **out);
+
+/* Admits one frame: llr_ch_host is HOST memory, n*n LLRs row-major in the
+   server's precision, copied before the call returns (the caller keeps it).
+   A server accepts up to 16 distinct codes.  Returns SOGRAND_EAGAIN when no
+   slot is free (poll for results, then retry), EINVAL for bad arguments or a
+   seventeenth code, EDEVICE after a device failure. */
+int sogrand_serve_submit(sogrand_server_t *server, const sogrand_code_t *code, const void *llr_ch_host,
+                         uint64_t user_tag, uint64_t *request_id);
+
+/* Takes up to max_results finished requests, oldest first, waiting up to
+   timeout_ns (0: do not wait; < 0: until one finishes).  If hard_out_host is
+   not NULL it receives each result's n*n hard decisions at hard_offset, packed
+   back to back (at most max_results * 16384 bytes).  Returns SOGRAND_OK with
+   *n_results >= 1, SOGRAND_ETIMEDOUT if none finished in time, SOGRAND_ENOTFOUND
+   if nothing is in flight and nothing is waiting to be taken. */
+int sogrand_serve_poll(sogrand_server_t *server, sogrand_result_t *results, size_t max_results,
+                       size_t *n_results, uint8_t *hard_out_host, int64_t timeout_ns);
+
+/* Counters since creation: steps run, frames finished, and the summed wall
+   time of the steps (launch to completion). */
+int sogrand_serve_stats(sogrand_server_t *server, uint64_t *steps, uint64_t *frames, double *step_ms);
+
+/* Finishes every admitted request, then releases the server; results not
+   taken are discarded. */
+int sogrand_serve_destroy(sogrand_server_t *server);
+
+/* ------------------------------------------------------------------------ */
 /* Measurement                                                              */
 /* ------------------------------------------------------------------------ */
 /* Per-kernel-family totals collected between sogrand_profile_begin and

@@ -13,7 +13,7 @@ import os
 __all__ = [
     "SograndError", "Code", "params", "sched", "lib", "library_path", "profile_begin", "profile_end",
     "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_batched", "pack_frames",
-    "SOGRAND_F64", "SOGRAND_F32",
+    "Server", "sogrand_clock_ns", "SOGRAND_F64", "SOGRAND_F32",
 ]
 
 SOGRAND_F64 = 0
@@ -28,8 +28,14 @@ EXPORTS = [
     "sogrand_code_create", "sogrand_code_create_ebch", "sogrand_code_info", "sogrand_code_destroy",
     "sogrand_decode_component", "sogrand_decode_product",
     "sogrand_sched_default", "sogrand_decode_batched",
+    "sogrand_clock_ns", "sogrand_serve_create", "sogrand_serve_submit", "sogrand_serve_poll",
+    "sogrand_serve_stats", "sogrand_serve_destroy",
     "sogrand_profile_begin", "sogrand_profile_end",
 ]
+
+SOGRAND_EAGAIN = -4
+SOGRAND_ENOTFOUND = -5
+SOGRAND_ETIMEDOUT = -6
 
 
 class SograndError(RuntimeError):
@@ -56,6 +62,22 @@ class sogrand_sched_t(ctypes.Structure):
         ("frames_per_group", ctypes.c_int),
         ("steal_chunk", ctypes.c_int),
         ("groups_per_cu", ctypes.c_int),
+    ]
+
+
+class sogrand_result_t(ctypes.Structure):
+    _fields_ = [
+        ("request_id", ctypes.c_uint64),
+        ("user_tag", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("success", ctypes.c_uint8),
+        ("half_iters", ctypes.c_uint16),
+        ("n", ctypes.c_uint16),
+        ("queries", ctypes.c_uint64),
+        ("hard_offset", ctypes.c_uint64),
+        ("t_submit_ns", ctypes.c_uint64),
+        ("t_admit_ns", ctypes.c_uint64),
+        ("t_done_ns", ctypes.c_uint64),
     ]
 
 
@@ -96,6 +118,12 @@ def lib():
     L.sogrand_sched_default.argtypes = [P]
     L.sogrand_sched_default.restype = None
     L.sogrand_decode_batched.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 9
+    L.sogrand_clock_ns.restype = ctypes.c_uint64
+    L.sogrand_serve_create.argtypes = [P, SZ, P]
+    L.sogrand_serve_submit.argtypes = [P, P, P, ctypes.c_uint64, P]
+    L.sogrand_serve_poll.argtypes = [P, P, SZ, P, P, ctypes.c_int64]
+    L.sogrand_serve_stats.argtypes = [P, P, P, P]
+    L.sogrand_serve_destroy.argtypes = [P]
     L.sogrand_profile_begin.argtypes = [I]
     L.sogrand_profile_end.argtypes = [P, I, P]
     for name in EXPORTS:
@@ -311,3 +339,83 @@ def sogrand_decode_batched(codes, frame_code, frame_offset, llr, list_max=4, que
         _ptr(llr), _ptr(out["hard"]), _ptr(out["success"]), _ptr(out["half_iters"]), _ptr(out["sum_queries"]),
         _ptr(out["sum_max_queries"]), _ptr(out["status"]), ctypes.byref(sc), _stream(stream)))
     return out
+
+
+def sogrand_clock_ns() -> int:
+    """The library's clock (CLOCK_MONOTONIC, ns), the clock of serving timestamps."""
+    return int(lib().sogrand_clock_ns())
+
+
+class Server:
+    """A serving instance: continuous batching of product-frame decode requests.
+
+    Frames are submitted from host memory (numpy arrays of shape (n, n) in the
+    server's precision) and results are taken with poll().
+    """
+
+    def __init__(self, hbm_budget_bytes, list_max=4, query_cap=1000, max_iter=4, alpha=0.5, early_stop=True,
+                 precision=SOGRAND_F32):
+        self._h = ctypes.c_void_p()
+        self.precision = precision
+        p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
+                   early_stop=early_stop, precision=precision)
+        _check(lib().sogrand_serve_create(ctypes.byref(p), int(hbm_budget_bytes), ctypes.byref(self._h)))
+
+    def submit(self, code: Code, llr_host, tag: int = 0):
+        """Submits one frame; returns its request id, or None if no slot is free (retry after poll)."""
+        import numpy as np
+        want = np.float64 if self.precision == SOGRAND_F64 else np.float32
+        if llr_host.dtype != want or not llr_host.flags.c_contiguous or llr_host.size != code.n * code.n:
+            raise ValueError(f"llr_host must be a C-contiguous {want.__name__} array of n*n elements")
+        rid = ctypes.c_uint64()
+        rc = lib().sogrand_serve_submit(self._h, code.handle, ctypes.c_void_p(llr_host.ctypes.data),
+                                        int(tag), ctypes.byref(rid))
+        if rc == SOGRAND_EAGAIN:
+            return None
+        _check(rc)
+        return rid.value
+
+    def poll(self, max_results=256, timeout_ns=0, want_hard=True):
+        """Finished requests as a list of dicts (hard: (n, n) uint8 numpy array when want_hard)."""
+        import numpy as np
+        res = (sogrand_result_t * max_results)()
+        hard = np.empty(max_results * 128 * 128, dtype=np.uint8) if want_hard else None
+        nres = ctypes.c_size_t()
+        rc = lib().sogrand_serve_poll(self._h, res, max_results, ctypes.byref(nres),
+                                      None if hard is None else ctypes.c_void_p(hard.ctypes.data), int(timeout_ns))
+        if rc in (SOGRAND_ETIMEDOUT, SOGRAND_ENOTFOUND):
+            return []
+        _check(rc)
+        out = []
+        for i in range(nres.value):
+            r = res[i]
+            d = dict(request_id=r.request_id, user_tag=r.user_tag, status=r.status, success=r.success,
+                     half_iters=r.half_iters, n=r.n, queries=r.queries, t_submit_ns=r.t_submit_ns,
+                     t_admit_ns=r.t_admit_ns, t_done_ns=r.t_done_ns)
+            if hard is not None:
+                nn = r.n * r.n
+                d["hard"] = hard[r.hard_offset:r.hard_offset + nn].reshape(r.n, r.n).copy()
+            out.append(d)
+        return out
+
+    def stats(self):
+        st, fr, ms = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
+        _check(lib().sogrand_serve_stats(self._h, ctypes.byref(st), ctypes.byref(fr), ctypes.byref(ms)))
+        return dict(steps=st.value, frames=fr.value, step_ms=ms.value)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().sogrand_serve_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsogrand.so")
 
-SOURCES = ["code.hip", "decode.hip", "batched.hip", "profile.hip"]
+SOURCES = ["code.hip", "decode.hip", "batched.hip", "serve.hip", "profile.hip"]
 HOST_SOURCES: list = []
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,645 @@
+// Serving: continuous batching of product-frame decode requests.
+//
+// A host thread runs steps.  Each step advances every admitted frame by one
+// half-iteration of the block turbo loop (section "Iterative decoding"): one
+// wave per row or column, frames of every code in the same launches (one per
+// word width), then one wave per frame tests the hard decision.  A frame that
+// is valid (with early stopping) or has run its last half-iteration leaves:
+// the check kernel writes its hard decision straight into pinned host memory
+// and its slot is recycled.  Requests that arrived during a step join the next
+// one, so the device is shared by frames at every stage of decoding.
+//
+// Frame state stays in a device slot for the frame's whole life.  Channel LLRs
+// reach the device through pinned host memory that the first row pass reads
+// directly (and copies into the slot), so admission costs no copy call.
+#include <time.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+
+#include "word.hpp"
+
+namespace sg {
+
+constexpr int kServeCodes = 16;
+constexpr size_t kServeMinBudget = (size_t)1 << 20;
+
+// One admitted frame in one step (device copy of the host's list).
+struct ServeDesc {
+    uint64_t slot;    // byte offset of the frame's slot, in both arenas
+    uint32_t line0;   // first global line of this frame in its launch
+    uint16_t code;    // index into the server's code table
+    uint16_t n;
+    uint32_t h;       // half-iteration run in this step, 1 .. 2 max_iter
+    uint32_t pad;
+};
+
+// Written by the check kernel into pinned host memory, one per admitted frame.
+struct ServeOut {
+    uint32_t flags;   // bit 0: the hard decision is a product codeword; bit 1: the frame is finished
+    uint32_t pad;
+    uint64_t queries; // patterns tested in this step
+};
+
+// Byte layout of a frame's slot for code length n and element size esz.
+struct SlotLayout {
+    size_t la, hard, masks, bytes;
+};
+
+__host__ __device__ inline SlotLayout slot_layout(int n, size_t esz) {
+    SlotLayout s;
+    const size_t nn = (size_t)n * n;
+    s.la = nn * esz;
+    s.hard = 2 * nn * esz;
+    s.masks = (s.hard + nn + 15) & ~(size_t)15;
+    s.bytes = (s.masks + (size_t)n * 2 * sizeof(uint64_t) + 255) & ~(size_t)255;
+    return s;
+}
+
+struct ServeArgs {
+    const DevCode *codes;
+    char *arena;              // device slots
+    const char *mirror;       // pinned host copy of the slots (device view)
+    char *mirror_w;           // the same, for the check kernel's hard-decision export
+    const ServeDesc *desc;    // this launch's frames
+    uint32_t nact;            // frames in this launch
+    uint32_t nlines;          // lines in this launch
+    ServeOut *out;            // pinned host memory (device view), indexed like desc
+    unsigned long long *qsum; // per frame: queries of this step
+    int L;
+    uint32_t qcap;
+    double alpha;
+    int max_iter;
+    int early_stop;
+    ProfCounters *prof;
+};
+
+// One wave per line of one word width.  Every frame of the launch runs the
+// half-iteration its descriptor names (rows for odd h).
+template <typename T, int NS>
+__global__ __launch_bounds__(kBlock) void k_serve_pass(ServeArgs a) {
+    constexpr int NB = Lanes<NS>::NB;
+    __shared__ WaveLds lds[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    WaveLds &S = lds[wave];
+    const uint32_t gl = (uint32_t)blockIdx.x * kWavesPerBlock + (uint32_t)wave;
+    if (gl >= a.nlines) return;
+    // the frame owning global line gl: the last descriptor whose line0 <= gl
+    uint32_t lo = 0, hi = a.nact - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (load_uniform(&a.desc[mid].line0) <= gl) lo = mid;
+        else hi = mid - 1;
+    }
+    const ServeDesc d = load_uniform(a.desc + lo);
+    const DevCode *cdev = a.codes + d.code;
+    const DevCode c = load_uniform(cdev);
+    const int n = d.n;
+    const int line = (int)(gl - d.line0);
+    const SlotLayout sl = slot_layout(n, sizeof(T));
+    char *slot = a.arena + d.slot;
+    T *ch = reinterpret_cast<T *>(slot);
+    T *la = reinterpret_cast<T *>(slot + sl.la);
+    uint8_t *hard = reinterpret_cast<uint8_t *>(slot + sl.hard);
+    uint64_t *mk = reinterpret_cast<uint64_t *>(slot + sl.masks);
+    const bool rows = (d.h & 1u) != 0;
+    const T *src = reinterpret_cast<const T *>(a.mirror + d.slot);
+    double lam[NB];
+    int pos[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int i = lane + kWave * b;
+        pos[b] = rows ? line * n + i : i * n + line;
+        lam[b] = 0.0;
+        if (i < n) {
+            if (d.h == 1) {
+                // first half-iteration: the channel LLRs come from host memory and
+                // stay in the slot; the a-priori LLRs are zero
+                const T v = src[pos[b]];
+                ch[pos[b]] = v;
+                lam[b] = (double)v;
+            } else {
+                lam[b] = (double)ch[pos[b]] + (double)la[pos[b]];
+            }
+        }
+    }
+    double lapp[NB];
+    const WordStats st = decode_word<NS, true>(c, cdev, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    if (a.prof && lane == 0) prof_add(a.prof, st);
+    uint64_t hm[2] = {0ull, 0ull};
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int i = lane + kWave * b;
+        const bool v = i < n;
+        const bool neg = v && lapp[b] < 0.0;
+        hm[b] = __ballot(neg);
+        if (!v) continue;
+        la[pos[b]] = (T)(a.alpha * (lapp[b] - lam[b]));
+        hard[pos[b]] = neg;
+    }
+    if (lane == 0) {
+        mk[line * 2 + 0] = hm[0];
+        mk[line * 2 + 1] = hm[1];
+        atomicAdd(&a.qsum[lo], (unsigned long long)st.Q);
+    }
+}
+
+// One wave per frame of the step: validity of the hard decision (every line of
+// the last pass and every cross line a codeword), the frame's verdict into host
+// memory, and for a finished frame its hard decision into the host copy.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t i = (uint32_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (i >= a.nact) return;
+    const ServeDesc d = load_uniform(a.desc + i);
+    const int n = d.n;
+    const SlotLayout sl = slot_layout(n, sizeof(T));
+    const char *slot = a.arena + d.slot;
+    const uint64_t *mk = reinterpret_cast<const uint64_t *>(slot + sl.masks);
+    const uint32_t *hcol = load_uniform(&a.codes[d.code].hcol);
+    bool bad = false;
+    for (int b = 0; b < 2; b++) {
+        const int x = lane + kWave * b;
+        if (x >= n) continue;
+        const uint64_t m0 = mk[x * 2], m1 = mk[x * 2 + 1];
+        uint32_t s = 0;
+        for (int j = 0; j < n; j++) {
+            const uint64_t bit = j < 64 ? (m0 >> j) & 1ull : (m1 >> (j - 64)) & 1ull;
+            if (bit) s ^= hcol[j];
+        }
+        uint32_t t = 0;
+        for (int l = 0; l < n; l++) {
+            const uint64_t w = x < 64 ? mk[l * 2] : mk[l * 2 + 1];
+            if ((w >> (x & 63)) & 1ull) t ^= hcol[l];
+        }
+        bad |= (s != 0u) || (t != 0u);
+    }
+    const bool valid = __ballot(bad) == 0ull;
+    const bool finished = (valid && a.early_stop) || d.h == (uint32_t)(2 * a.max_iter);
+    if (finished) {
+        // 16-byte copies when n is a multiple of 4 (n*n a multiple of 16), else bytes
+        const size_t nn = (size_t)n * n;
+        const uint8_t *hs = reinterpret_cast<const uint8_t *>(slot + sl.hard);
+        uint8_t *hd = reinterpret_cast<uint8_t *>(a.mirror_w + d.slot + sl.hard);
+        if ((nn & 15) == 0) {
+            for (size_t o = (size_t)lane * 16; o < nn; o += kWave * 16)
+                *reinterpret_cast<uint4 *>(hd + o) = *reinterpret_cast<const uint4 *>(hs + o);
+        } else {
+            for (size_t o = lane; o < nn; o += kWave) hd[o] = hs[o];
+        }
+    }
+    if (lane == 0) {
+        ServeOut o;
+        o.flags = (valid ? 1u : 0u) | (finished ? 2u : 0u);
+        o.pad = 0;
+        o.queries = a.qsum[i];
+        a.out[i] = o;
+        a.qsum[i] = 0ull;   // ready for the next step
+    }
+}
+
+uint64_t clock_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+}  // namespace sg
+
+using sg::ServeDesc;
+using sg::ServeOut;
+
+struct sogrand_server {
+    struct Req {
+        uint64_t id = 0, tag = 0;
+        int code = 0, n = 0, wclass = 0;
+        uint64_t slot = 0;
+        uint32_t h = 1;
+        uint64_t queries = 0;
+        uint64_t t_submit = 0, t_admit = 0;
+    };
+    struct Done {
+        sogrand_result_t r;
+        std::vector<uint8_t> hard;
+    };
+
+    sogrand_params_t params{};
+    int device = 0;
+    size_t esz = 8;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    char *arena = nullptr;        // device slots
+    char *mirror = nullptr;       // pinned host copy (host pointer)
+    char *mirror_dev = nullptr;   // the same (device pointer)
+    size_t class_bytes[3] = {0, 0, 0};
+    size_t bump = 0;
+    std::vector<uint64_t> free_slots[3];
+    size_t max_active = 0;
+
+    const sogrand_code_t *code_ptr[sg::kServeCodes] = {};
+    sg::DevCode *codes_host = nullptr;   // pinned staging of the table
+    sg::DevCode *codes_dev = nullptr;
+    int ncodes = 0;
+    bool codes_dirty = false;
+
+    ServeDesc *desc_host = nullptr;      // pinned
+    ServeDesc *desc_dev = nullptr;
+    ServeOut *out_host = nullptr;        // pinned, written by the device
+    ServeOut *out_dev = nullptr;         // device view of out_host
+    unsigned long long *qsum = nullptr;  // device
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req> pending;
+    std::deque<Done> done;
+    size_t in_flight = 0;                // admitted, not yet finished
+    uint64_t next_id = 1;
+    bool stop = false;
+    int error = SOGRAND_OK;
+    uint64_t steps = 0, frames = 0;
+    double step_ms = 0.0;
+    std::thread worker;
+
+    void run();
+    int step(std::vector<Req> &active);
+};
+
+namespace sg {
+
+static int width_class(int n) { return n <= 32 ? 0 : (n <= 64 ? 1 : 2); }
+static int class_width(int c) { return c == 0 ? 32 : (c == 1 ? 64 : 128); }
+
+template <typename T>
+static void launch_serve_pass(const ServeArgs &a, int wclass, hipStream_t st) {
+    const dim3 g((a.nlines + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (wclass == 0) hipLaunchKernelGGL((k_serve_pass<T, 32>), g, dim3(kBlock), 0, st, a);
+    else if (wclass == 1) hipLaunchKernelGGL((k_serve_pass<T, 64>), g, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_serve_pass<T, 128>), g, dim3(kBlock), 0, st, a);
+}
+
+}  // namespace sg
+
+// One step over the admitted frames; updates `active` and publishes finished ones.
+int sogrand_server::step(std::vector<Req> &active) {
+    using namespace sg;
+    const uint64_t t0 = clock_ns();
+    // frames grouped by word width, each group one launch
+    std::vector<uint32_t> order;
+    order.reserve(active.size());
+    uint32_t gstart[4] = {0, 0, 0, 0};
+    for (int c = 0; c < 3; c++) {
+        gstart[c] = (uint32_t)order.size();
+        for (uint32_t i = 0; i < active.size(); i++)
+            if (active[i].wclass == c) order.push_back(i);
+    }
+    gstart[3] = (uint32_t)order.size();
+    uint32_t glines[3] = {0, 0, 0};
+    for (int c = 0; c < 3; c++) {
+        for (uint32_t j = gstart[c]; j < gstart[c + 1]; j++) {
+            const Req &r = active[order[j]];
+            ServeDesc &d = desc_host[j];
+            d.slot = r.slot;
+            d.line0 = glines[c];
+            d.code = (uint16_t)r.code;
+            d.n = (uint16_t)r.n;
+            d.h = r.h;
+            d.pad = 0;
+            glines[c] += (uint32_t)r.n;
+        }
+    }
+    const uint32_t nact = gstart[3];
+    // host writes to the pinned arena (submitted LLRs) and the descriptor
+    // staging complete before the device is told to read them
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    if (hipMemcpyAsync(desc_dev, desc_host, nact * sizeof(ServeDesc), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return fail(SOGRAND_EDEVICE, "descriptor copy failed");
+    ServeArgs a{};
+    a.codes = codes_dev;
+    a.arena = arena;
+    a.mirror = mirror_dev;
+    a.mirror_w = mirror_dev;
+    a.L = params.list_max;
+    a.qcap = params.query_cap;
+    a.alpha = params.alpha;
+    a.max_iter = params.max_iter;
+    a.early_stop = params.early_stop ? 1 : 0;
+    a.prof = prof_counters(PK_SERVE);
+    for (int c = 0; c < 3; c++) {
+        const uint32_t cnt = gstart[c + 1] - gstart[c];
+        if (!cnt) continue;
+        ServeArgs g = a;
+        g.desc = desc_dev + gstart[c];
+        g.nact = cnt;
+        g.nlines = glines[c];
+        g.qsum = qsum + gstart[c];
+        if (esz == 8) launch_serve_pass<double>(g, c, stream);
+        else launch_serve_pass<float>(g, c, stream);
+    }
+    ServeArgs ck = a;
+    ck.desc = desc_dev;
+    ck.nact = nact;
+    ck.out = out_dev;
+    ck.qsum = qsum;
+    const dim3 cg((nact + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (esz == 8) hipLaunchKernelGGL(k_serve_check<double>, cg, dim3(kBlock), 0, stream, ck);
+    else hipLaunchKernelGGL(k_serve_check<float>, cg, dim3(kBlock), 0, stream, ck);
+    if (hipGetLastError() != hipSuccess) return fail(SOGRAND_EDEVICE, "serving kernel launch failed");
+    if (hipStreamSynchronize(stream) != hipSuccess) return fail(SOGRAND_EDEVICE, "serving step failed on the device");
+    const uint64_t t1 = clock_ns();
+
+    std::vector<Done> fin;
+    std::vector<Req> keep;
+    keep.reserve(active.size());
+    std::vector<uint8_t> is_done(active.size(), 0);
+    for (uint32_t j = 0; j < nact; j++) {
+        Req &r = active[order[j]];
+        const ServeOut o = out_host[j];
+        r.queries += o.queries;
+        if (o.flags & 2u) {
+            Done dn;
+            dn.r.request_id = r.id;
+            dn.r.user_tag = r.tag;
+            dn.r.status = SOGRAND_OK;
+            dn.r.success = (uint8_t)(o.flags & 1u);
+            dn.r.half_iters = (uint16_t)r.h;
+            dn.r.n = (uint16_t)r.n;
+            dn.r.queries = r.queries;
+            dn.r.hard_offset = 0;
+            dn.r.t_submit_ns = r.t_submit;
+            dn.r.t_admit_ns = r.t_admit;
+            dn.r.t_done_ns = t1;
+            const SlotLayout sl = slot_layout(r.n, esz);
+            const uint8_t *src = reinterpret_cast<const uint8_t *>(mirror + r.slot + sl.hard);
+            dn.hard.assign(src, src + (size_t)r.n * r.n);
+            fin.push_back(std::move(dn));
+            is_done[order[j]] = 1;
+        } else {
+            r.h += 1;
+        }
+    }
+    for (uint32_t i = 0; i < active.size(); i++)
+        if (!is_done[i]) keep.push_back(active[i]);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (uint32_t i = 0; i < active.size(); i++)
+            if (is_done[i]) free_slots[active[i].wclass].push_back(active[i].slot);
+        for (Done &d : fin) done.push_back(std::move(d));
+        in_flight -= fin.size();
+        steps += 1;
+        frames += fin.size();
+        step_ms += (double)(t1 - t0) * 1e-6;
+    }
+    active.swap(keep);
+    if (!fin.empty()) cv_done.notify_all();
+    return SOGRAND_OK;
+}
+
+void sogrand_server::run() {
+    using namespace sg;
+    (void)hipSetDevice(device);
+    std::vector<Req> active;
+    for (;;) {
+        bool copy_codes = false;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
+            if (pending.empty() && active.empty()) break;   // stop requested and drained
+            const uint64_t now = clock_ns();
+            while (!pending.empty()) {
+                Req r = pending.front();
+                pending.pop_front();
+                r.t_admit = now;
+                active.push_back(r);
+            }
+            if (codes_dirty) {
+                copy_codes = true;
+                codes_dirty = false;
+            }
+            if (copy_codes &&
+                hipMemcpyAsync(codes_dev, codes_host, sizeof(DevCode) * kServeCodes, hipMemcpyHostToDevice, stream) !=
+                    hipSuccess)
+                error = SOGRAND_EDEVICE;
+            if (copy_codes && error == SOGRAND_OK && hipStreamSynchronize(stream) != hipSuccess) error = SOGRAND_EDEVICE;
+        }
+        int rc = error == SOGRAND_OK ? step(active) : error;
+        if (rc != SOGRAND_OK) {
+            // the device failed: every admitted request ends with the error
+            std::lock_guard<std::mutex> lk(mu);
+            error = rc;
+            const uint64_t now = clock_ns();
+            for (const Req &r : active) {
+                Done dn;
+                std::memset(&dn.r, 0, sizeof dn.r);
+                dn.r.request_id = r.id;
+                dn.r.user_tag = r.tag;
+                dn.r.status = rc;
+                dn.r.n = (uint16_t)r.n;
+                dn.r.t_submit_ns = r.t_submit;
+                dn.r.t_admit_ns = r.t_admit;
+                dn.r.t_done_ns = now;
+                done.push_back(std::move(dn));
+                free_slots[r.wclass].push_back(r.slot);
+            }
+            in_flight -= active.size();
+            active.clear();
+            cv_done.notify_all();
+        }
+    }
+}
+
+extern "C" {
+
+uint64_t sogrand_clock_ns(void) { return sg::clock_ns(); }
+
+int sogrand_serve_create(const sogrand_params_t *params, size_t hbm_budget_bytes, sogrand_server_t **out) {
+    using namespace sg;
+    if (!out) return fail(SOGRAND_EINVAL, "out is NULL");
+    *out = nullptr;
+    SG_TRY(check_params(params));
+    if (hbm_budget_bytes < kServeMinBudget) return fail(SOGRAND_EINVAL, "hbm_budget_bytes below 1 MiB");
+    sogrand_server_t *s = new (std::nothrow) sogrand_server_t();
+    if (!s) return fail(SOGRAND_ENOMEM, "server allocation failed");
+    s->params = *params;
+    s->esz = params->precision == SOGRAND_F64 ? 8 : 4;
+    s->budget = hbm_budget_bytes & ~(size_t)255;
+    for (int c = 0; c < 3; c++) s->class_bytes[c] = slot_layout(class_width(c), s->esz).bytes;
+    s->max_active = s->budget / s->class_bytes[0] + 1;
+    auto cleanup = [s](int rc) {
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+        if (s->arena) (void)hipFree(s->arena);
+        if (s->mirror) (void)hipHostFree(s->mirror);
+        if (s->codes_host) (void)hipHostFree(s->codes_host);
+        if (s->codes_dev) (void)hipFree(s->codes_dev);
+        if (s->desc_host) (void)hipHostFree(s->desc_host);
+        if (s->desc_dev) (void)hipFree(s->desc_dev);
+        if (s->out_host) (void)hipHostFree(s->out_host);
+        if (s->qsum) (void)hipFree(s->qsum);
+        delete s;
+        return rc;
+    };
+    if (hipGetDevice(&s->device) != hipSuccess) return cleanup(fail(SOGRAND_EDEVICE, "no current device"));
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(fail(SOGRAND_EDEVICE, "stream creation failed"));
+    if (hipMalloc(reinterpret_cast<void **>(&s->arena), s->budget) != hipSuccess)
+        return cleanup(fail(SOGRAND_ENOMEM, "slot arena of %zu bytes", s->budget));
+    // the device reads submitted LLRs from, and writes hard decisions and verdicts
+    // to, these two host allocations inside kernels: coherent and mapped
+    const unsigned shared_flags = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->mirror), s->budget, shared_flags) != hipSuccess)
+        return cleanup(fail(SOGRAND_ENOMEM, "pinned host arena of %zu bytes", s->budget));
+    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&s->mirror_dev), s->mirror, 0) != hipSuccess)
+        return cleanup(fail(SOGRAND_EDEVICE, "pinned host arena not visible to the device"));
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->codes_host), sizeof(DevCode) * kServeCodes, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&s->codes_dev), sizeof(DevCode) * kServeCodes) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&s->desc_host), sizeof(ServeDesc) * s->max_active,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&s->desc_dev), sizeof(ServeDesc) * s->max_active) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&s->out_host), sizeof(ServeOut) * s->max_active, shared_flags) !=
+            hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&s->qsum), sizeof(unsigned long long) * s->max_active) != hipSuccess)
+        return cleanup(fail(SOGRAND_ENOMEM, "server tables"));
+    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&s->out_dev), s->out_host, 0) != hipSuccess)
+        return cleanup(fail(SOGRAND_EDEVICE, "pinned result table not visible to the device"));
+    std::memset(s->codes_host, 0, sizeof(DevCode) * kServeCodes);
+    if (hipMemsetAsync(s->qsum, 0, sizeof(unsigned long long) * s->max_active, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return cleanup(fail(SOGRAND_EDEVICE, "server initialisation failed"));
+    try {
+        s->worker = std::thread([s] { s->run(); });
+    } catch (...) {
+        return cleanup(fail(SOGRAND_ENOMEM, "server thread could not start"));
+    }
+    *out = s;
+    return SOGRAND_OK;
+}
+
+int sogrand_serve_submit(sogrand_server_t *s, const sogrand_code_t *code, const void *llr_ch_host, uint64_t user_tag,
+                         uint64_t *request_id) {
+    using namespace sg;
+    if (!s || !code || !llr_ch_host) return fail(SOGRAND_EINVAL, "server, code and llr_ch_host are required");
+    const int n = code->n;
+    const int wc = width_class(n);
+    sogrand_server::Req r;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->error != SOGRAND_OK) return fail(s->error, "the server's device failed");
+        if (s->stop) return fail(SOGRAND_EINVAL, "server is shutting down");
+        int ci = -1;
+        for (int i = 0; i < s->ncodes; i++)
+            if (s->code_ptr[i] == code) ci = i;
+        if (ci < 0) {
+            if (s->ncodes == kServeCodes) return fail(SOGRAND_EINVAL, "a server accepts at most %d codes", kServeCodes);
+            // the code's tables are built on the server's device; the caller's
+            // current device is restored afterwards
+            DevCode dc;
+            int prev = 0;
+            if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(s->device) != hipSuccess)
+                return fail(SOGRAND_EDEVICE, "cannot select the server's device");
+            const int rc = prepare_code(const_cast<sogrand_code_t *>(code), s->params.query_cap, &dc);
+            (void)hipSetDevice(prev);
+            if (rc != SOGRAND_OK) return rc;
+            ci = s->ncodes++;
+            s->code_ptr[ci] = code;
+            s->codes_host[ci] = dc;
+            s->codes_dirty = true;
+        }
+        // a slot: a recycled one of this width, else fresh space in the arena
+        if (!s->free_slots[wc].empty()) {
+            r.slot = s->free_slots[wc].back();
+            s->free_slots[wc].pop_back();
+        } else if (s->bump + s->class_bytes[wc] <= s->budget) {
+            r.slot = s->bump;
+            s->bump += s->class_bytes[wc];
+        } else {
+            return SOGRAND_EAGAIN;
+        }
+        r.id = s->next_id++;
+        r.code = ci;
+    }
+    // the slot is reserved: fill its host copy outside the lock
+    std::memcpy(s->mirror + r.slot, llr_ch_host, (size_t)n * n * s->esz);
+    r.tag = user_tag;
+    r.n = n;
+    r.wclass = wc;
+    r.h = 1;
+    r.t_submit = clock_ns();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->pending.push_back(r);
+        s->in_flight += 1;
+    }
+    s->cv_work.notify_one();
+    if (request_id) *request_id = r.id;
+    return SOGRAND_OK;
+}
+
+int sogrand_serve_poll(sogrand_server_t *s, sogrand_result_t *results, size_t max_results, size_t *n_results,
+                       uint8_t *hard_out_host, int64_t timeout_ns) {
+    using namespace sg;
+    if (!s || !results || !n_results || max_results == 0)
+        return fail(SOGRAND_EINVAL, "server, results, n_results and max_results > 0 are required");
+    *n_results = 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->done.empty()) {
+        if (s->in_flight == 0) return SOGRAND_ENOTFOUND;
+        if (timeout_ns == 0) return SOGRAND_ETIMEDOUT;
+        auto ready = [&] { return !s->done.empty() || s->in_flight == 0; };
+        if (timeout_ns < 0) s->cv_done.wait(lk, ready);
+        else s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready);
+        if (s->done.empty()) return s->in_flight == 0 ? SOGRAND_ENOTFOUND : SOGRAND_ETIMEDOUT;
+    }
+    size_t k = 0, off = 0;
+    while (k < max_results && !s->done.empty()) {
+        sogrand_server::Done &d = s->done.front();
+        results[k] = d.r;
+        results[k].hard_offset = off;
+        if (hard_out_host && !d.hard.empty()) std::memcpy(hard_out_host + off, d.hard.data(), d.hard.size());
+        off += (size_t)d.r.n * d.r.n;
+        s->done.pop_front();
+        k++;
+    }
+    *n_results = k;
+    return SOGRAND_OK;
+}
+
+int sogrand_serve_stats(sogrand_server_t *s, uint64_t *steps, uint64_t *frames, double *step_ms) {
+    if (!s) return sg::fail(SOGRAND_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (steps) *steps = s->steps;
+    if (frames) *frames = s->frames;
+    if (step_ms) *step_ms = s->step_ms;
+    return SOGRAND_OK;
+}
+
+int sogrand_serve_destroy(sogrand_server_t *s) {
+    if (!s) return SOGRAND_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamDestroy(s->stream);
+    (void)hipFree(s->arena);
+    (void)hipHostFree(s->mirror);
+    (void)hipHostFree(s->codes_host);
+    (void)hipFree(s->codes_dev);
+    (void)hipHostFree(s->desc_host);
+    (void)hipFree(s->desc_dev);
+    (void)hipHostFree(s->out_host);
+    (void)hipFree(s->qsum);
+    delete s;
+    return SOGRAND_OK;
+}
+
+}  // extern "C"

@@ -144,3 +144,25 @@ def test_batched_rejects_bad_arguments_before_device_work(sg):
     empty = list(args)
     empty[3] = 0
     assert L.sogrand_decode_batched(*empty) == 0
+
+
+def test_serving_rejects_bad_arguments_before_device_work(sg):
+    L = sg.lib()
+    p = sg.params()
+    out = ctypes.c_void_p()
+    assert L.sogrand_serve_create(ctypes.byref(p), 1 << 10, ctypes.byref(out)) == -1   # budget below 1 MiB
+    assert L.sogrand_serve_create(ctypes.byref(p), 1 << 30, None) == -1
+    bad = sg.params()
+    bad.list_max = 0
+    assert L.sogrand_serve_create(ctypes.byref(bad), 1 << 30, ctypes.byref(out)) == -1
+    assert not out.value
+    rid = ctypes.c_uint64()
+    code = sg.Code.ebch(32, 26)
+    assert L.sogrand_serve_submit(None, code.handle, ctypes.c_void_p(1), 0, ctypes.byref(rid)) == -1
+    res = (sg.sogrand_result_t * 2)()
+    n = ctypes.c_size_t()
+    assert L.sogrand_serve_poll(None, res, 2, ctypes.byref(n), None, 0) == -1
+    assert L.sogrand_serve_stats(None, None, None, None) == -1
+    assert L.sogrand_serve_destroy(None) == 0
+    assert L.sogrand_clock_ns() > 0
+    assert ctypes.sizeof(sg.sogrand_result_t) == 72   # the C layout (natural alignment)
