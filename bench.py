@@ -1,22 +1,37 @@
 #!/usr/bin/env python3
 """Benchmark of SOGRAND product-code decoding on one MI355X.
 
-Workload: the (4096, 3249) = [64,57]^2 eBCH product code over BPSK-AWGN at
-Eb/N0 = 2.5, 3.0 and 3.5 dB, 10^4 frames per Eb/N0 (seeds 1, 2, 3), list size
-L = 4, query cap 10^4, 6 row+column iterations, alpha = 0.5.  One step decodes
-all 3x10^4 frames (every step of the hot path: ranking, query loop, soft
-output, exchange, validity checks) with inputs already resident in HBM.
+Default workload (--workload product): the (4096, 3249) = [64,57]^2 eBCH
+product code over BPSK-AWGN at Eb/N0 = 2.5, 3.0 and 3.5 dB, 10^4 frames per
+Eb/N0 (seeds 1, 2, 3), list size L = 4, query cap 10^4, 6 row+column
+iterations, alpha = 0.5.  One step decodes all 3x10^4 frames (every step of
+the hot path: ranking, query loop, soft output, exchange, validity checks)
+with inputs already resident in HBM.
+
+Other workloads, each printing its own line:
+  mixed      3x10^4 frames, codes uniform over [32,26]^2, [64,57]^2, [128,120]^2,
+             Eb/N0 uniform in [2, 4] dB (seed 4), FP32 storage, L = 4, cap 10^5,
+             6 iterations: one persistent batched launch vs per-code plain calls.
+  component  2^20 independent [128,120] words at 4.0 dB (seed 5), cap 10^5,
+             L = 1 and 4, FP32 and FP64 storage.
+  serve      10^5 requests arriving as a Poisson process of rate 2x10^5/s
+             (seed 6), codes uniform over the three above, Eb/N0 uniform in
+             [2.5, 4.0] dB, FP32, L = 4, cap 10^5, 6 iterations, served by
+             continuous batching; p50/p99 latency from arrival to result.
 
 Prints one JSON line.  `value` is decoded information bits per second of the
-fastest form whose BLER matches the plain binary64 form at every Eb/N0.
+fastest form whose BLER matches the plain binary64 form (product workload).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -25,6 +40,9 @@ sys.path.insert(0, ROOT)
 PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # VALU lane-operations: 256 CUs x 64 lanes/clk x 2.4 GHz
 SNRS = ((2.5, 1), (3.0, 2), (3.5, 3))
 N, K, L, QCAP, ITERS = 64, 57, 4, 10000, 6
+MIX_CODES = ((32, 26), (64, 57), (128, 120))
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "product_pass_64x57_hbm_bytes.md")
+KERNEL_SOURCES = ("word.hpp", "decode.hip", "internal.hpp")
 
 
 def ops_per_word(n: int, lst: int) -> int:
@@ -38,6 +56,12 @@ def ops_per_word(n: int, lst: int) -> int:
     return 2 * n + n * lg + n + 3 * n + (2 * lst + 4) + n * (lst + 8) + 2 * n
 
 
+def algorithmic_ops(work: dict, n: int, lst: int) -> float:
+    """Per query: one syndrome XOR and one mass multiply per rank, plus the zero test and the
+    accumulation (2 + 2w); per word: ops_per_word."""
+    return work["words"] * ops_per_word(n, lst) + 2 * work["queries"] + 2 * work["ranks"]
+
+
 def wilson(k: int, n: int, z: float = 1.96):
     if n == 0:
         return (0.0, 1.0)
@@ -48,33 +72,111 @@ def wilson(k: int, n: int, z: float = 1.96):
     return (max(0.0, c - h), min(1.0, c + h))
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--frames", type=int, default=10000, help="frames per Eb/N0")
-    ap.add_argument("--cpu-frames", type=int, default=10000, help="oracle sample: frames per Eb/N0")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="plain_f64,plain_f32,batched_f64,batched_f32")
-    ap.add_argument("--tune", action="store_true",
-                    help="pick the batched launch shape by timing a few candidates on a sample first")
-    ap.add_argument("--no-count", action="store_true",
-                    help="skip the work-counting run (for profiler runs that average kernel durations)")
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="also run a device copy of this many MiB (HBM byte-counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(frames shard across GPUs with no communication; see the design notes).", file=sys.stderr)
-        return 2
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2310_10737_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
-    import numpy as np
+
+def recorded_traffic(form: str):
+    """HBM bytes per launch of the row/column pass kernel, from the committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    if not m or m.group(1) != kernel_digest():
+        return None
+    m = re.search(rf"bytes_per_launch\[{form}\]:\s*([0-9.eE+]+)", text)
+    return float(m.group(1)) if m else None
+
+
+def timed(step, steps, warmup, sg, count=True):
+    """Runs warmup steps, a work-counting step (separate: its atomics perturb timing), then the
+    timed steps under HIP-event profiling; returns (ms per step, kernel stats, work stats)."""
     import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    work = {}
+    if count:
+        sg.profile_begin(count_work=True)
+        step()
+        torch.cuda.synchronize()
+        work = sg.profile_end()
+    sg.profile_begin(count_work=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = sg.profile_end()
+    return (t1 - t0) * 1e3 / steps, kern, work
 
-    import paper_2310_10737_amd as sg
+
+def roofline(kname, label, kern, work, steps, n, lst, traffic=None):
+    kp, wk = kern.get(kname, {}), work.get(kname, {})
+    if not kp.get("launches") or not wk:
+        return None
+    avg_ms = kp["total_ms"] / kp["launches"]
+    launches_per_step = kp["launches"] / steps
+    ops_launch = algorithmic_ops(wk, n, lst) / launches_per_step
+    achieved = ops_launch / (avg_ms / 1e3) / 1e12
+    return dict(bound="alu", achieved=achieved, peak=PEAK_ALU_TOPS, unit="Top/s", frac=achieved / PEAK_ALU_TOPS,
+                traffic=traffic, kernel=label, avg_launch_ms=avg_ms, ops_per_launch=ops_launch,
+                words_per_step=wk["words"], queries_per_step=wk["queries"], ranks_per_step=wk["ranks"],
+                exact_rank_words_per_step=wk.get("exact_rank"))
+
+
+def base_line(args, metric, value, unit, ms, dtype, config, roof, cpu, **extra):
+    line = {
+        "metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    return line
+
+
+def _mixed_chunk(job):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
     import synth
+    nks, lo, hi, seed, a, b = job
+    with threadpool_limits(1):   # one BLAS thread per worker process
+        codes = [synth.ebch(*nk) for nk in nks]
+        cidx, eb, offs, llr, cw = synth.mixed_product_frames(codes, lo, hi, seed, np.arange(a, b))
+    return cidx, eb, offs, llr.astype(np.float32), cw
 
+
+def mixed_frames_f32(nks, lo, hi, seed, F, np):
+    """synth.mixed_product_frames over frames 0..F-1 with FP32 LLRs, generated by a process pool
+    in chunks of frames (each frame's values depend only on (seed, frame), so the result is the
+    same as one call).  Runs before the GPU is touched: the pool forks."""
+    import multiprocessing as mp
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    step = 1000
+    jobs = [(nks, lo, hi, seed, a, min(F, a + step)) for a in range(0, F, step)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_mixed_chunk, jobs)
+    cidx = np.concatenate([p[0] for p in parts])
+    eb = np.concatenate([p[1] for p in parts])
+    base, offs = 0, []
+    for p in parts:
+        offs.append(p[2] + base)
+        base += p[3].shape[0]
+    return cidx, eb, np.concatenate(offs), np.concatenate([p[3] for p in parts]), np.concatenate([p[4] for p in parts])
+
+
+# --------------------------------------------------------------------------------------------
+# product: [64,57]^2 at three Eb/N0, plain and batched forms
+# --------------------------------------------------------------------------------------------
+def bench_product(args, sg, np, torch, synth):
     dev = torch.device("cuda:0")
     code = synth.ebch(N, K)
     gcode = sg.Code.ebch(N, K)
@@ -92,7 +194,7 @@ def main() -> int:
     total = x64.shape[0]
     info_bits_per_step = total * K * K
 
-    def outputs(dt):
+    def outputs():
         return dict(
             hard=torch.empty((total, N, N), dtype=torch.uint8, device=dev), llr_app=None,
             success=torch.empty(total, dtype=torch.uint8, device=dev),
@@ -100,12 +202,8 @@ def main() -> int:
             sum_queries=torch.empty(total, dtype=torch.int64, device=dev),
             sum_max_queries=torch.empty(total, dtype=torch.int64, device=dev))
 
-    def run_plain(x, out):
-        sg.sogrand_decode_product(gcode, x, list_max=L, query_cap=QCAP, max_iter=ITERS, outputs=out)
-
     fcode = torch.zeros(total, dtype=torch.uint8, device=dev)
     foff = torch.arange(total, dtype=torch.int64, device=dev) * (N * N)
-    shape = sg.sched()
 
     def run_batched(x, out, sc):
         sg.sogrand_decode_batched([gcode], fcode, foff, x.view(-1), list_max=L, query_cap=QCAP, max_iter=ITERS,
@@ -115,14 +213,13 @@ def main() -> int:
         """Times candidate launch shapes on the first 3000 frames; returns the fastest."""
         m = min(3000, total)
         xs = x[:m].contiguous().view(-1)
-        fc, fo = fcode[:m], foff[:m]
         best = None
         for w, f, ch, g in [(8, 2, 1, 3), (4, 2, 1, 6), (8, 3, 1, 3), (4, 2, 1, 8), (8, 2, 2, 3), (4, 1, 1, 6)]:
             sc = sg.sched(w, f, ch, g)
-            sg.sogrand_decode_batched([gcode], fc, fo, xs, L, QCAP, ITERS, sched_=sc)
+            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, ITERS, sched_=sc)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sg.sogrand_decode_batched([gcode], fc, fo, xs, L, QCAP, ITERS, sched_=sc)
+            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, ITERS, sched_=sc)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             if best is None or dt < best[0]:
@@ -131,40 +228,20 @@ def main() -> int:
 
     forms = {}
     for form in args.forms.split(","):
-        if form == "plain_f64":
-            x, out = x64, outputs(torch.float64)
-            step = lambda: run_plain(x64, out)  # noqa: E731
-        elif form == "plain_f32":
-            x, out = x32, outputs(torch.float32)
-            step = lambda: run_plain(x32, out)  # noqa: E731
-        elif form in ("batched_f64", "batched_f32"):
-            x = x64 if form == "batched_f64" else x32
-            out = outputs(x.dtype)
+        x = x64 if form.endswith("f64") else x32
+        out = outputs()
+        if form.startswith("plain"):
+            step = (lambda x_, o_: lambda: sg.sogrand_decode_product(
+                gcode, x_, list_max=L, query_cap=QCAP, max_iter=ITERS, outputs=o_))(x, out)
+            sc = None
+        elif form.startswith("batched"):
             out["hard"] = out["hard"].view(-1)
             out["status"] = torch.zeros(1, dtype=torch.int32, device=dev)
-            sc = tune(x) if args.tune else shape
-            step = lambda: run_batched(x, out, sc)  # noqa: E731
+            sc = tune(x) if args.tune else sg.sched()
+            step = (lambda x_, o_, s_: lambda: run_batched(x_, o_, s_))(x, out, sc)
         else:
             raise SystemExit(f"unknown form {form}")
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        # work counted once in a separate run (the counters add atomics); decoding is deterministic
-        work = {}
-        if not args.no_count:
-            sg.profile_begin(count_work=True)
-            step()
-            torch.cuda.synchronize()
-            work = sg.profile_end()
-        sg.profile_begin(count_work=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        kern = sg.profile_end()
-        ms = (t1 - t0) * 1e3 / args.steps
+        ms, kern, work = timed(step, args.steps, args.warmup, sg, count=not args.no_count)
         if "status" in out and int(out["status"].item()) != 0:
             raise SystemExit(f"{form}: batched kernel reported status {int(out['status'].item())}")
         err = torch.any((out["hard"].view(total, N, N) != cw_all).view(total, -1), dim=1).cpu().numpy()
@@ -181,7 +258,7 @@ def main() -> int:
                 parallel_queries_per_bit=float(smq[sl].mean() / (N * N)))
         forms[form] = dict(ms_per_step=ms, info_bits_per_s=info_bits_per_step / (ms / 1e3),
                            per_snr=per_snr, kernels=kern, work=work)
-        if form.startswith("batched"):
+        if sc is not None:
             forms[form]["sched"] = dict(waves_per_group=sc.waves_per_group, frames_per_group=sc.frames_per_group,
                                         steal_chunk=sc.steal_chunk, groups_per_cu=sc.groups_per_cu)
 
@@ -198,26 +275,18 @@ def main() -> int:
         f["bler_matches_plain_f64"] = ok
         if ok and (best is None or f["info_bits_per_s"] > best["info_bits_per_s"]):
             best_name, best = name, f
+    for prec in ("f64", "f32"):
+        if f"plain_{prec}" in forms and f"batched_{prec}" in forms:
+            forms[f"batched_{prec}"]["speedup_vs_plain"] = (forms[f"plain_{prec}"]["ms_per_step"]
+                                                            / forms[f"batched_{prec}"]["ms_per_step"])
 
     # roofline of the dominant kernel of the chosen form: the row/column pass kernel of the
     # plain forms, the persistent kernel of the batched forms
-    kname = "batched" if best_name.startswith("batched") else "product_pass"
-    kp = best["kernels"].get(kname, {})
-    wk = best["work"].get(kname, {})
-    roof = None
-    if kp.get("launches") and wk:
-        avg_ms = kp["total_ms"] / kp["launches"]
-        launches_per_step = kp["launches"] / args.steps
-        ops_step = wk["words"] * ops_per_word(N, L) + 2 * wk["queries"] + 2 * wk["ranks"]
-        ops_launch = ops_step / launches_per_step
-        achieved = ops_launch / (avg_ms / 1e3) / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=PEAK_ALU_TOPS, unit="Top/s",
-                    frac=achieved / PEAK_ALU_TOPS, traffic=None,
-                    kernel="k_batched (persistent)" if kname == "batched" else
-                    "k_product_pass (row and column instantiations)",
-                    avg_launch_ms=avg_ms, ops_per_launch=ops_launch,
-                    words_per_step=wk["words"], queries_per_step=wk["queries"],
-                    ranks_per_step=wk["ranks"], exact_rank_words_per_step=wk.get("exact_rank"))
+    if best_name.startswith("batched"):
+        roof = roofline("batched", "k_batched (persistent)", best["kernels"], best["work"], args.steps, N, L)
+    else:
+        roof = roofline("product_pass", "k_product_pass (row and column instantiations)", best["kernels"],
+                        best["work"], args.steps, N, L, traffic=recorded_traffic(best_name))
 
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
@@ -239,28 +308,293 @@ def main() -> int:
         cpu = dict(value=sample.shape[0] * K * K / dt, unit="info bits/s", cores=threads, kind="oracle",
                    sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall")
 
-    line = {
-        "metric": "decoded info bits/s at matched BLER",
-        "value": best["info_bits_per_s"],
-        "unit": "info bits/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": best["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "eBCH [64,57]^2 product code, BPSK-AWGN 2.5/3.0/3.5 dB, 1e4 frames each, "
-                               "L=4, query cap 1e4, 6 iterations, alpha 0.5",
-                   "form": best_name, "frames_per_step": total, "info_bits_per_frame": K * K,
-                   "parallelism": "single GPU"},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "forms": {k: {kk: vv for kk, vv in v.items() if kk not in ("work",)} for k, v in forms.items()},
-        "p99_frame_latency_ms": None,
-    }
+    storage = "f32" if best_name.endswith("f32") else "f64"
+    config = {"workload": "eBCH [64,57]^2 product code, BPSK-AWGN 2.5/3.0/3.5 dB, 1e4 frames each, "
+                          "L=4, query cap 1e4, 6 iterations, alpha 0.5",
+              "form": best_name, "llr_storage": storage, "frames_per_step": total,
+              "info_bits_per_frame": K * K, "parallelism": "single GPU"}
+    return base_line(args, "decoded info bits/s at matched BLER", best["info_bits_per_s"], "info bits/s",
+                     best["ms_per_step"], "f64", config, roof, cpu,
+                     forms={k: {kk: vv for kk, vv in v.items() if kk != "work"} for k, v in forms.items()},
+                     p99_frame_latency_ms=None)
+
+
+# --------------------------------------------------------------------------------------------
+# mixed: one persistent launch over three codes vs per-code plain calls
+# --------------------------------------------------------------------------------------------
+def bench_mixed(args, sg, np, torch, synth):
+    dev = torch.device("cuda:0")
+    F, qcap = (args.frames if args.frames_set else 30000), (args.qcap or 100000)
+    codes = [synth.ebch(*nk) for nk in MIX_CODES]
+    cidx, eb, offs, llr, cw = mixed_frames_f32(MIX_CODES, 2.0, 4.0, 4, F, np)
+    gcodes = [sg.Code.ebch(*nk) for nk in MIX_CODES]
+    x = torch.from_numpy(llr).to(dev)
+    fc = torch.from_numpy(cidx).to(dev)
+    fo = torch.from_numpy(offs).to(dev)
+    info = int(sum(codes[c].k ** 2 for c in cidx))
+    groups = []
+    for c, code in enumerate(codes):
+        sel = np.nonzero(cidx == c)[0]
+        nn = code.n * code.n
+        idx = (offs[sel][:, None] + np.arange(nn)[None, :]).reshape(-1)
+        groups.append((c, sel, idx))
+    plain_in = [x[torch.from_numpy(idx).to(dev)].view(-1, codes[c].n, codes[c].n).contiguous()
+                for c, sel, idx in groups]
+
+    pouts = []
+
+    def plain_step():
+        pouts.clear()
+        for (c, sel, idx), xi in zip(groups, plain_in):
+            pouts.append(sg.sogrand_decode_product(gcodes[c], xi, list_max=L, query_cap=qcap, max_iter=ITERS))
+
+    bout = {}
+
+    def batched_step(sc):
+        bout.update(sg.sogrand_decode_batched(gcodes, fc, fo, x, list_max=L, query_cap=qcap, max_iter=ITERS,
+                                              sched_=sc))
+
+    # launch shape: the fastest of a few candidates on the first 2000 frames
+    m = min(2000, F)
+    end = int(offs[m - 1] + codes[cidx[m - 1]].n ** 2)
+    best = None
+    for w, f, ch, g in [(8, 2, 1, 3), (4, 2, 1, 6), (8, 4, 1, 2), (4, 2, 1, 4), (8, 2, 1, 2)]:
+        sc = sg.sched(w, f, ch, g)
+        t0 = time.perf_counter()
+        sg.sogrand_decode_batched(gcodes, fc[:m], fo[:m], x[:end], L, qcap, ITERS, sched_=sc)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if best is None or dt < best[0]:
+            best = (dt, sc)
+    sc = best[1]
+    ms_b, kern_b, work_b = timed(lambda: batched_step(sc), args.steps, args.warmup, sg, count=not args.no_count)
+    if int(bout["status"].item()) != 0:
+        raise SystemExit(f"batched kernel reported status {int(bout['status'].item())}")
+    ms_p, _, _ = timed(plain_step, args.steps, args.warmup, sg, count=False)
+    torch.cuda.synchronize()
+    same = True
+    bhard = bout["hard"].cpu().numpy()
+    bsucc = bout["success"].cpu().numpy()
+    bhalf = bout["half_iters"].double().cpu().numpy()
+    bq = bout["sum_queries"].double().cpu().numpy()
+    per_code = {}
+    for (c, sel, idx), po in zip(groups, pouts):
+        nn = codes[c].n ** 2
+        same &= bool(np.array_equal(bsucc[sel], po["success"].cpu().numpy()))
+        same &= bool(np.array_equal(bhard[idx], po["hard"].cpu().numpy().reshape(-1)))
+        err = np.any(bhard[idx].reshape(-1, nn) != cw[idx].reshape(-1, nn), axis=1)
+        k_err = int(err.sum())
+        per_code[f"[{codes[c].n},{codes[c].k}]^2"] = dict(
+            frames=int(sel.size), bler=k_err / max(1, sel.size), bler_ci95=wilson(k_err, int(sel.size)),
+            avg_iterations=float(bhalf[sel].mean() / 2), queries_per_bit=float(bq[sel].mean() / nn))
+    roof = None
+    kp, wk = kern_b.get("batched", {}), work_b.get("batched", {})
+    if kp.get("launches") and wk:
+        # ops per word depend on n: weight by each code's share of the decoded words
+        share = {c: float(bhalf[sel].sum()) * codes[c].n for c, sel, _ in groups}
+        tw = sum(share.values())
+        per_word = sum(ops_per_word(codes[c].n, L) * w for c, w in share.items()) / max(1.0, tw)
+        ops = wk["words"] * per_word + 2 * wk["queries"] + 2 * wk["ranks"]
+        avg_ms = kp["total_ms"] / kp["launches"]
+        ops_launch = ops / (kp["launches"] / args.steps)
+        achieved = ops_launch / (avg_ms / 1e3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=PEAK_ALU_TOPS, unit="Top/s", frac=achieved / PEAK_ALU_TOPS,
+                    traffic=None, kernel="k_batched (persistent)", avg_launch_ms=avg_ms, ops_per_launch=ops_launch,
+                    words_per_step=wk["words"], queries_per_step=wk["queries"], ranks_per_step=wk["ranks"])
+    cpu = None
+    if not args.no_cpu and args.cpu_frames > 0:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        cf = min(args.cpu_frames, F)
+        t0 = time.perf_counter()
+        bits = 0
+        for c, code in enumerate(codes):
+            sel = np.nonzero(cidx[:cf] == c)[0]
+            if sel.size == 0:
+                continue
+            nn = code.n * code.n
+            fr = np.stack([llr[o:o + nn] for o in offs[sel]]).astype(np.float64)
+            oracle.decode_product(code, fr.reshape(-1, code.n, code.n), L, qcap, ITERS, store_f32=True,
+                                  nthreads=threads)
+            bits += sel.size * code.k ** 2
+        dt = time.perf_counter() - t0
+        cpu = dict(value=bits / dt, unit="info bits/s", cores=threads, kind="oracle",
+                   sample=f"first {cf} frames of the mixed stream, {dt:.1f} s wall")
+    config = {"workload": "mixed eBCH product frames [32,26]^2/[64,57]^2/[128,120]^2 uniform, Eb/N0 U[2,4] dB, "
+                          f"{F} frames, L=4, query cap {qcap}, 6 iterations, FP32 storage",
+              "form": "batched_f32", "sched": dict(waves_per_group=sc.waves_per_group,
+                                                   frames_per_group=sc.frames_per_group,
+                                                   steal_chunk=sc.steal_chunk, groups_per_cu=sc.groups_per_cu),
+              "parallelism": "single GPU"}
+    return base_line(args, "decoded info bits/s (batched vs plain) at matched BLER", info / (ms_b / 1e3),
+                     "info bits/s", ms_b, "f64", config, roof, cpu,
+                     plain_f32=dict(ms_per_step=ms_p, info_bits_per_s=info / (ms_p / 1e3)),
+                     speedup_vs_plain=ms_p / ms_b, identical_to_plain=same, per_code=per_code)
+
+
+# --------------------------------------------------------------------------------------------
+# component: 2^20 independent [128,120] words
+# --------------------------------------------------------------------------------------------
+def bench_component(args, sg, np, torch, synth):
+    dev = torch.device("cuda:0")
+    W = args.words
+    qcap = args.qcap or 100000
+    code = synth.ebch(128, 120)
+    g = sg.Code.ebch(128, 120)
+    llr, cw, _ = synth.component_words(code, 4.0, 5, np.arange(W))
+    x64 = torch.from_numpy(llr).to(dev)
+    x32 = x64.float()
+    cwt = torch.from_numpy(cw).to(dev)
+    forms = {}
+    for name, x, lst in (("L4_f32", x32, 4), ("L1_f32", x32, 1), ("L4_f64", x64, 4), ("L1_f64", x64, 1)):
+        out = dict(llr_app=None, llr_ext=torch.empty_like(x),
+                   hard=torch.empty((W, 128), dtype=torch.uint8, device=dev),
+                   n_queries=torch.empty(W, dtype=torch.int32, device=dev), n_found=None, found_q=None,
+                   p_found=None, p_notfound=None)
+        step = (lambda x_, l_, o_: lambda: sg.sogrand_decode_component(g, x_, list_max=l_, query_cap=qcap,
+                                                                       outputs=o_))(x, lst, out)
+        ms, kern, work = timed(step, args.steps, args.warmup, sg, count=not args.no_count)
+        werr = torch.any(out["hard"] != cwt, dim=1).double().mean().item()
+        q = out["n_queries"].double()
+        forms[name] = dict(ms_per_step=ms, words_per_s=W / (ms / 1e3), info_bits_per_s=W * 120 / (ms / 1e3),
+                           queries_per_s=q.sum().item() / (ms / 1e3), mean_queries=q.mean().item(),
+                           max_queries=q.max().item(), word_error_rate=werr,
+                           roofline=roofline("component", "k_component", kern, work, args.steps, 128, lst))
+    head = forms["L4_f32"]
+    cpu = None
+    if not args.no_cpu and args.cpu_words > 0:
+        import oracle
+        m = min(args.cpu_words, W)
+        t0 = time.perf_counter()
+        oracle.decode_component(code, llr[:m].astype(np.float32).astype(np.float64), 4, qcap)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=m * 120 / dt, unit="info bits/s", cores=1, kind="oracle",
+                   sample=f"first {m} words, L=4, {dt:.1f} s wall")
+    config = {"workload": f"{W} independent eBCH [128,120] words, BPSK-AWGN 4.0 dB, query cap {qcap}, "
+                          "L=4 FP32 storage (L=1 and FP64 in forms)", "form": "L4_f32", "parallelism": "single GPU"}
+    return base_line(args, "decoded info bits/s (component words)", head["info_bits_per_s"], "info bits/s",
+                     head["ms_per_step"], "f64", config, head["roofline"], cpu, forms=forms)
+
+
+# --------------------------------------------------------------------------------------------
+# serve: open-loop Poisson arrivals through continuous batching
+# --------------------------------------------------------------------------------------------
+def bench_serve(args, sg, np, torch, synth):
+    R = args.requests
+    rate = args.rate
+    qcap = args.qcap or 100000
+    codes = [synth.ebch(*nk) for nk in MIX_CODES]
+    cidx, eb, offs, x, cw = mixed_frames_f32(MIX_CODES, 2.5, 4.0, 6, R, np)
+    gcodes = [sg.Code.ebch(*nk) for nk in MIX_CODES]
+    # exponential inter-arrival times from the counter generator (stream 3 of seed 6)
+    u = (synth.splitmix_stream(6, np.arange(R, dtype=np.uint64), 3, 1)[:, 0] >> np.uint64(11)).astype(np.float64)
+    arrival = np.cumsum(-np.log1p(-(u * 2.0 ** -53)) / rate)
+    arrival_ns = np.round((arrival - arrival[0]) * 1e9).astype(np.uint64)
+    budget = args.hbm_gib << 30
+    srv = sg.Server(budget, list_max=L, query_cap=qcap, max_iter=ITERS, precision=sg.SOGRAND_F32)
+    # build the codes' schedules and load the kernels with one frame of each code
+    for c in range(len(codes)):
+        f = int(np.nonzero(cidx == c)[0][0])
+        n = codes[c].n
+        srv.submit(gcodes[c], np.ascontiguousarray(x[offs[f]:offs[f] + n * n]), tag=0)
+    while srv.poll(max_results=8, timeout_ns=-1, want_hard=False):
+        pass
+    st0 = srv.stats()
+    results = []
+    t0 = sg.sogrand_clock_ns() + 20_000_000
+    fed = {}
+
+    def feed():
+        try:
+            fed["retries"] = srv.replay(gcodes, cidx, offs, x, arrival_ns, t0)
+        except Exception as e:   # reported by the main thread
+            fed["error"] = e
+
+    th = threading.Thread(target=feed)
+    th.start()
+    last_print = time.time()
+    while len(results) < R:
+        results.extend(srv.poll(max_results=1024, timeout_ns=50_000_000, want_hard=True))
+        if "error" in fed:
+            raise SystemExit(f"replay failed: {fed['error']}")
+        if time.time() - last_print > 30:
+            print(f"[serve] {len(results)}/{R} results", file=sys.stderr, flush=True)
+            last_print = time.time()
+    th.join()
+    st1 = srv.stats()
+    srv.close()
+    tags = np.array([r["user_tag"] for r in results])
+    done = np.array([r["t_done_ns"] for r in results], dtype=np.float64)
+    lat_ms = (done - (t0 + arrival_ns[tags].astype(np.float64))) / 1e6
+    span_s = (done.max() - t0) / 1e9
+    info = float(sum(codes[c].k ** 2 for c in cidx))
+    errs = np.zeros(R, dtype=bool)
+    for r in results:
+        f = r["user_tag"]
+        n = codes[cidx[f]].n
+        errs[f] = not np.array_equal(r["hard"].reshape(-1), cw[offs[f]:offs[f] + n * n])
+    per_code = {}
+    ctag = cidx[tags]
+    for c, code in enumerate(codes):
+        sel = cidx == c
+        k_err = int(errs[sel].sum())
+        per_code[f"[{code.n},{code.k}]^2"] = dict(
+            requests=int(sel.sum()), bler=k_err / max(1, int(sel.sum())), bler_ci95=wilson(k_err, int(sel.sum())),
+            p50_ms=float(np.percentile(lat_ms[ctag == c], 50)), p99_ms=float(np.percentile(lat_ms[ctag == c], 99)))
+    steps = st1["steps"] - st0["steps"]
+    config = {"workload": f"{R} requests, Poisson arrivals {rate:.0f}/s, eBCH [32,26]^2/[64,57]^2/[128,120]^2 "
+                          f"uniform, Eb/N0 U[2.5,4.0] dB, L=4, query cap {qcap}, 6 iterations, FP32 storage",
+              "hbm_budget_bytes": budget, "form": "served (continuous batching)", "parallelism": "single GPU"}
+    return base_line(args, "decoded info bits/s (served) and p99 frame latency", info / span_s, "info bits/s",
+                     span_s * 1e3, "f64", config, None, None,
+                     p50_frame_latency_ms=float(np.percentile(lat_ms, 50)),
+                     p99_frame_latency_ms=float(np.percentile(lat_ms, 99)),
+                     offered_info_bits_per_s=info / max(1e-9, float(arrival[-1] - arrival[0])),
+                     admission_retries=fed.get("retries"), serve_steps=steps,
+                     mean_step_ms=(st1["step_ms"] - st0["step_ms"]) / max(1, steps), per_code=per_code)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="product", choices=["product", "mixed", "component", "serve"])
+    ap.add_argument("--frames", type=int, default=None, help="frames per Eb/N0 (product) or in total (mixed)")
+    ap.add_argument("--words", type=int, default=1 << 20, help="component words")
+    ap.add_argument("--requests", type=int, default=100000, help="serving requests")
+    ap.add_argument("--rate", type=float, default=2e5, help="serving arrival rate (1/s)")
+    ap.add_argument("--hbm-gib", type=int, default=8, help="serving slot budget")
+    ap.add_argument("--qcap", type=int, default=None, help="query cap (mixed, component, serve)")
+    ap.add_argument("--cpu-frames", type=int, default=None, help="oracle sample: frames (per Eb/N0 for product)")
+    ap.add_argument("--cpu-words", type=int, default=1 << 14, help="oracle sample: component words")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--forms", default="plain_f64,plain_f32,batched_f64,batched_f32")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick the batched launch shape by timing a few candidates on a sample first")
+    ap.add_argument("--no-count", action="store_true",
+                    help="skip the work-counting run (for profiler runs that average kernel durations)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a device copy of this many MiB (HBM byte-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(frames shard across GPUs with no communication; see the design notes).", file=sys.stderr)
+        return 2
+    args.frames_set = args.frames is not None
+    if args.frames is None:
+        args.frames = 10000
+    if args.cpu_frames is None:
+        args.cpu_frames = {"product": 10000, "mixed": 240}.get(args.workload, 0)
+
+    import numpy as np
+    import torch
+
+    import paper_2310_10737_amd as sg
+    import synth
+
+    fn = dict(product=bench_product, mixed=bench_mixed, component=bench_component, serve=bench_serve)[args.workload]
+    line = fn(args, sg, np, torch, synth)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -244,6 +244,18 @@ int sogrand_serve_submit(sogrand_server_t *server, const sogrand_code_t *code, c
 int sogrand_serve_poll(sogrand_server_t *server, sogrand_result_t *results, size_t max_results,
                        size_t *n_results, uint8_t *hard_out_host, int64_t timeout_ns);
 
+/* Open-loop load generator for measurement: submits request i (code
+   codes[req_code[i]], LLRs at element offset req_offset[i] of llr_host, HOST
+   memory of llr_len elements) at time t0_ns + arrival_ns[i] on sogrand_clock_ns(), with user_tag i,
+   busy-waiting until it is due; a refused request (no free slot) is retried
+   until admitted, so its wait counts in its latency.  Blocks until every
+   request is submitted; results are taken with sogrand_serve_poll from another
+   thread meanwhile.  *retries (optional) counts refused attempts.
+   Errors: EINVAL, EDEVICE. */
+int sogrand_serve_replay(sogrand_server_t *server, const sogrand_code_t *const *codes, int ncodes, size_t nreq,
+                         const uint8_t *req_code, const uint64_t *req_offset, const void *llr_host,
+                         uint64_t llr_len, const uint64_t *arrival_ns, uint64_t t0_ns, uint64_t *retries);
+
 /* Counters since creation: steps run, frames finished, and the summed wall
    time of the steps (launch to completion). */
 int sogrand_serve_stats(sogrand_server_t *server, uint64_t *steps, uint64_t *frames, double *step_ms);

@@ -29,7 +29,7 @@ EXPORTS = [
     "sogrand_decode_component", "sogrand_decode_product",
     "sogrand_sched_default", "sogrand_decode_batched",
     "sogrand_clock_ns", "sogrand_serve_create", "sogrand_serve_submit", "sogrand_serve_poll",
-    "sogrand_serve_stats", "sogrand_serve_destroy",
+    "sogrand_serve_stats", "sogrand_serve_replay", "sogrand_serve_destroy",
     "sogrand_profile_begin", "sogrand_profile_end",
 ]
 
@@ -123,6 +123,7 @@ def lib():
     L.sogrand_serve_submit.argtypes = [P, P, P, ctypes.c_uint64, P]
     L.sogrand_serve_poll.argtypes = [P, P, SZ, P, P, ctypes.c_int64]
     L.sogrand_serve_stats.argtypes = [P, P, P, P]
+    L.sogrand_serve_replay.argtypes = [P, P, I, SZ, P, P, P, ctypes.c_uint64, P, ctypes.c_uint64, P]
     L.sogrand_serve_destroy.argtypes = [P]
     L.sogrand_profile_begin.argtypes = [I]
     L.sogrand_profile_end.argtypes = [P, I, P]
@@ -397,6 +398,24 @@ class Server:
                 d["hard"] = hard[r.hard_offset:r.hard_offset + nn].reshape(r.n, r.n).copy()
             out.append(d)
         return out
+
+    def replay(self, codes, req_code, req_offset, llr_host, arrival_ns, t0_ns):
+        """Submits a trace open-loop (see sogrand_serve_replay); returns the refused-attempt count.
+        Blocks; poll from another thread meanwhile (the call releases the GIL)."""
+        import numpy as np
+        req_code = np.ascontiguousarray(req_code, dtype=np.uint8)
+        req_offset = np.ascontiguousarray(req_offset, dtype=np.uint64)
+        arrival_ns = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+        want = np.float64 if self.precision == SOGRAND_F64 else np.float32
+        if llr_host.dtype != want or not llr_host.flags.c_contiguous:
+            raise ValueError(f"llr_host must be a C-contiguous {want.__name__} array")
+        handles = (ctypes.c_void_p * len(codes))(*[c.handle for c in codes])
+        retries = ctypes.c_uint64()
+        _check(lib().sogrand_serve_replay(
+            self._h, handles, len(codes), req_code.shape[0], ctypes.c_void_p(req_code.ctypes.data),
+            ctypes.c_void_p(req_offset.ctypes.data), ctypes.c_void_p(llr_host.ctypes.data), llr_host.size,
+            ctypes.c_void_p(arrival_ns.ctypes.data), int(t0_ns), ctypes.byref(retries)))
+        return retries.value
 
     def stats(self):
         st, fr, ms = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()

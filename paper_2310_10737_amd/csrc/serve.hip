@@ -610,6 +610,36 @@ int sogrand_serve_poll(sogrand_server_t *s, sogrand_result_t *results, size_t ma
     return SOGRAND_OK;
 }
 
+int sogrand_serve_replay(sogrand_server_t *s, const sogrand_code_t *const *codes, int ncodes, size_t nreq,
+                         const uint8_t *req_code, const uint64_t *req_offset, const void *llr_host,
+                         uint64_t llr_len, const uint64_t *arrival_ns, uint64_t t0_ns, uint64_t *retries) {
+    using namespace sg;
+    if (!s || !codes || ncodes < 1 || (nreq && (!req_code || !req_offset || !llr_host || !arrival_ns)))
+        return fail(SOGRAND_EINVAL, "server, codes, and the request arrays are required");
+    for (int i = 0; i < ncodes; i++)
+        if (!codes[i]) return fail(SOGRAND_EINVAL, "codes[%d] is NULL", i);
+    const char *base = static_cast<const char *>(llr_host);
+    uint64_t again = 0;
+    for (size_t i = 0; i < nreq; i++) {
+        if (req_code[i] >= ncodes) return fail(SOGRAND_EINVAL, "request %zu: code index out of range", i);
+        const uint64_t nn = (uint64_t)codes[req_code[i]]->n * codes[req_code[i]]->n;
+        if (req_offset[i] > llr_len || llr_len - req_offset[i] < nn)
+            return fail(SOGRAND_EINVAL, "request %zu: LLRs outside llr_host", i);
+        const uint64_t due = t0_ns + arrival_ns[i];
+        while (clock_ns() < due) {
+        }
+        for (;;) {
+            const int rc = sogrand_serve_submit(s, codes[req_code[i]], base + req_offset[i] * s->esz, i, nullptr);
+            if (rc == SOGRAND_OK) break;
+            if (rc != SOGRAND_EAGAIN) return rc;
+            again++;
+            std::this_thread::yield();
+        }
+    }
+    if (retries) *retries = again;
+    return SOGRAND_OK;
+}
+
 int sogrand_serve_stats(sogrand_server_t *s, uint64_t *steps, uint64_t *frames, double *step_ms) {
     if (!s) return sg::fail(SOGRAND_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);

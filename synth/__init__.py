@@ -293,19 +293,22 @@ def _check_code(code: Code) -> None:
         raise AssertionError(f"{code.name}: generator not systematic on info_pos")
 
 
+# Products of 0/1 matrices go through float32 BLAS: every sum is an integer of at
+# most 128, exact in float32, and its parity is taken afterwards.
+def _gf2_matmul(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    return (np.matmul(a.astype(np.float32), b.astype(np.float32)).astype(np.int64) & 1).astype(np.uint8)
+
+
 def encode(code: Code, info: np.ndarray) -> np.ndarray:
     """info (..., k) bits -> codewords (..., n) uint8."""
-    info = np.asarray(info, dtype=np.int64)
-    return ((info @ code.G.astype(np.int64)) & 1).astype(np.uint8)
+    return _gf2_matmul(np.asarray(info), code.G)
 
 
 def encode_product(code: Code, info: np.ndarray) -> np.ndarray:
     """info (F, k, k) -> product codewords (F, n, n): k rows first, then n columns."""
-    info = np.asarray(info, dtype=np.int64)
-    G = code.G.astype(np.int64)
-    rows = (info @ G) & 1                        # (F, k, n)
-    cols = (np.swapaxes(rows, -1, -2) @ G) & 1   # (F, n, n): [col j][row i]
-    return np.swapaxes(cols, -1, -2).astype(np.uint8)
+    rows = _gf2_matmul(np.asarray(info), code.G)                 # (F, k, n)
+    cols = _gf2_matmul(np.swapaxes(rows, -1, -2), code.G)        # (F, n, n): [col j][row i]
+    return np.ascontiguousarray(np.swapaxes(cols, -1, -2))
 
 
 # ----------------------------------------------------------------------------
