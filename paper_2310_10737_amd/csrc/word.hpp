@@ -30,13 +30,10 @@ constexpr int kWavesPerBlock = 4;            // init and check kernels
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kXcds = 8;                     // MI355X: workgroups are dealt to 8 XCDs in turn
 
-// Per-wave scratch.  The rank tables hs_r, rlo_r and rhi_r share one 4-byte
-// stride, so a rank's three lookups use one address register, and ranks below 32
-// fall in distinct LDS banks.
+// Per-wave scratch.  A rank's H column and rho share one 16-byte entry, so the
+// query loop reads both with one LDS instruction into an aligned register pair.
 struct WaveLds {
-    uint32_t hs_r[SOGRAND_NMAX + 4];     // H column by rank (1..n); [0] = 0 for zero padding
-    uint32_t rlo_r[SOGRAND_NMAX + 4];    // low and high words of rho by rank; [0] = 1.0
-    uint32_t rhi_r[SOGRAND_NMAX + 4];
+    uint4 ent_r[SOGRAND_NMAX + 4];       // by rank (1..n): rho (x, y), H column (z); [0]: rho 1, H 0
     uint64_t key_b[SOGRAND_NMAX + 2];    // |lambda| bit patterns by bit index, padded with ~0
     double tau_l[SOGRAND_LIST_MAX];      // prod rho of each found pattern
     uint4 pat_l[SOGRAND_LIST_MAX];       // found patterns (ranks)
@@ -400,21 +397,22 @@ __device__ __forceinline__ void mark_found(WaveLds &S, int found, int lane) {
 }
 
 __device__ __forceinline__ double rho_at(const WaveLds &S, int r) {
-    return __longlong_as_double((long long)(((uint64_t)S.rhi_r[r] << 32) | S.rlo_r[r]));
+    return __longlong_as_double((long long)(((uint64_t)S.ent_r[r].y << 32) | S.ent_r[r].x));
 }
 
 __device__ __forceinline__ void put_rho(WaveLds &S, int r, double v) {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
-    S.rlo_r[r] = (uint32_t)u;
-    S.rhi_r[r] = (uint32_t)(u >> 32);
+    S.ent_r[r].x = (uint32_t)u;
+    S.ent_r[r].y = (uint32_t)(u >> 32);
 }
 
 // One rank of a pattern: r is byte SH/8 of dword d.
 #define SG_RANK(d, SH)                                   \
     do {                                                 \
         const uint32_t r_ = ((d) >> (SH)) & 0xffu;       \
-        s ^= S.hs_r[r_];                                 \
-        tau *= rho_at(S, r_);                            \
+        const uint4 q_ = S.ent_r[r_];                    \
+        s ^= q_.z;                                       \
+        tau *= __longlong_as_double((long long)(((uint64_t)q_.y << 32) | q_.x)); \
     } while (0)
 
 // Decodes one word held as lam[slot] at bit index lane + 64*slot (< n).
@@ -517,14 +515,14 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
         if (valid[b]) {
-            S.hs_r[myrank[b]] = c.hcol[i];
+            S.ent_r[myrank[b]].z = c.hcol[i];
             put_rho(S, myrank[b], rho[b]);
             S.pi_r[myrank[b]] = (uint8_t)i;
         }
         if (i < SOGRAND_NMAX) S.zmask[i] = 0u;
     }
     if (lane == 0) {
-        S.hs_r[0] = 0u;
+        S.ent_r[0].z = 0u;
         put_rho(S, 0, 1.0);
     }
     wave_sync();
