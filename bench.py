@@ -542,6 +542,11 @@ def bench_serve(args, sg, np, torch, synth):
             requests=int(sel.sum()), bler=k_err / max(1, int(sel.sum())), bler_ci95=wilson(k_err, int(sel.sum())),
             p50_ms=float(np.percentile(lat_ms[ctag == c], 50)), p99_ms=float(np.percentile(lat_ms[ctag == c], 99)))
     steps = st1["steps"] - st0["steps"]
+    # frames finishing in one step share its completion time: the gaps between
+    # distinct completion times are step durations (plus any idle time)
+    ends = np.unique(done)
+    gaps_ms = np.diff(ends) / 1e6 if ends.size > 1 else np.zeros(1)
+    mid = (arrival_ns[tags] >= np.percentile(arrival_ns, 10)) & (arrival_ns[tags] <= np.percentile(arrival_ns, 90))
     config = {"workload": f"{R} requests, Poisson arrivals {rate:.0f}/s, eBCH [32,26]^2/[64,57]^2/[128,120]^2 "
                           f"uniform, Eb/N0 U[2.5,4.0] dB, L=4, query cap {qcap}, 6 iterations, FP32 storage",
               "hbm_budget_bytes": budget, "form": "served (continuous batching)", "parallelism": "single GPU"}
@@ -550,8 +555,12 @@ def bench_serve(args, sg, np, torch, synth):
                      p50_frame_latency_ms=float(np.percentile(lat_ms, 50)),
                      p99_frame_latency_ms=float(np.percentile(lat_ms, 99)),
                      offered_info_bits_per_s=info / max(1e-9, float(arrival[-1] - arrival[0])),
+                     p99_frame_latency_ms_middle_80pct_arrivals=float(np.percentile(lat_ms[mid], 99)),
+                     max_step_gap_ms=float(gaps_ms.max()), p99_step_gap_ms=float(np.percentile(gaps_ms, 99)),
                      admission_retries=fed.get("retries"), serve_steps=steps,
-                     mean_step_ms=(st1["step_ms"] - st0["step_ms"]) / max(1, steps), per_code=per_code)
+                     mean_step_ms=(st1["step_ms"] - st0["step_ms"]) / max(1, steps),
+                     max_step_ms=st1["max_step_ms"], max_frames_per_step=st1["max_active"],
+                     host_ms_between_steps=st1["host_ms"] - st0["host_ms"], per_code=per_code)
 
 
 def main() -> int:

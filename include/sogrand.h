@@ -256,9 +256,18 @@ int sogrand_serve_replay(sogrand_server_t *server, const sogrand_code_t *const *
                          const uint8_t *req_code, const uint64_t *req_offset, const void *llr_host,
                          uint64_t llr_len, const uint64_t *arrival_ns, uint64_t t0_ns, uint64_t *retries);
 
-/* Counters since creation: steps run, frames finished, and the summed wall
-   time of the steps (launch to completion). */
-int sogrand_serve_stats(sogrand_server_t *server, uint64_t *steps, uint64_t *frames, double *step_ms);
+/* Counters since creation. */
+typedef struct {
+    uint64_t steps;        /* steps run                                          */
+    uint64_t frames;       /* frames finished                                    */
+    uint64_t max_active;   /* most frames advanced by one step                   */
+    double step_ms;        /* summed step time, first launch to completion       */
+    double max_step_ms;    /* longest step                                       */
+    double host_ms;        /* summed host time outside steps while work was admitted
+                              (admission, result hand-off)                       */
+} sogrand_serve_stats_t;
+
+int sogrand_serve_stats(sogrand_server_t *server, sogrand_serve_stats_t *stats);
 
 /* Finishes every admitted request, then releases the server; results not
    taken are discarded. */

@@ -81,6 +81,17 @@ class sogrand_result_t(ctypes.Structure):
     ]
 
 
+class sogrand_serve_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_uint64),
+        ("frames", ctypes.c_uint64),
+        ("max_active", ctypes.c_uint64),
+        ("step_ms", ctypes.c_double),
+        ("max_step_ms", ctypes.c_double),
+        ("host_ms", ctypes.c_double),
+    ]
+
+
 class sogrand_params_t(ctypes.Structure):
     _fields_ = [
         ("list_max", ctypes.c_int),
@@ -122,7 +133,7 @@ def lib():
     L.sogrand_serve_create.argtypes = [P, SZ, P]
     L.sogrand_serve_submit.argtypes = [P, P, P, ctypes.c_uint64, P]
     L.sogrand_serve_poll.argtypes = [P, P, SZ, P, P, ctypes.c_int64]
-    L.sogrand_serve_stats.argtypes = [P, P, P, P]
+    L.sogrand_serve_stats.argtypes = [P, P]
     L.sogrand_serve_replay.argtypes = [P, P, I, SZ, P, P, P, ctypes.c_uint64, P, ctypes.c_uint64, P]
     L.sogrand_serve_destroy.argtypes = [P]
     L.sogrand_profile_begin.argtypes = [I]
@@ -418,9 +429,9 @@ class Server:
         return retries.value
 
     def stats(self):
-        st, fr, ms = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
-        _check(lib().sogrand_serve_stats(self._h, ctypes.byref(st), ctypes.byref(fr), ctypes.byref(ms)))
-        return dict(steps=st.value, frames=fr.value, step_ms=ms.value)
+        st = sogrand_serve_stats_t()
+        _check(lib().sogrand_serve_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in st._fields_}
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

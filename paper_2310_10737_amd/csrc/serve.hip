@@ -263,8 +263,8 @@ struct sogrand_server {
     uint64_t next_id = 1;
     bool stop = false;
     int error = SOGRAND_OK;
-    uint64_t steps = 0, frames = 0;
-    double step_ms = 0.0;
+    sogrand_serve_stats_t stats{};
+    uint64_t last_step_end = 0;   // clock at the end of the previous step (0: idle)
     std::thread worker;
 
     void run();
@@ -392,9 +392,14 @@ int sogrand_server::step(std::vector<Req> &active) {
             if (is_done[i]) free_slots[active[i].wclass].push_back(active[i].slot);
         for (Done &d : fin) done.push_back(std::move(d));
         in_flight -= fin.size();
-        steps += 1;
-        frames += fin.size();
-        step_ms += (double)(t1 - t0) * 1e-6;
+        const double ms = (double)(t1 - t0) * 1e-6;
+        stats.steps += 1;
+        stats.frames += fin.size();
+        stats.step_ms += ms;
+        if (ms > stats.max_step_ms) stats.max_step_ms = ms;
+        if (nact > stats.max_active) stats.max_active = nact;
+        if (last_step_end) stats.host_ms += (double)(t0 - last_step_end) * 1e-6;
+        last_step_end = keep.empty() ? 0 : clock_ns();
     }
     active.swap(keep);
     if (!fin.empty()) cv_done.notify_all();
@@ -640,12 +645,10 @@ int sogrand_serve_replay(sogrand_server_t *s, const sogrand_code_t *const *codes
     return SOGRAND_OK;
 }
 
-int sogrand_serve_stats(sogrand_server_t *s, uint64_t *steps, uint64_t *frames, double *step_ms) {
-    if (!s) return sg::fail(SOGRAND_EINVAL, "server is NULL");
+int sogrand_serve_stats(sogrand_server_t *s, sogrand_serve_stats_t *stats) {
+    if (!s || !stats) return sg::fail(SOGRAND_EINVAL, "server and stats are required");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (steps) *steps = s->steps;
-    if (frames) *frames = s->frames;
-    if (step_ms) *step_ms = s->step_ms;
+    *stats = s->stats;
     return SOGRAND_OK;
 }
 

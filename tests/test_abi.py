@@ -162,7 +162,7 @@ def test_serving_rejects_bad_arguments_before_device_work(sg):
     res = (sg.sogrand_result_t * 2)()
     n = ctypes.c_size_t()
     assert L.sogrand_serve_poll(None, res, 2, ctypes.byref(n), None, 0) == -1
-    assert L.sogrand_serve_stats(None, None, None, None) == -1
+    assert L.sogrand_serve_stats(None, None) == -1
     assert L.sogrand_serve_destroy(None) == 0
     assert L.sogrand_clock_ns() > 0
     assert ctypes.sizeof(sg.sogrand_result_t) == 72   # the C layout (natural alignment)
