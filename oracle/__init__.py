@@ -46,10 +46,10 @@ def lib():
         L.oracle_code_is_even.argtypes = [ctypes.c_int, ctypes.c_int, P]
         L.oracle_decode_component.restype = ctypes.c_int
         L.oracle_decode_component.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_long, P,
-                                              ctypes.c_int, ctypes.c_long] + [P] * 10
+                                              ctypes.c_int, ctypes.c_long, ctypes.c_double] + [P] * 10
         L.oracle_decode_product.restype = ctypes.c_int
         L.oracle_decode_product.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_long, P,
-                                            ctypes.c_int, ctypes.c_long, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int]
         _lib = L
     return _lib
@@ -81,8 +81,11 @@ def code_is_even(code) -> bool:
 
 
 def decode_component(code, llr, list_max: int = 4, qcap: int = 1000, want_z: bool = False,
-                     want_diag: bool = False):
-    """SISO SOGRAND decode of each row of llr (W, n) float64 (lambda = L_Ch + L_A)."""
+                     want_diag: bool = False, pstop: float = 0.0):
+    """SISO SOGRAND decode of each row of llr (W, n) float64 (lambda = L_Ch + L_A).
+
+    pstop > 0 ends a word's search once the predicted list-BLER of the list found so
+    far is below pstop."""
     llr = np.ascontiguousarray(llr, dtype=np.float64)
     W, n = llr.shape
     assert n == code.n
@@ -95,7 +98,7 @@ def decode_component(code, llr, list_max: int = 4, qcap: int = 1000, want_z: boo
         diag=np.zeros((W, 4)) if want_diag else None,
     )
     rc = lib().oracle_decode_component(
-        code.n, code.k, _p(_hcols(code)), W, _p(llr), list_max, qcap,
+        code.n, code.k, _p(_hcols(code)), W, _p(llr), list_max, qcap, float(pstop),
         _p(out["llr_app"]), _p(out["llr_ext"]), _p(out["hard"]), _p(out["n_queries"]),
         _p(out["n_found"]), _p(out["found_q"]), _p(out["p_found"]), _p(out["p_notfound"]),
         _p(out["found_z"]), _p(out["diag"]))
@@ -106,7 +109,7 @@ def decode_component(code, llr, list_max: int = 4, qcap: int = 1000, want_z: boo
 
 def decode_product(code, llr_ch, list_max: int = 4, qcap: int = 1000, max_iter: int = 4,
                    alpha: float = 0.5, early_stop: bool = True, store_f32: bool = False,
-                   want_app: bool = False, nthreads: int = 1):
+                   want_app: bool = False, nthreads: int = 1, pstop: float = 0.0):
     """Block-turbo decode of frames llr_ch (F, n, n) float64."""
     llr_ch = np.ascontiguousarray(llr_ch, dtype=np.float64)
     F, n, n2 = llr_ch.shape
@@ -117,7 +120,7 @@ def decode_product(code, llr_ch, list_max: int = 4, qcap: int = 1000, max_iter: 
         sum_queries=np.zeros(F, np.uint64), sum_max_queries=np.zeros(F, np.uint64),
     )
     rc = lib().oracle_decode_product(
-        code.n, code.k, _p(_hcols(code)), F, _p(llr_ch), list_max, qcap, max_iter, alpha,
+        code.n, code.k, _p(_hcols(code)), F, _p(llr_ch), list_max, qcap, float(pstop), max_iter, alpha,
         int(early_stop), int(store_f32), _p(out["hard"]), _p(out["llr_app"]), _p(out["success"]),
         _p(out["half_iters"]), _p(out["sum_queries"]), _p(out["sum_max_queries"]), nthreads)
     if rc:

@@ -32,6 +32,11 @@
  *  - The per-bit soft input in eq. (LLRi) is the SISO input L_Ch + L_A.
  *  - L_APP is clamped to [-1000, 1000] (reached only when a probability is
  *    exactly zero); a zero LLR decides bit 0.
+ *  - List-BLER stop (the figures' "lists are added to until L or the predicted
+ *    list-BLER is below tau"): after each codeword found before the L-th, the
+ *    not-found probability of Corollary 1 is evaluated for the list so far, with
+ *    the mass tested up to and including that codeword's query; the search ends
+ *    when it is below tau (tau = 0: never).  The comparison is in binary64.
  *  - Product decoding (Sec. "Iterative decoding"): L_A = 0; half-iteration h
  *    decodes all rows (h odd) or all columns (h even) of L_Ch + L_A; the hard
  *    decision of L_APP is checked after every half-iteration (all rows and
@@ -262,7 +267,7 @@ static void scratch_free(oscratch *s) {
 }
 
 static void decode_word(const ocode *c, const oorders *os, const double *lam, int L, long qcap,
-                        oscratch *sc, const oword_out *out) {
+                        double pstop, oscratch *sc, const oword_out *out) {
     const int n = c->n;
     /* 1. hard decision: bit 1 iff the LLR log p(0)/p(1) is negative */
     uint8_t y[ONMAX];
@@ -286,14 +291,33 @@ static void decode_word(const ocode *c, const oorders *os, const double *lam, in
         p0 *= 1.0L / (1.0L + sc->rho[i]);
     }
 
-    /* 5. GRAND query loop in ORBGRAND order, parity-matched for even codes */
-    const oorder *ord = c->even ? &os->ord[ypar] : &os->ord[0];
+    /* 5. mass of the hard decision's parity class (needed by Corollary 1, and by
+          the list-BLER stop inside the loop).  It is p0 * (1[zero in class] + E or
+          O), where E and O are the sums of prod rho over nonzero even / odd subsets,
+          obtained by adding bits one at a time: E' = E + O rho_i, O' = O + (1 + E) rho_i. */
     const int zero_in_class = c->even ? (ypar == 0) : 1;
+    long double E = 0.0L, O = 0.0L;
+    for (int i = 0; i < n; i++) {
+        long double e2 = E + O * sc->rho[i];
+        long double o2 = O + (1.0L + E) * sc->rho[i];
+        E = e2; O = o2;
+    }
+    const long double T_nz = c->even ? (ypar ? O : E) : (E + O);
+    long double phi;
+    if (c->even) phi = (ldexpl(1.0L, c->k) - 1.0L) / (ldexpl(1.0L, n - 1) - 1.0L);
+    else         phi = (ldexpl(1.0L, c->k) - 1.0L) / (ldexpl(1.0L, n) - 1.0L);
+
+    /* 6. GRAND query loop in ORBGRAND order, parity-matched for even codes.  It
+          stops at the L-th codeword, at the cap, or (pstop > 0) as soon as the
+          list-BLER predicted by Corollary 1 for the list so far, with the mass
+          tested up to this codeword, is below pstop; that test is taken in binary64. */
+    const oorder *ord = c->even ? &os->ord[ypar] : &os->ord[0];
     long t = 0;
+    int stopped = 0;
     int found = 0;
     long double S_nz = 0.0L;   /* sum of p(z)/p0 over tested nonzero patterns */
     int zero_tested = 0;
-    while (t < ord->count && t < qcap && found < L) {
+    while (t < ord->count && t < qcap && found < L && !stopped) {
         const uint8_t *u = ord->ranks + ord->off[t];
         int w = (int)(ord->off[t + 1] - ord->off[t]);
         uint64_t s = s0;
@@ -312,31 +336,25 @@ static void decode_word(const ocode *c, const oorders *os, const double *lam, in
             sc->pz[found] = p0 * tau;
             if (out->found_q) out->found_q[found] = (uint32_t)t;
             found++;
+            if (pstop > 0.0 && found < L) {
+                long double Mi = p0 * ((long double)(zero_in_class - zero_tested) + (T_nz - S_nz));
+                if (Mi < 0.0L) Mi = 0.0L;
+                long double Di = Mi * phi;
+                for (int l = 0; l < found; l++) Di += sc->pz[l];
+                if ((double)((Mi * phi) / Di) < pstop) stopped = 1;
+            }
         }
     }
     const long Q = t;
 
-    /* 6. not-found mass and block soft output (Corollary 1).  The mass of the
-          parity class is p0 * (1[zero in class] + E or O), where E and O are the
-          sums of prod rho over nonzero even / odd subsets, obtained by adding
-          bits one at a time: E' = E + O rho_i, O' = O + (1 + E) rho_i. */
-    long double E = 0.0L, O = 0.0L;
-    for (int i = 0; i < n; i++) {
-        long double e2 = E + O * sc->rho[i];
-        long double o2 = O + (1.0L + E) * sc->rho[i];
-        E = e2; O = o2;
-    }
-    long double T_nz = c->even ? (ypar ? O : E) : (E + O);
+    /* 7. not-found mass and block soft output (Corollary 1) */
     long double M = p0 * ((long double)(zero_in_class - zero_tested) + (T_nz - S_nz));
     if (M < 0.0L) M = 0.0L;
-    long double phi;
-    if (c->even) phi = (ldexpl(1.0L, c->k) - 1.0L) / (ldexpl(1.0L, n - 1) - 1.0L);
-    else         phi = (ldexpl(1.0L, c->k) - 1.0L) / (ldexpl(1.0L, n) - 1.0L);
     long double D = M * phi;
     for (int l = 0; l < found; l++) D += sc->pz[l];
     long double Pnf = (M * phi) / D;
 
-    /* 7. bitwise soft output, eq. (LLRi), and the extrinsic LLR */
+    /* 8. bitwise soft output, eq. (LLRi), and the extrinsic LLR */
     for (int i = 0; i < n; i++) {
         long double N0 = 0.0L, N1 = 0.0L;
         for (int l = 0; l < found; l++) {
@@ -373,13 +391,13 @@ static void decode_word(const ocode *c, const oorders *os, const double *lam, in
    found_q/p_found are [nwords][list_max]; entries past n_found are left zero.
    found_z ([nwords][list_max][n]) and diag ([nwords][4]) may be NULL. */
 int oracle_decode_component(int n, int k, const uint64_t *hcols, long nwords, const double *llr,
-                            int list_max, long qcap,
+                            int list_max, long qcap, double pstop,
                             double *llr_app, double *llr_ext, uint8_t *hard,
                             uint32_t *n_queries, int32_t *n_found, uint32_t *found_q,
                             double *p_found, double *p_notfound, uint8_t *found_z, double *diag) {
     ocode c;
     if (code_init(&c, n, k, hcols)) return -1;
-    if (list_max < 1 || qcap < 1) return -1;
+    if (list_max < 1 || qcap < 1 || !(pstop >= 0.0 && pstop <= 1.0)) return -1;
     oorders os;
     orders_build(&os, &c, qcap);
     oscratch sc;
@@ -399,7 +417,7 @@ int oracle_decode_component(int n, int k, const uint64_t *hcols, long nwords, co
         memset(o.found_q, 0, sizeof(uint32_t) * list_max);
         memset(o.p_found, 0, sizeof(double) * list_max);
         if (o.found_z) memset(o.found_z, 0, (size_t)list_max * n);
-        decode_word(&c, &os, llr + wd * n, list_max, qcap, &sc, &o);
+        decode_word(&c, &os, llr + wd * n, list_max, qcap, pstop, &sc, &o);
     }
     scratch_free(&sc);
     orders_free(&os);
@@ -416,6 +434,7 @@ typedef struct {
     const double *llr_ch;
     int list_max, max_iter, early_stop, store_f32;
     long qcap;
+    double pstop;
     double alpha;
     uint8_t *hard;
     double *llr_app;
@@ -451,7 +470,7 @@ static void decode_frame(const oprod_job *J, long f, oscratch *sc, double *LA, d
             }
             uint32_t q; int32_t nf; double pnf;
             oword_out o = { app, ext, hd, &q, &nf, fq, pf, &pnf, NULL, NULL };
-            decode_word(c, J->os, lam, J->list_max, J->qcap, sc, &o);
+            decode_word(c, J->os, lam, J->list_max, J->qcap, J->pstop, sc, &o);
             sq += q;
             if (q > qmax) qmax = q;
             for (int j = 0; j < n; j++) {
@@ -512,15 +531,15 @@ static void *prod_worker(void *arg) {
    store_f32 != 0 stores the exchanged a-priori LLRs in binary32 (the caller
    passes binary32-representable channel LLRs).  llr_app may be NULL. */
 int oracle_decode_product(int n, int k, const uint64_t *hcols, long nframes, const double *llr_ch,
-                          int list_max, long qcap, int max_iter, double alpha, int early_stop,
+                          int list_max, long qcap, double pstop, int max_iter, double alpha, int early_stop,
                           int store_f32, uint8_t *hard, double *llr_app, uint8_t *success,
                           uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq, int nthreads) {
     ocode c;
     if (code_init(&c, n, k, hcols)) return -1;
-    if (list_max < 1 || qcap < 1 || max_iter < 1) return -1;
+    if (list_max < 1 || qcap < 1 || max_iter < 1 || !(pstop >= 0.0 && pstop <= 1.0)) return -1;
     oorders os;
     orders_build(&os, &c, qcap);
-    oprod_job J = { &c, &os, nframes, llr_ch, list_max, max_iter, early_stop, store_f32, qcap, alpha,
+    oprod_job J = { &c, &os, nframes, llr_ch, list_max, max_iter, early_stop, store_f32, qcap, pstop, alpha,
                     hard, llr_app, success, half_iters, sum_q, sum_maxq, 0 };
     if (nthreads < 1) nthreads = 1;
     if (nthreads == 1) {
