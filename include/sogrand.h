@@ -100,10 +100,14 @@ typedef struct {
     int max_iter;       /* product codes: full row+column iterations, 1..1000     */
     int early_stop;     /* product codes: stop once the hard decision is valid    */
     int precision;      /* SOGRAND_F64 or SOGRAND_F32 LLR storage                 */
+    double list_bler_stop; /* 0 (off) or a threshold in (0, 1]: a word's search also
+                           ends after a codeword whose list so far has a predicted
+                           list-BLER (Corollary 1, with the mass tested up to that
+                           query) below it; the paper's figures use 1e-4..1e-6 */
 } sogrand_params_t;
 
 /* Fills the paper's settings: L = 4, cap 1000, alpha 0.5, 4 iterations,
-   early stop on, binary64 storage. */
+   early stop on, binary64 storage, no list-BLER stop. */
 void sogrand_params_default(sogrand_params_t *p);
 
 /* ------------------------------------------------------------------------ */

@@ -100,6 +100,7 @@ class sogrand_params_t(ctypes.Structure):
         ("max_iter", ctypes.c_int),
         ("early_stop", ctypes.c_int),
         ("precision", ctypes.c_int),
+        ("list_bler_stop", ctypes.c_double),
     ]
 
 
@@ -205,10 +206,12 @@ def profile_end():
                                          exact_rank=arr[i].exact_rank) for i in range(n.value)}
 
 
-def params(list_max=4, query_cap=1000, alpha=0.5, max_iter=4, early_stop=True, precision=SOGRAND_F64):
+def params(list_max=4, query_cap=1000, alpha=0.5, max_iter=4, early_stop=True, precision=SOGRAND_F64,
+           list_bler_stop=0.0):
     p = sogrand_params_t()
     p.list_max, p.query_cap, p.alpha = int(list_max), int(query_cap), float(alpha)
     p.max_iter, p.early_stop, p.precision = int(max_iter), int(bool(early_stop)), int(precision)
+    p.list_bler_stop = float(list_bler_stop)
     return p
 
 
@@ -232,7 +235,7 @@ def _precision_of(t):
 
 
 def sogrand_decode_component(code: Code, llr_in, list_max=4, query_cap=1000, found_z=False,
-                             outputs=None, stream=None):
+                             outputs=None, stream=None, list_bler_stop=0.0):
     """Component SISO decode of llr_in (W, n) on its device; returns a dict of tensors.
 
     ``outputs`` may pre-supply any output tensor by name (llr_app, llr_ext, hard,
@@ -258,7 +261,7 @@ def sogrand_decode_component(code: Code, llr_in, list_max=4, query_cap=1000, fou
     )
     if outputs:
         out.update(outputs)
-    p = params(list_max=L, query_cap=query_cap, precision=_precision_of(llr_in))
+    p = params(list_max=L, query_cap=query_cap, precision=_precision_of(llr_in), list_bler_stop=list_bler_stop)
     _check(lib().sogrand_decode_component(
         code.handle, ctypes.byref(p), W, _ptr(llr_in), _ptr(out["llr_app"]), _ptr(out["llr_ext"]),
         _ptr(out["hard"]), _ptr(out["n_queries"]), _ptr(out["n_found"]), _ptr(out["found_q"]),
@@ -267,7 +270,7 @@ def sogrand_decode_component(code: Code, llr_in, list_max=4, query_cap=1000, fou
 
 
 def sogrand_decode_product(code: Code, llr_ch, list_max=4, query_cap=1000, max_iter=4, alpha=0.5,
-                           early_stop=True, want_app=False, outputs=None, stream=None):
+                           early_stop=True, want_app=False, outputs=None, stream=None, list_bler_stop=0.0):
     """Block-turbo decode of frames llr_ch (F, n, n); returns a dict of tensors."""
     import torch
     if not llr_ch.is_cuda or not llr_ch.is_contiguous() or llr_ch.dim() != 3 or \
@@ -286,7 +289,7 @@ def sogrand_decode_product(code: Code, llr_ch, list_max=4, query_cap=1000, max_i
     if outputs:
         out.update(outputs)
     p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
-               early_stop=early_stop, precision=_precision_of(llr_ch))
+               early_stop=early_stop, precision=_precision_of(llr_ch), list_bler_stop=list_bler_stop)
     _check(lib().sogrand_decode_product(
         code.handle, ctypes.byref(p), F, _ptr(llr_ch), _ptr(out["hard"]), _ptr(out["llr_app"]),
         _ptr(out["success"]), _ptr(out["half_iters"]), _ptr(out["sum_queries"]),
@@ -317,7 +320,7 @@ def pack_frames(frames):
 
 
 def sogrand_decode_batched(codes, frame_code, frame_offset, llr, list_max=4, query_cap=1000, max_iter=4,
-                           alpha=0.5, early_stop=True, sched_=None, outputs=None, stream=None):
+                           alpha=0.5, early_stop=True, sched_=None, outputs=None, stream=None, list_bler_stop=0.0):
     """Batched decode of product frames of mixed codes in one persistent launch.
 
     codes: list of Code; frame_code: (F,) uint8 CUDA tensor of indices into codes;
@@ -344,7 +347,7 @@ def sogrand_decode_batched(codes, frame_code, frame_offset, llr, list_max=4, que
         out.update(outputs)
     handles = (ctypes.c_void_p * len(codes))(*[c.handle for c in codes])
     p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
-               early_stop=early_stop, precision=_precision_of(llr))
+               early_stop=early_stop, precision=_precision_of(llr), list_bler_stop=list_bler_stop)
     sc = sched_ if sched_ is not None else sched()
     _check(lib().sogrand_decode_batched(
         handles, len(codes), ctypes.byref(p), F, _ptr(frame_code), _ptr(frame_offset), llr.numel(),
@@ -366,11 +369,11 @@ class Server:
     """
 
     def __init__(self, hbm_budget_bytes, list_max=4, query_cap=1000, max_iter=4, alpha=0.5, early_stop=True,
-                 precision=SOGRAND_F32):
+                 precision=SOGRAND_F32, list_bler_stop=0.0):
         self._h = ctypes.c_void_p()
         self.precision = precision
         p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
-                   early_stop=early_stop, precision=precision)
+                   early_stop=early_stop, precision=precision, list_bler_stop=list_bler_stop)
         _check(lib().sogrand_serve_create(ctypes.byref(p), int(hbm_budget_bytes), ctypes.byref(self._h)))
 
     def submit(self, code: Code, llr_host, tag: int = 0):

@@ -28,6 +28,7 @@ struct BatchArgs {
     int ncodes;
     int L;
     uint32_t qcap;
+    double pstop;                   // list-BLER stop threshold, 0 = off
     double alpha;
     int max_iter;
     int early_stop;
@@ -146,7 +147,7 @@ __device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, 
 }
 
 // Decodes line `line` of the slot's frame in half-iteration h (rows for odd h).
-template <typename T, int NS>
+template <typename T, int NS, bool STOP>
 __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl, const DevCode &c,
                                                 const DevCode *cdev, int frame,
                                                 int h, int line, T *la, WaveLds &S, int lane) {
@@ -165,7 +166,8 @@ __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl,
         lam[b] = i < n ? (double)ch[pos[b]] + (h > 1 ? (double)la[pos[b]] : 0.0) : 0.0;
     }
     double lapp[NB];
-    const WordStats st = decode_word<NS, true>(c, cdev, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    const WordStats st = decode_word<NS, true, STOP>(c, cdev, a.L, a.qcap, a.pstop, lam, S, lapp, lane,
+                                                     a.prof != nullptr);
     uint64_t hm[2] = {0ull, 0ull};
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -187,7 +189,7 @@ __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl,
 // NSMAX: 64 when every code of the batch has n <= 64, else 128; the narrower
 // instantiation compiles without the wide-word path and keeps more waves resident
 // (six per SIMD, 80 registers, no spills; measured faster than five or seven).
-template <typename T, int WPB, int NSMAX>
+template <typename T, int WPB, int NSMAX, bool STOP>
 __global__ __launch_bounds__(kWave * WPB) __attribute__((amdgpu_waves_per_eu(NSMAX > 64 ? 4 : 6)))
 void k_batched(BatchArgs a) {
     __shared__ WaveLds wl[WPB];
@@ -254,8 +256,8 @@ void k_batched(BatchArgs a) {
         uint32_t qmax = 0;
         for (int line = first; line < last; line++) {
             WordStats st;
-            if (NSMAX == 64 || n <= 64) st = batch_line<T, 64>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
-            else st = batch_line<T, 128>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
+            if (NSMAX == 64 || n <= 64) st = batch_line<T, 64, STOP>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
+            else st = batch_line<T, 128, STOP>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
             if (a.prof && lane == 0) prof_add(a.prof, st);
             qsum += st.Q;
             qmax = st.Q > qmax ? st.Q : qmax;
@@ -303,23 +305,30 @@ __global__ void k_batched_status(const uint32_t *error, uint32_t *status) {
     if (threadIdx.x == 0) *status = *error;
 }
 
-template <typename T, int WPB, int NSMAX>
+template <typename T, int WPB, int NSMAX, bool STOP>
 static void launch_batched_w(const BatchArgs &a, int grid, hipStream_t st) {
     const size_t dyn = sizeof(SlotLds) * a.slots;
-    hipLaunchKernelGGL((k_batched<T, WPB, NSMAX>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
+    hipLaunchKernelGGL((k_batched<T, WPB, NSMAX, STOP>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
 }
 
-template <typename T, int NSMAX>
+template <typename T, int NSMAX, bool STOP>
 static void launch_batched_n(const BatchArgs &a, int wpb, int grid, hipStream_t st) {
-    if (wpb == 4) launch_batched_w<T, 4, NSMAX>(a, grid, st);
-    else if (wpb == 8) launch_batched_w<T, 8, NSMAX>(a, grid, st);
-    else launch_batched_w<T, 16, NSMAX>(a, grid, st);
+    if (wpb == 4) launch_batched_w<T, 4, NSMAX, STOP>(a, grid, st);
+    else if (wpb == 8) launch_batched_w<T, 8, NSMAX, STOP>(a, grid, st);
+    else launch_batched_w<T, 16, NSMAX, STOP>(a, grid, st);
 }
 
+// the list-BLER stop is a separate instantiation, so that batches without it pay nothing
 template <typename T>
 static void launch_batched(const BatchArgs &a, int wpb, int grid, hipStream_t st) {
-    if (a.nmax <= 64) launch_batched_n<T, 64>(a, wpb, grid, st);
-    else launch_batched_n<T, 128>(a, wpb, grid, st);
+    const bool stop = a.pstop > 0.0;
+    if (a.nmax <= 64) {
+        if (stop) launch_batched_n<T, 64, true>(a, wpb, grid, st);
+        else launch_batched_n<T, 64, false>(a, wpb, grid, st);
+    } else {
+        if (stop) launch_batched_n<T, 128, true>(a, wpb, grid, st);
+        else launch_batched_n<T, 128, false>(a, wpb, grid, st);
+    }
 }
 
 static int check_sched(const sogrand_sched_t *s) {
@@ -385,6 +394,7 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
     a.ncodes = ncodes;
     a.L = params->list_max;
     a.qcap = params->query_cap;
+    a.pstop = params->list_bler_stop;
     a.alpha = params->alpha;
     a.max_iter = params->max_iter;
     a.early_stop = params->early_stop ? 1 : 0;

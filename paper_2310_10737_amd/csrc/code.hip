@@ -154,6 +154,8 @@ int check_params(const sogrand_params_t *p) {
     if (p->max_iter < 1 || p->max_iter > 1000) return fail(SOGRAND_EINVAL, "max_iter %d outside 1..1000", p->max_iter);
     if (p->precision != SOGRAND_F64 && p->precision != SOGRAND_F32)
         return fail(SOGRAND_EINVAL, "precision must be SOGRAND_F64 or SOGRAND_F32");
+    if (!(p->list_bler_stop >= 0.0 && p->list_bler_stop <= 1.0))
+        return fail(SOGRAND_EINVAL, "list_bler_stop must lie in [0, 1]");
     return SOGRAND_OK;
 }
 
@@ -396,6 +398,7 @@ void sogrand_params_default(sogrand_params_t *p) {
     p->max_iter = 4;
     p->early_stop = 1;
     p->precision = SOGRAND_F64;
+    p->list_bler_stop = 0.0;
 }
 
 int sogrand_code_create(int n, int k, const uint32_t *h_cols, sogrand_code_t **out) {

@@ -11,6 +11,7 @@ struct ComponentArgs {
     DevCode code;
     int L;
     uint32_t qcap;
+    double pstop;           // list-BLER stop threshold, 0 = off
     size_t nwords;
     const void *llr_in;
     void *llr_app;
@@ -27,7 +28,7 @@ struct ComponentArgs {
 };
 
 
-template <typename T, int NS, int WPB>
+template <typename T, int NS, int WPB, bool STOP>
 __global__ __launch_bounds__(kWave * WPB) void k_component(ComponentArgs a) {
     constexpr int NB = Lanes<NS>::NB;
     __shared__ WaveLds lds[WPB];
@@ -45,7 +46,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_component(ComponentArgs a) {
         lam[b] = i < n ? (double)in[i] : 0.0;
     }
     double lapp[NB];
-    const WordStats st = decode_word<NS>(a.code, nullptr, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    const WordStats st = decode_word<NS, false, STOP>(a.code, nullptr, a.L, a.qcap, a.pstop, lam, S, lapp, lane,
+                                                      a.prof != nullptr);
     if (a.prof && lane == 0) prof_add(a.prof, st);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -88,6 +90,7 @@ struct ProductArgs {
     DevCode code;
     int L;
     uint32_t qcap;
+    double pstop;           // list-BLER stop threshold, 0 = off
     double alpha;
     size_t nframes;
     const void *llr_ch;     // [F][n][n]
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_product_init(ProductArgs a) {
 }
 
 // One wave per line: ROWS decodes row `line` of L_Ch + L_A, otherwise column `line`.
-template <typename T, int NS, bool ROWS, int WPB>
+template <typename T, int NS, bool ROWS, int WPB, bool STOP>
 __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
     constexpr int NB = Lanes<NS>::NB;
     __shared__ WaveLds lds[WPB];
@@ -150,7 +153,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
         lam[b] = i < n ? (double)ch[pos[b]] + (double)la[pos[b]] : 0.0;
     }
     double lapp[NB];
-    const WordStats st = decode_word<NS>(a.code, nullptr, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    const WordStats st = decode_word<NS, false, STOP>(a.code, nullptr, a.L, a.qcap, a.pstop, lam, S, lapp, lane,
+                                                      a.prof != nullptr);
     if (a.prof && lane == 0) prof_add(a.prof, st);
     uint64_t hm[2] = {0ull, 0ull};
 #pragma unroll
@@ -219,9 +223,9 @@ __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, 
 // ----------------------------------------------------------------------------
 static int sort_width(int n) { return n <= 32 ? 32 : (n <= 64 ? 64 : 128); }
 
-// Launch shape of the decode kernels: waves per workgroup and the XCD-aware
-// workgroup order.  Defaults come from measurement on MI355X; SOGRAND_WPB (1, 2
-// or 4) and SOGRAND_XCD (0 or 1) override them.
+// Launch shape of the decode kernels: kWavesPerBlock waves per workgroup (measured
+// best on MI355X against 1 and 2) and the workgroup order; SOGRAND_XCD=1 selects the
+// XCD-aware order (measured slower here: frames of similar SNR then share an XCD).
 struct LaunchShape {
     int wpb;
     int xcd;
@@ -229,11 +233,7 @@ struct LaunchShape {
 
 static LaunchShape launch_shape() {
     static const LaunchShape shape = [] {
-        LaunchShape s{4, 0};
-        if (const char *e = getenv("SOGRAND_WPB")) {
-            const int v = atoi(e);
-            if (v == 1 || v == 2 || v == 4) s.wpb = v;
-        }
+        LaunchShape s{kWavesPerBlock, 0};
         if (const char *e = getenv("SOGRAND_XCD")) s.xcd = atoi(e) != 0;
         return s;
     }();
@@ -248,32 +248,33 @@ static size_t word_grid(size_t words, const LaunchShape &ls) {
     return g;
 }
 
-template <typename T, int WPB>
-static void launch_component_w(const ComponentArgs &a, int ns, dim3 g, hipStream_t st) {
-    if (ns == 32) hipLaunchKernelGGL((k_component<T, 32, WPB>), g, dim3(kWave * WPB), 0, st, a);
-    else if (ns == 64) hipLaunchKernelGGL((k_component<T, 64, WPB>), g, dim3(kWave * WPB), 0, st, a);
-    else hipLaunchKernelGGL((k_component<T, 128, WPB>), g, dim3(kWave * WPB), 0, st, a);
+template <typename T, bool STOP>
+static void launch_component_s(const ComponentArgs &a, int ns, dim3 g, hipStream_t st) {
+    constexpr int W = kWavesPerBlock;
+    if (ns == 32) hipLaunchKernelGGL((k_component<T, 32, W, STOP>), g, dim3(kWave * W), 0, st, a);
+    else if (ns == 64) hipLaunchKernelGGL((k_component<T, 64, W, STOP>), g, dim3(kWave * W), 0, st, a);
+    else hipLaunchKernelGGL((k_component<T, 128, W, STOP>), g, dim3(kWave * W), 0, st, a);
 }
 
+// the list-BLER stop is a separate instantiation, so that words without it pay nothing
 template <typename T>
-static void launch_component(const ComponentArgs &a, int ns, int wpb, dim3 g, hipStream_t st) {
-    if (wpb == 1) launch_component_w<T, 1>(a, ns, g, st);
-    else if (wpb == 2) launch_component_w<T, 2>(a, ns, g, st);
-    else launch_component_w<T, 4>(a, ns, g, st);
+static void launch_component(const ComponentArgs &a, int ns, dim3 g, hipStream_t st) {
+    if (a.pstop > 0.0) launch_component_s<T, true>(a, ns, g, st);
+    else launch_component_s<T, false>(a, ns, g, st);
 }
 
-template <typename T, bool ROWS, int WPB>
-static void launch_pass_w(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
-    if (ns == 32) hipLaunchKernelGGL((k_product_pass<T, 32, ROWS, WPB>), g, dim3(kWave * WPB), 0, st, a);
-    else if (ns == 64) hipLaunchKernelGGL((k_product_pass<T, 64, ROWS, WPB>), g, dim3(kWave * WPB), 0, st, a);
-    else hipLaunchKernelGGL((k_product_pass<T, 128, ROWS, WPB>), g, dim3(kWave * WPB), 0, st, a);
+template <typename T, bool ROWS, bool STOP>
+static void launch_pass_s(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
+    constexpr int W = kWavesPerBlock;
+    if (ns == 32) hipLaunchKernelGGL((k_product_pass<T, 32, ROWS, W, STOP>), g, dim3(kWave * W), 0, st, a);
+    else if (ns == 64) hipLaunchKernelGGL((k_product_pass<T, 64, ROWS, W, STOP>), g, dim3(kWave * W), 0, st, a);
+    else hipLaunchKernelGGL((k_product_pass<T, 128, ROWS, W, STOP>), g, dim3(kWave * W), 0, st, a);
 }
 
 template <typename T, bool ROWS>
-static void launch_pass(const ProductArgs &a, int ns, int wpb, dim3 g, hipStream_t st) {
-    if (wpb == 1) launch_pass_w<T, ROWS, 1>(a, ns, g, st);
-    else if (wpb == 2) launch_pass_w<T, ROWS, 2>(a, ns, g, st);
-    else launch_pass_w<T, ROWS, 4>(a, ns, g, st);
+static void launch_pass(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
+    if (a.pstop > 0.0) launch_pass_s<T, ROWS, true>(a, ns, g, st);
+    else launch_pass_s<T, ROWS, false>(a, ns, g, st);
 }
 
 }  // namespace sg
@@ -305,6 +306,7 @@ int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t 
     SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &a.code));
     a.L = params->list_max;
     a.qcap = params->query_cap;
+    a.pstop = params->list_bler_stop;
     a.nwords = nwords;
     a.llr_in = llr_in;
     a.llr_app = llr_app;
@@ -324,8 +326,8 @@ int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int ns = sort_width(code->n);
     const int tok = prof_start(PK_COMPONENT, st);
-    if (params->precision == SOGRAND_F64) launch_component<double>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
-    else launch_component<float>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
+    if (params->precision == SOGRAND_F64) launch_component<double>(a, ns, dim3((unsigned)blocks), st);
+    else launch_component<float>(a, ns, dim3((unsigned)blocks), st);
     prof_stop(tok, st);
     SG_HIP(hipGetLastError());
     return SOGRAND_OK;
@@ -365,6 +367,7 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
         return fail(SOGRAND_ENOMEM, "work buffer allocation of %zu bytes failed", total);
     a.L = params->list_max;
     a.qcap = params->query_cap;
+    a.pstop = params->list_bler_stop;
     a.alpha = params->alpha;
     a.nframes = nframes;
     a.llr_ch = llr_ch;
@@ -396,11 +399,11 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
             const bool rows = (h & 1) != 0;
             tok = prof_start(PK_PASS, st);
             if (f64) {
-                if (rows) launch_pass<double, true>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
-                else launch_pass<double, false>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
+                if (rows) launch_pass<double, true>(a, ns, dim3((unsigned)blocks), st);
+                else launch_pass<double, false>(a, ns, dim3((unsigned)blocks), st);
             } else {
-                if (rows) launch_pass<float, true>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
-                else launch_pass<float, false>(a, ns, ls.wpb, dim3((unsigned)blocks), st);
+                if (rows) launch_pass<float, true>(a, ns, dim3((unsigned)blocks), st);
+                else launch_pass<float, false>(a, ns, dim3((unsigned)blocks), st);
             }
             prof_stop(tok, st);
             tok = prof_start(PK_CHECK, st);

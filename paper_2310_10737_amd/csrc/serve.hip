@@ -73,6 +73,7 @@ struct ServeArgs {
     unsigned long long *qsum; // per frame: queries of this step
     int L;
     uint32_t qcap;
+    double pstop;             // list-BLER stop threshold, 0 = off
     double alpha;
     int max_iter;
     int early_stop;
@@ -81,7 +82,7 @@ struct ServeArgs {
 
 // One wave per line of one word width.  Every frame of the launch runs the
 // half-iteration its descriptor names (rows for odd h).
-template <typename T, int NS>
+template <typename T, int NS, bool STOP>
 __global__ __launch_bounds__(kBlock) void k_serve_pass(ServeArgs a) {
     constexpr int NB = Lanes<NS>::NB;
     __shared__ WaveLds lds[kWavesPerBlock];
@@ -130,7 +131,8 @@ __global__ __launch_bounds__(kBlock) void k_serve_pass(ServeArgs a) {
         }
     }
     double lapp[NB];
-    const WordStats st = decode_word<NS, true>(c, cdev, a.L, a.qcap, lam, S, lapp, lane, a.prof != nullptr);
+    const WordStats st = decode_word<NS, true, STOP>(c, cdev, a.L, a.qcap, a.pstop, lam, S, lapp, lane,
+                                                     a.prof != nullptr);
     if (a.prof && lane == 0) prof_add(a.prof, st);
     uint64_t hm[2] = {0ull, 0ull};
 #pragma unroll
@@ -276,12 +278,18 @@ namespace sg {
 static int width_class(int n) { return n <= 32 ? 0 : (n <= 64 ? 1 : 2); }
 static int class_width(int c) { return c == 0 ? 32 : (c == 1 ? 64 : 128); }
 
+template <typename T, bool STOP>
+static void launch_serve_pass_s(const ServeArgs &a, int wclass, hipStream_t st) {
+    const dim3 g((a.nlines + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (wclass == 0) hipLaunchKernelGGL((k_serve_pass<T, 32, STOP>), g, dim3(kBlock), 0, st, a);
+    else if (wclass == 1) hipLaunchKernelGGL((k_serve_pass<T, 64, STOP>), g, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_serve_pass<T, 128, STOP>), g, dim3(kBlock), 0, st, a);
+}
+
 template <typename T>
 static void launch_serve_pass(const ServeArgs &a, int wclass, hipStream_t st) {
-    const dim3 g((a.nlines + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (wclass == 0) hipLaunchKernelGGL((k_serve_pass<T, 32>), g, dim3(kBlock), 0, st, a);
-    else if (wclass == 1) hipLaunchKernelGGL((k_serve_pass<T, 64>), g, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_serve_pass<T, 128>), g, dim3(kBlock), 0, st, a);
+    if (a.pstop > 0.0) launch_serve_pass_s<T, true>(a, wclass, st);
+    else launch_serve_pass_s<T, false>(a, wclass, st);
 }
 
 }  // namespace sg
@@ -327,6 +335,7 @@ int sogrand_server::step(std::vector<Req> &active) {
     a.mirror_w = mirror_dev;
     a.L = params.list_max;
     a.qcap = params.query_cap;
+    a.pstop = params.list_bler_stop;
     a.alpha = params.alpha;
     a.max_iter = params.max_iter;
     a.early_stop = params.early_stop ? 1 : 0;

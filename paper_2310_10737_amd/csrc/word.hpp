@@ -417,8 +417,10 @@ __device__ __forceinline__ void put_rho(WaveLds &S, int r, double v) {
 
 // Decodes one word held as lam[slot] at bit index lane + 64*slot (< n).
 // Writes the APP LLRs of the lane's bits into lapp; the list is left in S.
-template <int NS, bool TABLE = false>
+// STOP: the list-BLER stop is compiled in (pstop > 0 selects it at launch).
+template <int NS, bool TABLE = false, bool STOP = false>
 __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode *cdev, int L, uint32_t qcap,
+                                                 double pstop,
                                                  const double (&lam)[Lanes<NS>::NB], WaveLds &S,
                                                  double (&lapp)[Lanes<NS>::NB], int lane, bool count) {
     constexpr int NB = Lanes<NS>::NB;
@@ -568,6 +570,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         len = c.len[cls];
     }
     const uint32_t limit = qcap < len ? qcap : len;
+    bool stopped = false;     // the list-BLER stop ended the search
     int found = 0;
     uint32_t Q = 0;
     double s_lane = 0.0;   // this lane's share of the tested nonzero-pattern mass (relative to p(0|r))
@@ -623,7 +626,13 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         }
         uint64_t m = __ballot(act && s == 0u);
         int cut = kWave - 1;
-        while (m != 0ull && found < L) {
+        // tested nonzero-pattern mass before this chunk (only needed by the list-BLER stop)
+        const bool check = STOP && m != 0ull;
+        double s_before = 0.0;
+        if constexpr (STOP) {
+            if (check) s_before = bcast0(wave_sum(s_lane));
+        }
+        while (m != 0ull && found < L && !stopped) {
             const int h = __builtin_ctzll(m);
             m &= m - 1ull;
             const uint32_t hx = __builtin_amdgcn_readlane(e.x, h);
@@ -638,11 +647,26 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
             }
             found++;
             if (found == L) cut = h;
+            else if (STOP && check) {
+                // list-BLER stop: Corollary 1 for the list so far, with the mass tested up
+                // to and including this query (class mass relative to p(0|r), nonzero
+                // patterns only)
+                const double T = c.even ? (par ? O : E) : (E + O);
+                const double pre = (act && (e.x & 0xffu) != 0u && lane <= h) ? tau : 0.0;
+                double Mi = T - (s_before + bcast0(wave_sum(pre)));
+                if (!(Mi > 0.0)) Mi = 0.0;
+                double Di = Mi * c.phi;
+                for (int l = 0; l < found; l++) Di += S.tau_l[l];
+                if ((Mi * c.phi) / Di < pstop) {
+                    stopped = true;
+                    cut = h;
+                }
+            }
         }
         const bool nonzero = (e.x & 0xffu) != 0u;
         if (act && nonzero && lane <= cut) s_lane += tau;
         if (count && act && lane <= cut) w_lane += pattern_weight(e);
-        if (found >= L) {
+        if (found >= L || stopped) {
             Q = base + (uint32_t)cut + 1u;
             break;
         }

@@ -48,6 +48,8 @@ def test_version_and_defaults(sg):
     p = sg.sogrand_params_t()
     sg.lib().sogrand_params_default(ctypes.byref(p))
     assert (p.list_max, p.query_cap, p.alpha, p.max_iter, p.early_stop, p.precision) == (4, 1000, 0.5, 4, 1, 0)
+    assert p.list_bler_stop == 0.0
+    assert ctypes.sizeof(sg.sogrand_params_t) == 40   # the C layout
 
 
 @pytest.mark.parametrize("nk", [(8, 4), (16, 11), (32, 26), (64, 57), (128, 120), (16, 7)])
@@ -93,6 +95,7 @@ def test_ebch_rejects_unknown_parameters(sg):
 @pytest.mark.parametrize("field,value", [
     ("list_max", 0), ("list_max", 17), ("query_cap", 0), ("query_cap", (1 << 24) + 1),
     ("alpha", 0.0), ("alpha", float("nan")), ("max_iter", 0), ("precision", 2),
+    ("list_bler_stop", -0.1), ("list_bler_stop", 1.5), ("list_bler_stop", float("nan")),
 ])
 def test_decode_rejects_bad_params_before_device_work(sg, field, value):
     code = sg.Code.ebch(32, 26)
