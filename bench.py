@@ -205,9 +205,11 @@ def bench_product(args, sg, np, torch, synth):
     fcode = torch.zeros(total, dtype=torch.uint8, device=dev)
     foff = torch.arange(total, dtype=torch.int64, device=dev) * (N * N)
 
+    iters, stop = args.iters, args.list_bler_stop
+
     def run_batched(x, out, sc):
-        sg.sogrand_decode_batched([gcode], fcode, foff, x.view(-1), list_max=L, query_cap=QCAP, max_iter=ITERS,
-                                  sched_=sc, outputs=out)
+        sg.sogrand_decode_batched([gcode], fcode, foff, x.view(-1), list_max=L, query_cap=QCAP, max_iter=iters,
+                                  sched_=sc, outputs=out, list_bler_stop=stop)
 
     def tune(x):
         """Times candidate launch shapes on the first 3000 frames; returns the fastest."""
@@ -216,10 +218,10 @@ def bench_product(args, sg, np, torch, synth):
         best = None
         for w, f, ch, g in [(8, 2, 1, 3), (4, 2, 1, 6), (8, 3, 1, 3), (4, 2, 1, 8), (8, 2, 2, 3), (4, 1, 1, 6)]:
             sc = sg.sched(w, f, ch, g)
-            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, ITERS, sched_=sc)
+            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, iters, sched_=sc, list_bler_stop=stop)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, ITERS, sched_=sc)
+            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, iters, sched_=sc, list_bler_stop=stop)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             if best is None or dt < best[0]:
@@ -232,7 +234,7 @@ def bench_product(args, sg, np, torch, synth):
         out = outputs()
         if form.startswith("plain"):
             step = (lambda x_, o_: lambda: sg.sogrand_decode_product(
-                gcode, x_, list_max=L, query_cap=QCAP, max_iter=ITERS, outputs=o_))(x, out)
+                gcode, x_, list_max=L, query_cap=QCAP, max_iter=iters, outputs=o_, list_bler_stop=stop))(x, out)
             sc = None
         elif form.startswith("batched"):
             out["hard"] = out["hard"].view(-1)
@@ -303,14 +305,16 @@ def bench_product(args, sg, np, torch, synth):
         cf = min(args.cpu_frames, F)
         sample = np.concatenate([llr_all[j * F:j * F + cf] for j in range(len(SNRS))])
         t0 = time.perf_counter()
-        oracle.decode_product(code, sample, L, QCAP, ITERS, nthreads=threads)
+        oracle.decode_product(code, sample, L, QCAP, iters, nthreads=threads, pstop=stop)
         dt = time.perf_counter() - t0
         cpu = dict(value=sample.shape[0] * K * K / dt, unit="info bits/s", cores=threads, kind="oracle",
                    sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall")
 
     storage = "f32" if best_name.endswith("f32") else "f64"
-    config = {"workload": "eBCH [64,57]^2 product code, BPSK-AWGN 2.5/3.0/3.5 dB, 1e4 frames each, "
-                          "L=4, query cap 1e4, 6 iterations, alpha 0.5",
+    settings = f"L=4, query cap 1e4, {iters} iterations, alpha 0.5"
+    if stop > 0:
+        settings += f", list-BLER stop {stop:g}"
+    config = {"workload": "eBCH [64,57]^2 product code, BPSK-AWGN 2.5/3.0/3.5 dB, 1e4 frames each, " + settings,
               "form": best_name, "llr_storage": storage, "frames_per_step": total,
               "info_bits_per_frame": K * K, "parallelism": "single GPU"}
     return base_line(args, "decoded info bits/s at matched BLER", best["info_bits_per_s"], "info bits/s",
@@ -575,6 +579,9 @@ def main() -> int:
     ap.add_argument("--rate", type=float, default=2e5, help="serving arrival rate (1/s)")
     ap.add_argument("--hbm-gib", type=int, default=8, help="serving slot budget")
     ap.add_argument("--qcap", type=int, default=None, help="query cap (mixed, component, serve)")
+    ap.add_argument("--iters", type=int, default=ITERS, help="product workload: row+column iterations")
+    ap.add_argument("--list-bler-stop", type=float, default=0.0,
+                    help="product workload: end a word's search once its predicted list-BLER is below this")
     ap.add_argument("--cpu-frames", type=int, default=None, help="oracle sample: frames (per Eb/N0 for product)")
     ap.add_argument("--cpu-words", type=int, default=1 << 14, help="oracle sample: component words")
     ap.add_argument("--no-cpu", action="store_true")
