@@ -281,17 +281,6 @@ static void launch_pass(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
 
 extern "C" {
 
-#ifdef SOGRAND_PHASE_TIMING
-// Experiment builds only: copies and clears the per-phase cycle totals.
-int sogrand_debug_phase_cycles(unsigned long long *out) {
-    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(sg::g_phase_cycles), sizeof(unsigned long long) * 8) != hipSuccess)
-        return SOGRAND_EDEVICE;
-    unsigned long long z[8] = {};
-    if (hipMemcpyToSymbol(HIP_SYMBOL(sg::g_phase_cycles), z, sizeof z) != hipSuccess) return SOGRAND_EDEVICE;
-    return SOGRAND_OK;
-}
-#endif
-
 int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t *params, size_t nwords,
                              const void *llr_in, void *llr_app, void *llr_ext, uint8_t *hard,
                              uint32_t *n_queries, uint8_t *n_found, uint32_t *found_q, double *p_found,

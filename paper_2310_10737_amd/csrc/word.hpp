@@ -57,17 +57,6 @@ struct Lanes {
     static constexpr int NB = NS > 64 ? 2 : 1;   // elements held per lane
 };
 
-#ifdef SOGRAND_PHASE_TIMING
-// Experiment builds only: cycles spent per phase of decode_word, summed over words.
-static __device__ unsigned long long g_phase_cycles[8];
-#define SG_STAMP(v) const long long v = clock64()
-#define SG_PHASE(i, a, b) \
-    if (lane == 0) atomicAdd(&g_phase_cycles[i], (unsigned long long)((b) - (a)))
-#else
-#define SG_STAMP(v)
-#define SG_PHASE(i, a, b)
-#endif
-
 struct WordStats {
     uint32_t Q;      // patterns tested
     int found;       // codewords in the list
@@ -425,7 +414,6 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
                                                  double (&lapp)[Lanes<NS>::NB], int lane, bool count) {
     constexpr int NB = Lanes<NS>::NB;
     const int n = c.n;
-    SG_STAMP(t0);
 
     // 1. hard decision, its syndrome and parity; keys |lambda| and rho = e^-|lambda| by bit
     bool valid[NB];
@@ -447,7 +435,6 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     }
     const uint32_t s0 = wave_xor(spart);
     const int par = ycount & 1;
-    SG_STAMP(t1);
 
     // 2. reliability ranks (|lambda| ascending, ties by bit index)
     int myrank[NB];
@@ -529,7 +516,6 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     }
     wave_sync();
 
-    SG_STAMP(t2);
     // 3. parity-class masses: adding bit i maps (E, O) to (E + O rho_i, O + (1 + E) rho_i);
     //    two disjoint bit sets combine as E = E1 + E2 + E1 E2 + O1 O2, O = O1 + O2 + E1 O2 + O1 E2.
     //    Lane t folds ranks 8t+1 .. 8t+8 in turn, then NS/8 lanes combine pairwise.
@@ -549,7 +535,6 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     if constexpr (NS >= 128) eo_combine<8>(E, O);
     E = bcast0(E);
     O = bcast0(O);
-    SG_STAMP(t3);
 
     // 4. query loop over the schedule of the word's parity class; the next chunk's
     //    patterns are fetched while the current one is tested
@@ -674,7 +659,6 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     }
 
     const double Snz = bcast0(wave_sum(s_lane));
-    SG_STAMP(t4);
 
     // 5. Corollary 1 inside the parity class: not-found mass M = (class mass) - (tested mass),
     //    both relative to p(0|r); the zero pattern (first in its class) cancels exactly.
@@ -688,7 +672,6 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     const bool degenerate = !(D > 0.0) || !isfinite(D);
     if (degenerate) pnf = 1.0;   // every probability underflowed: keep the soft input
 
-    SG_STAMP(t5);
     // eq. (LLRi): list codewords weighted by their APPs, plus the soft input weighted by P_nf
     double N0[NB], N1[NB];
 #pragma unroll
@@ -724,13 +707,6 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         if (!(la >= -1000.0)) la = -1000.0;
         lapp[b] = la;
     }
-    SG_STAMP(t6);
-    SG_PHASE(0, t0, t1);
-    SG_PHASE(1, t1, t2);
-    SG_PHASE(2, t2, t3);
-    SG_PHASE(3, t3, t4);
-    SG_PHASE(4, t4, t5);
-    SG_PHASE(5, t5, t6);
     WordStats st;
     st.Q = Q;
     st.found = found;
