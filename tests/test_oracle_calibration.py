@@ -1,4 +1,4 @@
-"""Statistical pin of the oracle's block soft output against the paper's Fig. 2.
+"""Statistical pins of the oracle's soft output against the paper's Figs. 2 and 4.
 
 The paper shows that the predicted probability that the transmitted codeword is
 not in the list (eq. app_approxlist) matches the empirical list-BLER for eBCH
@@ -16,6 +16,7 @@ import oracle
 import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig2_list_bler_calibration.txt")
+GOLDEN4 = os.path.join(os.path.dirname(__file__), "golden", "fig4_bitwise_so_calibration.txt")
 
 
 def paper_points():
@@ -63,3 +64,36 @@ def test_list_bler_calibration_matches_fig2(nk, words):
         sd = np.sqrt(pred * (1 - pred) / cnt)
         assert abs(emp - pred) <= 0.25 * pred + 4 * sd, (nk, pred, emp, errs, cnt)
     assert checked >= 3
+
+
+def fig4_points():
+    pts = {}
+    for line in open(GOLDEN4):
+        if line.startswith("#") or not line.strip():
+            continue
+        nk, b, p, e = line.split()
+        pts.setdefault(tuple(int(x) for x in nk.split(",")), {})[int(b)] = (float(p), float(e))
+    return pts
+
+
+@pytest.mark.parametrize("nk,words", [((16, 11), 40000), ((32, 26), 30000), ((64, 57), 30000)])
+def test_bitwise_so_calibration_matches_fig4(nk, words):
+    """The bitwise soft output (eq. LLRi) binned by the predicted probability of a 1 reproduces
+    the paper's Fig. 4 below 0.5: the same mean prediction per bin and the same empirical
+    frequency.  Dropping the not-found term, taking the prior from L_Ch only, or a wrong
+    list weighting moves these points by far more than the tolerance."""
+    pts = fig4_points()[nk]
+    code = synth.ebch(*nk)
+    llr, cw, _ = synth.component_words(code, 2.0, 202, np.arange(words))
+    out = oracle.decode_component(code, llr, 4, 10 ** 5)
+    p1 = 1.0 / (1.0 + np.exp(np.clip(out["llr_app"], -700, 700)))
+    bins = np.minimum((p1 * 20).astype(int), 19)
+    for b, (pp, pe) in pts.items():
+        sel = bins == b
+        cnt = int(sel.sum())
+        assert cnt >= 1000, (nk, b, cnt)
+        pred = float(p1[sel].mean())
+        emp = float(cw[sel].mean())
+        sd = np.sqrt(emp * (1 - emp) / cnt)
+        assert abs(pred - pp) <= 0.05 * pp + 5e-4, (nk, b, pred, pp)
+        assert abs(emp - pe) <= 0.12 * pe + 4 * sd, (nk, b, emp, pe, cnt)
