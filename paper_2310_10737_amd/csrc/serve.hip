@@ -12,6 +12,11 @@
 // Frame state stays in a device slot for the frame's whole life.  Channel LLRs
 // reach the device through pinned host memory that the first row pass reads
 // directly (and copies into the slot), so admission costs no copy call.
+//
+// Several lanes (host threads, each with its own stream) run steps independently.
+// A lane takes every request that arrived while its previous step ran, so a step
+// held up by one long word delays only the frames of its own lane, and the other
+// lanes' launches fill the device meanwhile.
 #include <time.h>
 
 #include <algorithm>
@@ -28,6 +33,9 @@ namespace sg {
 
 constexpr int kServeCodes = 16;
 constexpr size_t kServeMinBudget = (size_t)1 << 20;
+// Independent step loops, each with its own stream and its own set of frames: while one
+// lane's step waits for its slowest word, the others keep the device busy.
+constexpr int kServeLanes = 4;
 
 // One admitted frame in one step (device copy of the host's list).
 struct ServeDesc {
@@ -232,10 +240,21 @@ struct sogrand_server {
         std::vector<uint8_t> hard;
     };
 
+    // one step loop: its thread, stream and per-step tables
+    struct Lane {
+        hipStream_t stream = nullptr;
+        ServeDesc *desc_host = nullptr;      // pinned
+        ServeDesc *desc_dev = nullptr;
+        ServeOut *out_host = nullptr;        // pinned, written by the device
+        ServeOut *out_dev = nullptr;         // device view of out_host
+        unsigned long long *qsum = nullptr;  // device
+        uint64_t last_step_end = 0;          // clock at the end of the previous step (0: idle)
+        std::thread thread;
+    };
+
     sogrand_params_t params{};
     int device = 0;
     size_t esz = 8;
-    hipStream_t stream = nullptr;
     size_t budget = 0;
     char *arena = nullptr;        // device slots
     char *mirror = nullptr;       // pinned host copy (host pointer)
@@ -249,13 +268,9 @@ struct sogrand_server {
     sg::DevCode *codes_host = nullptr;   // pinned staging of the table
     sg::DevCode *codes_dev = nullptr;
     int ncodes = 0;
-    bool codes_dirty = false;
+    int ncodes_dev = 0;                  // table entries already on the device
 
-    ServeDesc *desc_host = nullptr;      // pinned
-    ServeDesc *desc_dev = nullptr;
-    ServeOut *out_host = nullptr;        // pinned, written by the device
-    ServeOut *out_dev = nullptr;         // device view of out_host
-    unsigned long long *qsum = nullptr;  // device
+    Lane lanes[sg::kServeLanes];
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -266,11 +281,10 @@ struct sogrand_server {
     bool stop = false;
     int error = SOGRAND_OK;
     sogrand_serve_stats_t stats{};
-    uint64_t last_step_end = 0;   // clock at the end of the previous step (0: idle)
-    std::thread worker;
 
-    void run();
-    int step(std::vector<Req> &active);
+    void run(Lane &ln);
+    int step(Lane &ln, std::vector<Req> &active);
+    void release();
 };
 
 namespace sg {
@@ -294,8 +308,9 @@ static void launch_serve_pass(const ServeArgs &a, int wclass, hipStream_t st) {
 
 }  // namespace sg
 
-// One step over the admitted frames; updates `active` and publishes finished ones.
-int sogrand_server::step(std::vector<Req> &active) {
+// One step of lane `ln` over its admitted frames; updates `active` and publishes
+// finished ones.
+int sogrand_server::step(Lane &ln, std::vector<Req> &active) {
     using namespace sg;
     const uint64_t t0 = clock_ns();
     // frames grouped by word width, each group one launch
@@ -312,7 +327,7 @@ int sogrand_server::step(std::vector<Req> &active) {
     for (int c = 0; c < 3; c++) {
         for (uint32_t j = gstart[c]; j < gstart[c + 1]; j++) {
             const Req &r = active[order[j]];
-            ServeDesc &d = desc_host[j];
+            ServeDesc &d = ln.desc_host[j];
             d.slot = r.slot;
             d.line0 = glines[c];
             d.code = (uint16_t)r.code;
@@ -326,7 +341,8 @@ int sogrand_server::step(std::vector<Req> &active) {
     // host writes to the pinned arena (submitted LLRs) and the descriptor
     // staging complete before the device is told to read them
     std::atomic_thread_fence(std::memory_order_seq_cst);
-    if (hipMemcpyAsync(desc_dev, desc_host, nact * sizeof(ServeDesc), hipMemcpyHostToDevice, stream) != hipSuccess)
+    if (hipMemcpyAsync(ln.desc_dev, ln.desc_host, nact * sizeof(ServeDesc), hipMemcpyHostToDevice, ln.stream) !=
+        hipSuccess)
         return fail(SOGRAND_EDEVICE, "descriptor copy failed");
     ServeArgs a{};
     a.codes = codes_dev;
@@ -344,23 +360,23 @@ int sogrand_server::step(std::vector<Req> &active) {
         const uint32_t cnt = gstart[c + 1] - gstart[c];
         if (!cnt) continue;
         ServeArgs g = a;
-        g.desc = desc_dev + gstart[c];
+        g.desc = ln.desc_dev + gstart[c];
         g.nact = cnt;
         g.nlines = glines[c];
-        g.qsum = qsum + gstart[c];
-        if (esz == 8) launch_serve_pass<double>(g, c, stream);
-        else launch_serve_pass<float>(g, c, stream);
+        g.qsum = ln.qsum + gstart[c];
+        if (esz == 8) launch_serve_pass<double>(g, c, ln.stream);
+        else launch_serve_pass<float>(g, c, ln.stream);
     }
     ServeArgs ck = a;
-    ck.desc = desc_dev;
+    ck.desc = ln.desc_dev;
     ck.nact = nact;
-    ck.out = out_dev;
-    ck.qsum = qsum;
+    ck.out = ln.out_dev;
+    ck.qsum = ln.qsum;
     const dim3 cg((nact + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (esz == 8) hipLaunchKernelGGL(k_serve_check<double>, cg, dim3(kBlock), 0, stream, ck);
-    else hipLaunchKernelGGL(k_serve_check<float>, cg, dim3(kBlock), 0, stream, ck);
+    if (esz == 8) hipLaunchKernelGGL(k_serve_check<double>, cg, dim3(kBlock), 0, ln.stream, ck);
+    else hipLaunchKernelGGL(k_serve_check<float>, cg, dim3(kBlock), 0, ln.stream, ck);
     if (hipGetLastError() != hipSuccess) return fail(SOGRAND_EDEVICE, "serving kernel launch failed");
-    if (hipStreamSynchronize(stream) != hipSuccess) return fail(SOGRAND_EDEVICE, "serving step failed on the device");
+    if (hipStreamSynchronize(ln.stream) != hipSuccess) return fail(SOGRAND_EDEVICE, "serving step failed on the device");
     const uint64_t t1 = clock_ns();
 
     std::vector<Done> fin;
@@ -369,7 +385,7 @@ int sogrand_server::step(std::vector<Req> &active) {
     std::vector<uint8_t> is_done(active.size(), 0);
     for (uint32_t j = 0; j < nact; j++) {
         Req &r = active[order[j]];
-        const ServeOut o = out_host[j];
+        const ServeOut o = ln.out_host[j];
         r.queries += o.queries;
         if (o.flags & 2u) {
             Done dn;
@@ -407,20 +423,19 @@ int sogrand_server::step(std::vector<Req> &active) {
         stats.step_ms += ms;
         if (ms > stats.max_step_ms) stats.max_step_ms = ms;
         if (nact > stats.max_active) stats.max_active = nact;
-        if (last_step_end) stats.host_ms += (double)(t0 - last_step_end) * 1e-6;
-        last_step_end = keep.empty() ? 0 : clock_ns();
+        if (ln.last_step_end) stats.host_ms += (double)(t0 - ln.last_step_end) * 1e-6;
+        ln.last_step_end = keep.empty() ? 0 : clock_ns();
     }
     active.swap(keep);
     if (!fin.empty()) cv_done.notify_all();
     return SOGRAND_OK;
 }
 
-void sogrand_server::run() {
+void sogrand_server::run(Lane &ln) {
     using namespace sg;
     (void)hipSetDevice(device);
     std::vector<Req> active;
     for (;;) {
-        bool copy_codes = false;
         {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
@@ -432,19 +447,21 @@ void sogrand_server::run() {
                 r.t_admit = now;
                 active.push_back(r);
             }
-            if (codes_dirty) {
-                copy_codes = true;
-                codes_dirty = false;
+            // codes registered since the last copy: only the new entries are written,
+            // since other lanes' kernels may be reading the table
+            if (ncodes > ncodes_dev && error == SOGRAND_OK) {
+                const size_t off = (size_t)ncodes_dev, cnt = (size_t)(ncodes - ncodes_dev);
+                if (hipMemcpyAsync(codes_dev + off, codes_host + off, sizeof(DevCode) * cnt, hipMemcpyHostToDevice,
+                                   ln.stream) != hipSuccess ||
+                    hipStreamSynchronize(ln.stream) != hipSuccess)
+                    error = SOGRAND_EDEVICE;
+                else
+                    ncodes_dev = ncodes;
             }
-            if (copy_codes &&
-                hipMemcpyAsync(codes_dev, codes_host, sizeof(DevCode) * kServeCodes, hipMemcpyHostToDevice, stream) !=
-                    hipSuccess)
-                error = SOGRAND_EDEVICE;
-            if (copy_codes && error == SOGRAND_OK && hipStreamSynchronize(stream) != hipSuccess) error = SOGRAND_EDEVICE;
         }
-        int rc = error == SOGRAND_OK ? step(active) : error;
+        int rc = error == SOGRAND_OK ? step(ln, active) : error;
         if (rc != SOGRAND_OK) {
-            // the device failed: every admitted request ends with the error
+            // the device failed: every request of this lane ends with the error
             std::lock_guard<std::mutex> lk(mu);
             error = rc;
             const uint64_t now = clock_ns();
@@ -468,6 +485,24 @@ void sogrand_server::run() {
     }
 }
 
+// Frees every device and host resource (threads already joined).
+void sogrand_server::release() {
+    for (Lane &ln : lanes) {
+        if (ln.stream) {
+            (void)hipStreamSynchronize(ln.stream);
+            (void)hipStreamDestroy(ln.stream);
+        }
+        if (ln.desc_host) (void)hipHostFree(ln.desc_host);
+        if (ln.desc_dev) (void)hipFree(ln.desc_dev);
+        if (ln.out_host) (void)hipHostFree(ln.out_host);
+        if (ln.qsum) (void)hipFree(ln.qsum);
+    }
+    if (arena) (void)hipFree(arena);
+    if (mirror) (void)hipHostFree(mirror);
+    if (codes_host) (void)hipHostFree(codes_host);
+    if (codes_dev) (void)hipFree(codes_dev);
+}
+
 extern "C" {
 
 uint64_t sogrand_clock_ns(void) { return sg::clock_ns(); }
@@ -486,25 +521,15 @@ int sogrand_serve_create(const sogrand_params_t *params, size_t hbm_budget_bytes
     for (int c = 0; c < 3; c++) s->class_bytes[c] = slot_layout(class_width(c), s->esz).bytes;
     s->max_active = s->budget / s->class_bytes[0] + 1;
     auto cleanup = [s](int rc) {
-        if (s->stream) (void)hipStreamDestroy(s->stream);
-        if (s->arena) (void)hipFree(s->arena);
-        if (s->mirror) (void)hipHostFree(s->mirror);
-        if (s->codes_host) (void)hipHostFree(s->codes_host);
-        if (s->codes_dev) (void)hipFree(s->codes_dev);
-        if (s->desc_host) (void)hipHostFree(s->desc_host);
-        if (s->desc_dev) (void)hipFree(s->desc_dev);
-        if (s->out_host) (void)hipHostFree(s->out_host);
-        if (s->qsum) (void)hipFree(s->qsum);
+        s->release();
         delete s;
         return rc;
     };
     if (hipGetDevice(&s->device) != hipSuccess) return cleanup(fail(SOGRAND_EDEVICE, "no current device"));
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
-        return cleanup(fail(SOGRAND_EDEVICE, "stream creation failed"));
     if (hipMalloc(reinterpret_cast<void **>(&s->arena), s->budget) != hipSuccess)
         return cleanup(fail(SOGRAND_ENOMEM, "slot arena of %zu bytes", s->budget));
     // the device reads submitted LLRs from, and writes hard decisions and verdicts
-    // to, these two host allocations inside kernels: coherent and mapped
+    // to, these host allocations inside kernels: coherent and mapped
     const unsigned shared_flags = hipHostMallocMapped | hipHostMallocCoherent;
     if (hipHostMalloc(reinterpret_cast<void **>(&s->mirror), s->budget, shared_flags) != hipSuccess)
         return cleanup(fail(SOGRAND_ENOMEM, "pinned host arena of %zu bytes", s->budget));
@@ -512,23 +537,38 @@ int sogrand_serve_create(const sogrand_params_t *params, size_t hbm_budget_bytes
         return cleanup(fail(SOGRAND_EDEVICE, "pinned host arena not visible to the device"));
     if (hipHostMalloc(reinterpret_cast<void **>(&s->codes_host), sizeof(DevCode) * kServeCodes, hipHostMallocDefault) !=
             hipSuccess ||
-        hipMalloc(reinterpret_cast<void **>(&s->codes_dev), sizeof(DevCode) * kServeCodes) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&s->desc_host), sizeof(ServeDesc) * s->max_active,
-                      hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void **>(&s->desc_dev), sizeof(ServeDesc) * s->max_active) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&s->out_host), sizeof(ServeOut) * s->max_active, shared_flags) !=
-            hipSuccess ||
-        hipMalloc(reinterpret_cast<void **>(&s->qsum), sizeof(unsigned long long) * s->max_active) != hipSuccess)
-        return cleanup(fail(SOGRAND_ENOMEM, "server tables"));
-    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&s->out_dev), s->out_host, 0) != hipSuccess)
-        return cleanup(fail(SOGRAND_EDEVICE, "pinned result table not visible to the device"));
+        hipMalloc(reinterpret_cast<void **>(&s->codes_dev), sizeof(DevCode) * kServeCodes) != hipSuccess)
+        return cleanup(fail(SOGRAND_ENOMEM, "server code table"));
     std::memset(s->codes_host, 0, sizeof(DevCode) * kServeCodes);
-    if (hipMemsetAsync(s->qsum, 0, sizeof(unsigned long long) * s->max_active, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
-        return cleanup(fail(SOGRAND_EDEVICE, "server initialisation failed"));
+    for (sogrand_server::Lane &ln : s->lanes) {
+        if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess)
+            return cleanup(fail(SOGRAND_EDEVICE, "stream creation failed"));
+        if (hipHostMalloc(reinterpret_cast<void **>(&ln.desc_host), sizeof(ServeDesc) * s->max_active,
+                          hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&ln.desc_dev), sizeof(ServeDesc) * s->max_active) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&ln.out_host), sizeof(ServeOut) * s->max_active, shared_flags) !=
+                hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&ln.qsum), sizeof(unsigned long long) * s->max_active) != hipSuccess)
+            return cleanup(fail(SOGRAND_ENOMEM, "server tables"));
+        if (hipHostGetDevicePointer(reinterpret_cast<void **>(&ln.out_dev), ln.out_host, 0) != hipSuccess)
+            return cleanup(fail(SOGRAND_EDEVICE, "pinned result table not visible to the device"));
+        if (hipMemsetAsync(ln.qsum, 0, sizeof(unsigned long long) * s->max_active, ln.stream) != hipSuccess ||
+            hipStreamSynchronize(ln.stream) != hipSuccess)
+            return cleanup(fail(SOGRAND_EDEVICE, "server initialisation failed"));
+    }
+    int started = 0;
     try {
-        s->worker = std::thread([s] { s->run(); });
+        for (sogrand_server::Lane &ln : s->lanes) {
+            ln.thread = std::thread([s, &ln] { s->run(ln); });
+            started++;
+        }
     } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+        }
+        s->cv_work.notify_all();
+        for (int i = 0; i < started; i++) s->lanes[i].thread.join();
         return cleanup(fail(SOGRAND_ENOMEM, "server thread could not start"));
     }
     *out = s;
@@ -563,7 +603,6 @@ int sogrand_serve_submit(sogrand_server_t *s, const sogrand_code_t *code, const 
             ci = s->ncodes++;
             s->code_ptr[ci] = code;
             s->codes_host[ci] = dc;
-            s->codes_dirty = true;
         }
         // a slot: a recycled one of this width, else fresh space in the arena
         if (!s->free_slots[wc].empty()) {
@@ -668,18 +707,10 @@ int sogrand_serve_destroy(sogrand_server_t *s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    for (sogrand_server::Lane &ln : s->lanes)
+        if (ln.thread.joinable()) ln.thread.join();
     (void)hipSetDevice(s->device);
-    (void)hipStreamSynchronize(s->stream);
-    (void)hipStreamDestroy(s->stream);
-    (void)hipFree(s->arena);
-    (void)hipHostFree(s->mirror);
-    (void)hipHostFree(s->codes_host);
-    (void)hipFree(s->codes_dev);
-    (void)hipHostFree(s->desc_host);
-    (void)hipFree(s->desc_dev);
-    (void)hipHostFree(s->out_host);
-    (void)hipFree(s->qsum);
+    s->release();
     delete s;
     return SOGRAND_OK;
 }
