@@ -195,12 +195,13 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
 /* Serving: continuous batching of product-frame decode requests            */
 /* ------------------------------------------------------------------------ */
 /* A server owns a pool of frame slots in device memory (hbm_budget_bytes) and
-   a host thread that advances every admitted frame by one half-iteration per
-   step (section "Iterative decoding"): the row or column pass of all admitted
-   frames, whatever their codes, runs in one set of launches, followed by the
-   validity check.  Frames that finish leave, and requests submitted meanwhile
-   join at the next step, so new work overlaps with frames already in flight.
-   Each frame is decoded exactly as sogrand_decode_product decodes it alone.
+   four lanes: host threads with their own HIP streams that each advance their
+   frames by one half-iteration per step (section "Iterative decoding").  In a
+   step the row or column pass of all the lane's frames, whatever their codes,
+   runs in one set of launches, followed by the validity check.  Frames that
+   finish leave, and requests submitted meanwhile join the next lane to start a
+   step, so new work overlaps with frames already in flight.  Each frame is
+   decoded exactly as sogrand_decode_product decodes it alone.
 
    A slot holds the frame's channel LLRs, a-priori LLRs, hard decision and
    line syndromes; its size is set by the code length rounded up to 32, 64 or
