@@ -94,7 +94,14 @@ struct ProductArgs {
     double alpha;
     size_t nframes;
     const void *llr_ch;     // [F][n][n]
-    void *la;               // [F][n][n] a-priori LLRs (work buffer)
+    // Work buffers, each [F][n][n], laid out so that every pass reads its lines
+    // contiguously: L_Ch transposed (written by the first row pass), the a-priori
+    // LLRs for the row passes (row-major, written by column passes) and for the
+    // column passes (transposed, written by row passes).
+    void *ch_t;
+    void *la_rm;
+    void *la_cm;
+    int first;              // this launch is the first row pass (no a-priori LLRs yet)
     void *llr_app;          // [F][n][n] or NULL
     uint8_t *hard;          // [F][n][n]
     uint64_t *masks;        // [F][n][2] hard decision of each line of the last pass
@@ -109,13 +116,9 @@ struct ProductArgs {
     int xcd;
 };
 
-template <typename T>
+// Per-frame state at the start (the first row pass needs no a-priori LLRs and
+// writes every element the column pass reads).
 __global__ __launch_bounds__(kBlock) void k_product_init(ProductArgs a) {
-    const int n = a.code.n;
-    const size_t total = a.nframes * (size_t)n * n;
-    T *la = static_cast<T *>(a.la);
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
-        la[i] = (T)0;
     for (size_t f = (size_t)blockIdx.x * blockDim.x + threadIdx.x; f < a.nframes; f += (size_t)gridDim.x * blockDim.x) {
         a.done[f] = 0u;
         a.halfmax[f] = 0u;
@@ -142,15 +145,24 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
     if (f >= a.nframes) return;
     if (a.done[f]) return;
     const size_t fo = (size_t)f * n * n;   // element offset of frame f
-    const T *ch = static_cast<const T *>(a.llr_ch) + fo;
-    T *la = static_cast<T *>(a.la) + fo;
+    // inputs are read along the line (element i of the line at line * n + i); the
+    // a-priori LLRs for the other direction are written across (at i * n + line)
+    const T *ch = static_cast<const T *>(ROWS ? a.llr_ch : a.ch_t) + fo;
+    const T *la_in = static_cast<const T *>(ROWS ? a.la_rm : a.la_cm) + fo;
+    T *la_out = static_cast<T *>(ROWS ? a.la_cm : a.la_rm) + fo;
+    const bool first = ROWS && a.first;
     double lam[NB];
-    int pos[NB];
+    int pos[NB];   // row-major position of the lane's elements in the frame
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
         pos[b] = ROWS ? line * n + i : i * n + line;
-        lam[b] = i < n ? (double)ch[pos[b]] + (double)la[pos[b]] : 0.0;
+        lam[b] = 0.0;
+        if (i < n) {
+            const T c = ch[line * n + i];
+            lam[b] = first ? (double)c : (double)c + (double)la_in[line * n + i];
+            if (first) static_cast<T *>(a.ch_t)[fo + (size_t)i * n + line] = c;
+        }
     }
     double lapp[NB];
     const WordStats st = decode_word<NS, false, STOP>(a.code, nullptr, a.L, a.qcap, a.pstop, lam, S, lapp, lane,
@@ -165,7 +177,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
         hm[b] = __ballot(neg);
         if (!v) continue;
         const double le = lapp[b] - lam[b];
-        la[pos[b]] = (T)(a.alpha * le);
+        la_out[i * n + line] = (T)(a.alpha * le);
         if (a.llr_app) static_cast<T *>(a.llr_app)[fo + pos[b]] = (T)lapp[b];
         a.hard[fo + pos[b]] = neg;
     }
@@ -342,9 +354,10 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
     SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &a.code));
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t esz = params->precision == SOGRAND_F64 ? sizeof(double) : sizeof(float);
-    // work buffer layout: la | masks | done | halfmax | sumq | summax | half_iters
-    const size_t off_la = 0;
-    const size_t off_mk = (off_la + nframes * n * n * esz + 255) & ~(size_t)255;
+    // work buffer layout: ch_t | la_rm | la_cm | masks | done | halfmax | sumq | summax | half_iters
+    const size_t plane = (nframes * n * n * esz + 255) & ~(size_t)255;
+    const size_t off_ct = 0, off_lr = plane, off_lc = 2 * plane;
+    const size_t off_mk = 3 * plane;
     const size_t off_dn = (off_mk + nframes * n * 2 * sizeof(uint64_t) + 255) & ~(size_t)255;
     const size_t off_hm = (off_dn + nframes * sizeof(uint32_t) + 255) & ~(size_t)255;
     const size_t off_sq = (off_hm + nframes * sizeof(uint32_t) + 255) & ~(size_t)255;
@@ -360,7 +373,10 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
     a.alpha = params->alpha;
     a.nframes = nframes;
     a.llr_ch = llr_ch;
-    a.la = ws + off_la;
+    a.ch_t = ws + off_ct;
+    a.la_rm = ws + off_lr;
+    a.la_cm = ws + off_lc;
+    a.first = 0;
     a.llr_app = llr_app;
     a.hard = hard;
     a.masks = reinterpret_cast<uint64_t *>(ws + off_mk);
@@ -377,15 +393,15 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
     const bool f64 = params->precision == SOGRAND_F64;
     int rc = SOGRAND_OK;
     {
-        const size_t ib = (nframes * n * n + kBlock - 1) / kBlock;
+        const size_t ib = (nframes + kBlock - 1) / kBlock;
         const unsigned ig = (unsigned)(ib < 65536 ? ib : 65536);
         int tok = prof_start(PK_INIT, st);
-        if (f64) hipLaunchKernelGGL(k_product_init<double>, dim3(ig), dim3(kBlock), 0, st, a);
-        else hipLaunchKernelGGL(k_product_init<float>, dim3(ig), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_product_init, dim3(ig), dim3(kBlock), 0, st, a);
         prof_stop(tok, st);
         const unsigned cg = (unsigned)((nframes + kWavesPerBlock - 1) / kWavesPerBlock);
         for (int h = 1; h <= 2 * params->max_iter; h++) {
             const bool rows = (h & 1) != 0;
+            a.first = h == 1 ? 1 : 0;
             tok = prof_start(PK_PASS, st);
             if (f64) {
                 if (rows) launch_pass<double, true>(a, ns, dim3((unsigned)blocks), st);
