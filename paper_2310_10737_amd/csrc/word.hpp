@@ -10,8 +10,8 @@
 // One 64-lane wavefront decodes one component word:
 //   1. hard decision y, its syndrome s0 = XOR of the H columns where y = 1 and
 //      its parity (section "Background on GRAND": H c = 0; even-code parity);
-//   2. reliability ranks of (|lambda|, index): counting smaller keys for words of
-//      up to 64 bits, a bitonic network across lanes for longer words;
+//   2. reliability ranks of (|lambda|, index): counting smaller keys, or a bitonic
+//      network across lanes over 32-bit keys with an exact fallback;
 //   3. rho_i = exp(-|lambda_i|), so that p(z|r) = p(0|r) prod_{i in z} rho_i
 //      (the bookkeeping of section "GRAND per block SO": p(z) from p(0) in w(z)
 //      operations), and the parity-class masses E, O (sums of prod rho over
@@ -201,50 +201,45 @@ __device__ __forceinline__ uint32_t flip_lane(uint32_t v) {
     }
 }
 
-template <int K>
-__device__ __forceinline__ uint64_t flip_lane64(uint64_t v) {
-    return ((uint64_t)flip_lane<K>((uint32_t)(v >> 32)) << 32) | flip_lane<K>((uint32_t)v);
-}
-
-template <int M>
-__device__ __forceinline__ uint64_t xor_lane64(uint64_t v) {
-    return ((uint64_t)xor_lane<M>((uint32_t)(v >> 32)) << 32) | xor_lane<M>((uint32_t)v);
-}
-
 // compare-exchange in an ascending network: the lower position keeps the minimum
-__device__ __forceinline__ void cas64(uint64_t &k, uint64_t p, bool lower) {
-    const bool lt = p < k;
-    const uint64_t mn = lt ? p : k, mx = lt ? k : p;
-    k = lower ? mn : mx;
+__device__ __forceinline__ uint32_t cas32(uint32_t k, uint32_t p, bool lower) {
+    const uint32_t mn = p < k ? p : k, mx = p < k ? k : p;
+    return lower ? mn : mx;
 }
 
 // Bitonic network with ascending comparators only: for each block size K the
 // first step compares mirror images inside the block, the next ones compare
 // positions J = K/4, ..., 1 apart.
-template <int K, int J>
-__device__ __forceinline__ void merge64x2(uint64_t (&k)[2], int lane) {
+template <int J, int NB>
+__device__ __forceinline__ void merge32(uint32_t (&k)[NB], int lane) {
     if constexpr (J >= 1) {
-        cas64(k[0], xor_lane64<J>(k[0]), (lane & J) == 0);
-        cas64(k[1], xor_lane64<J>(k[1]), (lane & J) == 0);
-        merge64x2<K, J / 2>(k, lane);
+#pragma unroll
+        for (int b = 0; b < NB; b++) k[b] = cas32(k[b], xor_lane<J>(k[b]), (lane & J) == 0);
+        merge32<J / 2, NB>(k, lane);
     }
 }
 
-// 128 keys, element e = lane + 64*slot
-template <int K>
-__device__ __forceinline__ void sort64x2(uint64_t (&k)[2], int lane) {
-    if constexpr (K <= 64) {
-        cas64(k[0], flip_lane64<K>(k[0]), (lane & (K / 2)) == 0);
-        cas64(k[1], flip_lane64<K>(k[1]), (lane & (K / 2)) == 0);
-        merge64x2<K, K / 4>(k, lane);
-        sort64x2<K * 2>(k, lane);
-    } else if constexpr (K == 128) {
+// 64 * NB keys, element e = lane + 64*slot, sorted ascending in place; with KMAX = 32
+// each half of the wave is sorted on its own
+template <int K, int NB, int KMAX>
+__device__ __forceinline__ void sort32(uint32_t (&k)[NB], int lane) {
+    if constexpr (K <= 64 && K <= KMAX) {
+#pragma unroll
+        for (int b = 0; b < NB; b++) k[b] = cas32(k[b], flip_lane<K>(k[b]), (lane & (K / 2)) == 0);
+        merge32<K / 4, NB>(k, lane);
+        sort32<K * 2, NB, KMAX>(k, lane);
+    } else if constexpr (K == 128 && NB == 2) {
         // mirror of element lane (slot 0) is element 127 - lane = slot 1 of lane 63 - lane
-        const uint64_t f0 = flip_lane64<64>(k[0]), f1 = flip_lane64<64>(k[1]);
+        const uint32_t f0 = flip_lane<64>(k[0]), f1 = flip_lane<64>(k[1]);
         k[0] = f1 < k[0] ? f1 : k[0];
         k[1] = f0 > k[1] ? f0 : k[1];
-        merge64x2<128, 32>(k, lane);
+        merge32<32, NB>(k, lane);
     }
+}
+
+// v from lane + 1 (lane 63 reads lane 0)
+__device__ __forceinline__ uint32_t next_lane(uint32_t v) {
+    return (uint32_t)__shfl((int)v, (int)((threadIdx.x + 1) & (kWave - 1)));
 }
 
 // ---- binary64 elementary functions for the per-bit work ----
@@ -404,6 +399,94 @@ __device__ __forceinline__ void put_rho(WaveLds &S, int r, double v) {
         tau *= __longlong_as_double((long long)(((uint64_t)q_.y << 32) | q_.x)); \
     } while (0)
 
+// Rank (1-based) of each lane's key among the n keys, |lambda| bit patterns by bit
+// index (non-negative doubles order like their bit patterns), ties by bit index.
+// Returns whether the exact tie-resolving pass ran.
+//
+// By counting: a lane's rank is the number of smaller keys.  The ranks sum to
+// n(n-1)/2 unless equal keys exist, and then each group of equal keys is ordered
+// by bit index.
+__device__ __forceinline__ bool ranks_by_count(uint64_t key, bool valid, int n, WaveLds &S, int lane,
+                                               int &myrank) {
+    bool exact_pass = false;
+    S.key_b[lane] = key;
+    if (lane < 2) S.key_b[kWave + lane] = ~0ull;
+    wave_sync();
+    uint32_t cnt = 0;
+    for (int j = 0; j < n; j += 2) {
+        const uint64_t k0 = S.key_b[j], k1 = S.key_b[j + 1];
+        cnt += (k0 < key) ? 1u : 0u;
+        cnt += (k1 < key) ? 1u : 0u;
+    }
+    const uint32_t tot = __builtin_amdgcn_readfirstlane(wave_add(valid ? cnt : 0u));
+    if (tot != (uint32_t)(n * (n - 1) / 2)) {
+        exact_pass = true;
+        for (int j = 0; j < n; j++) {
+            const uint64_t kj = S.key_b[j];
+            cnt += (kj == key && j < lane) ? 1u : 0u;
+        }
+    }
+    myrank = valid ? (int)cnt + 1 : 0;
+    return exact_pass;
+}
+
+// By a bitonic network over 32-bit keys: |lambda| rounded to binary32 (a monotone
+// map) with its low IB bits replaced by the bit index, so the keys are distinct.  If
+// two neighbours of the sorted order agree above bit IB, the rounding or the
+// truncation may have decided their order, and the ranks are recomputed exactly by
+// counting.  Otherwise every sorted neighbour pair, and so every pair, is in exact
+// order.
+template <int NS, int NB>
+__device__ __forceinline__ bool ranks_by_network(const uint64_t (&key)[NB], const bool (&valid)[NB], int n,
+                                                 WaveLds &S, int lane, int (&myrank)[NB]) {
+    constexpr int IB = NB == 1 ? 6 : 7;
+    uint32_t k32[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const uint32_t id = (uint32_t)(lane + kWave * b);
+        const uint32_t f = __float_as_uint((float)__longlong_as_double((long long)key[b]));
+        k32[b] = valid[b] ? ((f & ~((1u << IB) - 1u)) | id) : (~((1u << IB) - 1u) | id);
+    }
+    // words of up to 32 bits sort the lower half of the wave only
+    sort32<2, NB, (NS > 32 ? 2 * kWave : kWave / 2)>(k32, lane);
+    bool amb;
+    if constexpr (NB == 1) {
+        const uint32_t nx = next_lane(k32[0]);
+        amb = lane + 1 < n && (k32[0] >> IB) == (nx >> IB);
+    } else {
+        const uint32_t n0 = next_lane(k32[0]), n1 = next_lane(k32[1]);
+        const uint32_t first1 = (uint32_t)__builtin_amdgcn_readfirstlane(k32[1]);
+        const uint32_t nx0 = lane == kWave - 1 ? first1 : n0;
+        amb = lane + 1 < n && (k32[0] >> IB) == (nx0 >> IB);
+        amb |= lane + kWave + 1 < n && (k32[1] >> IB) == (n1 >> IB);
+    }
+    const bool exact_pass = __ballot(amb) != 0ull;
+    if (!exact_pass) {
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+            if (lane + kWave * b < n) S.rank_b[k32[b] & ((1u << IB) - 1u)] = (uint8_t)(lane + kWave * b + 1);
+        wave_sync();
+#pragma unroll
+        for (int b = 0; b < NB; b++) myrank[b] = valid[b] ? S.rank_b[lane + kWave * b] : 0;
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; b++) S.key_b[lane + kWave * b] = key[b];
+        wave_sync();
+        uint32_t cnt[NB];
+#pragma unroll
+        for (int b = 0; b < NB; b++) cnt[b] = 0u;
+        for (int j = 0; j < n; j++) {
+            const uint64_t kj = S.key_b[j];
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+                cnt[b] += (kj < key[b] || (kj == key[b] && j < lane + kWave * b)) ? 1u : 0u;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; b++) myrank[b] = valid[b] ? (int)cnt[b] + 1 : 0;
+    }
+    return exact_pass;
+}
+
 // Decodes one word held as lam[slot] at bit index lane + 64*slot (< n).
 // Writes the APP LLRs of the lane's bits into lapp; the list is left in S.
 // STOP: the list-BLER stop is compiled in (pstop > 0 selects it at launch).
@@ -436,70 +519,15 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     const uint32_t s0 = wave_xor(spart);
     const int par = ycount & 1;
 
-    // 2. reliability ranks (|lambda| ascending, ties by bit index)
+    // 2. reliability ranks (|lambda| ascending, ties by bit index).  The plain kernels
+    //    count smaller keys for words of up to 64 bits: two VALU operations per key, with
+    //    the keys read back from LDS, whose latency their full occupancy hides.  The
+    //    persistent and served kernels, which hold fewer waves per SIMD, and all words
+    //    of 128 bits use a sorting network instead.
     int myrank[NB];
-    bool exact_pass = false;
-    if constexpr (NB == 1) {
-        // rank = number of smaller keys (bit patterns of non-negative doubles order like
-        // the values); the ranks sum to n(n-1)/2 unless equal keys exist, and then each
-        // group of equal keys is ordered by bit index
-        S.key_b[lane] = key[0];
-        if (lane < 2) S.key_b[kWave + lane] = ~0ull;
-        wave_sync();
-        uint32_t cnt = 0;
-        for (int j = 0; j < n; j += 2) {
-            const uint64_t k0 = S.key_b[j], k1 = S.key_b[j + 1];
-            cnt += (k0 < key[0]) ? 1u : 0u;
-            cnt += (k1 < key[0]) ? 1u : 0u;
-        }
-        const uint32_t tot = __builtin_amdgcn_readfirstlane(wave_add(valid[0] ? cnt : 0u));
-        if (tot != (uint32_t)(n * (n - 1) / 2)) {
-            exact_pass = true;
-            for (int j = 0; j < n; j++) {
-                const uint64_t kj = S.key_b[j];
-                cnt += (kj == key[0] && j < lane) ? 1u : 0u;
-            }
-        }
-        myrank[0] = valid[0] ? (int)cnt + 1 : 0;
-    } else {
-        // 128 keys whose low 7 bits are replaced by the bit index, sorted by a bitonic
-        // network; if two neighbours then agree in every remaining key bit the truncation
-        // may have decided their order, and the ranks are recomputed by counting
-        uint64_t k64[2];
-#pragma unroll
-        for (int b = 0; b < 2; b++) {
-            const uint64_t id = (uint64_t)(lane + kWave * b);
-            k64[b] = valid[b] ? ((key[b] & ~127ull) | id) : (~127ull | id);
-        }
-        sort64x2<2>(k64, lane);
-        const uint64_t n0 = __shfl_down(k64[0], 1), n1 = __shfl_down(k64[1], 1);
-        const uint64_t first1 = __shfl(k64[1], 0);
-        const uint64_t nx0 = lane == kWave - 1 ? first1 : n0;
-        bool amb = lane + 1 < n && (k64[0] >> 7) == (nx0 >> 7);
-        amb |= lane + kWave + 1 < n && (k64[1] >> 7) == (n1 >> 7);
-        exact_pass = __ballot(amb) != 0ull;
-        if (!exact_pass) {
-#pragma unroll
-            for (int b = 0; b < 2; b++)
-                if (lane + kWave * b < n) S.rank_b[k64[b] & 127ull] = (uint8_t)(lane + kWave * b + 1);
-            wave_sync();
-#pragma unroll
-            for (int b = 0; b < 2; b++) myrank[b] = valid[b] ? S.rank_b[lane + kWave * b] : 0;
-        } else {
-#pragma unroll
-            for (int b = 0; b < 2; b++) S.key_b[lane + kWave * b] = key[b];
-            wave_sync();
-            uint32_t cnt[2] = {0u, 0u};
-            for (int j = 0; j < n; j++) {
-                const uint64_t kj = S.key_b[j];
-#pragma unroll
-                for (int b = 0; b < 2; b++)
-                    cnt[b] += (kj < key[b] || (kj == key[b] && j < lane + kWave * b)) ? 1u : 0u;
-            }
-#pragma unroll
-            for (int b = 0; b < 2; b++) myrank[b] = valid[b] ? (int)cnt[b] + 1 : 0;
-        }
-    }
+    bool exact_pass;
+    if constexpr (NB == 1 && !TABLE) exact_pass = ranks_by_count(key[0], valid[0], n, S, lane, myrank[0]);
+    else exact_pass = ranks_by_network<NS, NB>(key, valid, n, S, lane, myrank);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
