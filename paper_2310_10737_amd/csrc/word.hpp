@@ -265,23 +265,112 @@ __device__ __forceinline__ V load_uniform(const V *p) {
 // length and cost a fifth of the register file.  A kernel that decodes one word
 // takes them as literals (TABLE = false).
 struct CoefSet {
-    double v[29];
+    double v[17];
 };
-constexpr int kInvLn2At = 0, kLn2HiAt = 1, kLn2LoAt = 2;
-constexpr int kExpAt = 3, kExpTerms = 14;                    // 1/13!, 1/12!, ..., 1/1!, 1
-constexpr int kLogAt = kExpAt + kExpTerms, kLogTerms = 12;   // 1/23, 1/21, ..., 1/3, 1
+constexpr int k64InvLn2At = 0, kLn2HiAt = 1, kLn2LoAt = 2, kLn2d64HiAt = 3, kLn2d64LoAt = 4;
+constexpr int kExpAt = 5, kExpTerms = 6;                     // 1/6!, 1/5!, ..., 1/1!
+constexpr int kLogAt = kExpAt + kExpTerms, kLogTerms = 6;    // 1/7, -1/6, ..., -1/2
 constexpr CoefSet kCoefV = {{
-    1.4426950408889634,                 // 1 / ln 2
+    0x1.71547652b82fep+6,               // 64 / ln 2
     0x1.62e42fefa2000p-1,               // ln 2 to 40 bits: k * this is exact for |k| < 2^13
     0x1.9ef35793c7673p-41,              // ln 2 minus the above
-    1.0 / 6227020800.0, 1.0 / 479001600.0, 1.0 / 39916800.0, 1.0 / 3628800.0, 1.0 / 362880.0,
-    1.0 / 40320.0, 1.0 / 5040.0, 1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0, 0.5, 1.0, 1.0,
-    1.0 / 23.0, 1.0 / 21.0, 1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0, 1.0 / 9.0,
-    1.0 / 7.0, 1.0 / 5.0, 1.0 / 3.0, 1.0,
+    0x1.62e42fefa0000p-7,               // ln 2 / 64 to 36 bits: N * this is exact for N < 2^17
+    0x1.cf79abc9e3b3ap-46,              // ln 2 / 64 minus the above
+    1.0 / 720.0, 1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0, 0.5, 1.0,
+    1.0 / 7.0, -1.0 / 6.0, 1.0 / 5.0, -1.0 / 4.0, 1.0 / 3.0, -0.5,
 }};
-static_assert(kLogAt + kLogTerms == 29, "coefficient count");
+static_assert(kLogAt + kLogTerms == 17, "coefficient count");
 static __constant__ CoefSet kCoefTable = kCoefV;
 typedef __attribute__((address_space(4))) const CoefSet ccoef;
+
+// 2^(-j/64), j = 0..63, each rounded to the nearest binary64
+static __constant__ double kExp2Frac[64] = {
+    0x1.0000000000000p+0, 0x1.fa7c1819e90d8p-1, 0x1.f50765b6e4540p-1, 0x1.efa1bee615a27p-1,
+    0x1.ea4afa2a490dap-1, 0x1.e502ee78b3ff6p-1, 0x1.dfc97337b9b5fp-1, 0x1.da9e603db3285p-1,
+    0x1.d5818dcfba487p-1, 0x1.d072d4a07897cp-1, 0x1.cb720dcef9069p-1, 0x1.c67f12e57d14bp-1,
+    0x1.c199bdd85529cp-1, 0x1.bcc1e904bc1d2p-1, 0x1.b7f76f2fb5e47p-1, 0x1.b33a2b84f15fbp-1,
+    0x1.ae89f995ad3adp-1, 0x1.a9e6b5579fdbfp-1, 0x1.a5503b23e255dp-1, 0x1.a0c667b5de565p-1,
+    0x1.9c49182a3f090p-1, 0x1.97d829fde4e50p-1, 0x1.93737b0cdc5e5p-1, 0x1.8f1ae99157736p-1,
+    0x1.8ace5422aa0dbp-1, 0x1.868d99b4492edp-1, 0x1.82589994cce13p-1, 0x1.7e2f336cf4e62p-1,
+    0x1.7a11473eb0187p-1, 0x1.75feb564267c9p-1, 0x1.71f75e8ec5f74p-1, 0x1.6dfb23c651a2fp-1,
+    0x1.6a09e667f3bcdp-1, 0x1.6623882552225p-1, 0x1.6247eb03a5585p-1, 0x1.5e76f15ad2148p-1,
+    0x1.5ab07dd485429p-1, 0x1.56f4736b527dap-1, 0x1.5342b569d4f82p-1, 0x1.4f9b2769d2ca7p-1,
+    0x1.4bfdad5362a27p-1, 0x1.486a2b5c13cd0p-1, 0x1.44e086061892dp-1, 0x1.4160a21f72e2ap-1,
+    0x1.3dea64c123422p-1, 0x1.3a7db34e59ff7p-1, 0x1.371a7373aa9cbp-1, 0x1.33c08b26416ffp-1,
+    0x1.306fe0a31b715p-1, 0x1.2d285a6e4030bp-1, 0x1.29e9df51fdee1p-1, 0x1.26b4565e27cddp-1,
+    0x1.2387a6e756238p-1, 0x1.2063b88628cd6p-1, 0x1.1d4873168b9aap-1, 0x1.1a35beb6fcb75p-1,
+    0x1.172b83c7d517bp-1, 0x1.1429aaea92de0p-1, 0x1.11301d0125b51p-1, 0x1.0e3ec32d3d1a2p-1,
+    0x1.0b5586cf9890fp-1, 0x1.0874518759bc8p-1, 0x1.059b0d3158574p-1, 0x1.02c9a3e778061p-1,
+};
+
+// For the 128 intervals [1/2 + j/256, 1/2 + (j+1)/256) of [1/2, 1), their centres
+// F_j = 1/2 + (j + 1/2)/256: {1/F_j, ln F_j}, each rounded to the nearest binary64
+static __constant__ double2 kLogCentre[128] = {
+    {0x1.fe01fe01fe020p+0, -0x1.60e52f45788e3p-1}, {0x1.fa11caa01fa12p+0, -0x1.5ced1e17c35c5p-1},
+    {0x1.f6310aca0dbb5p+0, -0x1.58fcddce004c4p-1}, {0x1.f25f644230ab5p+0, -0x1.55144fdbcbd62p-1},
+    {0x1.ee9c7f8458e02p+0, -0x1.513356667fc57p-1}, {0x1.eae807aba01ebp+0, -0x1.4d59d43fdaba2p-1},
+    {0x1.e741aa59750e4p+0, -0x1.4987ace0dabb0p-1}, {0x1.e3a9179dc1a73p+0, -0x1.45bcc464c893ap-1},
+    {0x1.e01e01e01e01ep+0, -0x1.41f8ff8471d61p-1}, {0x1.dca01dca01dcap+0, -0x1.3e3c43918f76cp-1},
+    {0x1.d92f2231e7f8ap+0, -0x1.3a86767257111p-1}, {0x1.d5cac807572b2p+0, -0x1.36d77e9d34fd7p-1},
+    {0x1.d272ca3fc5b1ap+0, -0x1.332f4314ad796p-1}, {0x1.cf26e5c44bfc6p+0, -0x1.2f8dab636337ap-1},
+    {0x1.cbe6d9601cbe7p+0, -0x1.2bf29f9841c3bp-1}, {0x1.c8b265afb8a42p+0, -0x1.285e0842ca384p-1},
+    {0x1.c5894d10d4986p+0, -0x1.24cfce6f80d9ap-1}, {0x1.c26b5392ea01cp+0, -0x1.2147dba47a394p-1},
+    {0x1.bf583ee868d8bp+0, -0x1.1dc619de06944p-1}, {0x1.bc4fd65883e7bp+0, -0x1.1a4a738b7a33cp-1},
+    {0x1.b951e2b18ff23p+0, -0x1.16d4d38c119fap-1}, {0x1.b65e2e3beee05p+0, -0x1.1365252bf0865p-1},
+    {0x1.b37484ad806cep+0, -0x1.0ffb54213a476p-1}, {0x1.b094b31d922a4p+0, -0x1.0c974c89431cep-1},
+    {0x1.adbe87f94905ep+0, -0x1.0938fae5d8e9bp-1}, {0x1.aaf1d2f87ebfdp+0, -0x1.05e04c1aa2c06p-1},
+    {0x1.a82e65130e159p+0, -0x1.028d2d6a963f4p-1}, {0x1.a574107688a4ap+0, -0x1.fe7f18eb03d3ep-2},
+    {0x1.a2c2a87c51ca0p+0, -0x1.f7eeae6b5761dp-2}, {0x1.a01a01a01a01ap+0, -0x1.f168f7fb05c52p-2},
+    {0x1.9d79f176b682dp+0, -0x1.eaedd2eac990cp-2}, {0x1.9ae24ea5510dap+0, -0x1.e47d1d32e677ep-2},
+    {0x1.9852f0d8ec0ffp+0, -0x1.de16b56ef90f0p-2}, {0x1.95cbb0be377aep+0, -0x1.d7ba7ad9e7da0p-2},
+    {0x1.934c67f9b2ce6p+0, -0x1.d1684d49f46aep-2}, {0x1.90d4f120190d5p+0, -0x1.cb200d2ceb643p-2},
+    {0x1.8e6527af1373fp+0, -0x1.c4e19b84723c2p-2}, {0x1.8bfce8062ff3ap+0, -0x1.beacd9e271ad1p-2},
+    {0x1.899c0f601899cp+0, -0x1.b881aa659bc93p-2}, {0x1.87427bcc092b9p+0, -0x1.b25fefb60cb2ep-2},
+    {0x1.84f00c2780614p+0, -0x1.ac478d020506fp-2}, {0x1.82a4a0182a4a0p+0, -0x1.a63865fabd0ecp-2},
+    {0x1.8060180601806p+0, -0x1.a0325ed14fda4p-2}, {0x1.7e225515a4f1dp+0, -0x1.9a355c33bd6bap-2},
+    {0x1.7beb3922e017cp+0, -0x1.9441434a03259p-2}, {0x1.79baa6bb6398bp+0, -0x1.8e55f9b349b83p-2},
+    {0x1.77908119ac60dp+0, -0x1.8873658327ccfp-2}, {0x1.756cac201756dp+0, -0x1.82996d3ef8bcbp-2},
+    {0x1.734f0c541fe8dp+0, -0x1.7cc7f7db46a0ep-2}, {0x1.713786d9c7c09p+0, -0x1.76feecb947175p-2},
+    {0x1.6f26016f26017p+0, -0x1.713e33a46a17cp-2}, {0x1.6d1a62681c861p+0, -0x1.6b85b4cffa3fdp-2},
+    {0x1.6b1490aa31a3dp+0, -0x1.65d558d4ce00bp-2}, {0x1.691473a88d0c0p+0, -0x1.602d08af091ecp-2},
+    {0x1.6719f3601671ap+0, -0x1.5a8cadbbedfa1p-2}, {0x1.6524f853b4aa3p+0, -0x1.54f431b7be1a9p-2},
+    {0x1.63356b88ac0dep+0, -0x1.4f637ebba9810p-2}, {0x1.614b36831ae94p+0, -0x1.49da7f3bcc41fp-2},
+    {0x1.5f66434292dfcp+0, -0x1.44591e0539f49p-2}, {0x1.5d867c3ece2a5p+0, -0x1.3edf463c1683ep-2},
+    {0x1.5babcc647fa91p+0, -0x1.396ce359bbf54p-2}, {0x1.59d61f123ccaap+0, -0x1.3401e12aecba1p-2},
+    {0x1.5805601580560p+0, -0x1.2e9e2bce12286p-2}, {0x1.56397ba7c52e2p+0, -0x1.2941afb186b7cp-2},
+    {0x1.54725e6bb82fep+0, -0x1.23ec5991eba49p-2}, {0x1.52aff56a8054bp+0, -0x1.1e9e1678899f4p-2},
+    {0x1.50f22e111c4c5p+0, -0x1.1956d3b9bc2fap-2}, {0x1.4f38f62dd4c9bp+0, -0x1.14167ef367783p-2},
+    {0x1.4d843bedc2c4cp+0, -0x1.0edd060b78081p-2}, {0x1.4bd3edda68fe1p+0, -0x1.09aa572e6c6d4p-2},
+    {0x1.4a27fad76014ap+0, -0x1.047e60cde83b8p-2}, {0x1.4880522014880p+0, -0x1.feb2233ea07cdp-3},
+    {0x1.46dce34596066p+0, -0x1.f474b134df229p-3}, {0x1.453d9e2c776cap+0, -0x1.ea4449f04aaf5p-3},
+    {0x1.43a2730abee4dp+0, -0x1.e020cc6235ab5p-3}, {0x1.420b5265e5951p+0, -0x1.d60a17f903515p-3},
+    {0x1.40782d10e6566p+0, -0x1.cc000c9db3c52p-3}, {0x1.3ee8f42a5af07p+0, -0x1.c2028ab17f9b4p-3},
+    {0x1.3d5d991aa75c6p+0, -0x1.b811730b823d2p-3}, {0x1.3bd60d9232955p+0, -0x1.ae2ca6f672bd4p-3},
+    {0x1.3a524387ac822p+0, -0x1.a454082e6ab05p-3}, {0x1.38d22d366088ep+0, -0x1.9a8778debaa38p-3},
+    {0x1.3755bd1c945eep+0, -0x1.90c6db9fcbcd9p-3}, {0x1.35dce5f9f2af8p+0, -0x1.871213750e994p-3},
+    {0x1.34679ace01346p+0, -0x1.7d6903caf5ad0p-3}, {0x1.32f5ced6a1dfap+0, -0x1.73cb9074fd14dp-3},
+    {0x1.3187758e9ebb6p+0, -0x1.6a399dabbd383p-3}, {0x1.301c82ac40260p+0, -0x1.60b3100b09476p-3},
+    {0x1.2eb4ea1fed14bp+0, -0x1.5737cc9018cddp-3}, {0x1.2d50a012d50a0p+0, -0x1.4dc7b897bc1c8p-3},
+    {0x1.2bef98e5a3711p+0, -0x1.4462b9dc9b3dcp-3}, {0x1.2a91c92f3c105p+0, -0x1.3b08b6757f2a9p-3},
+    {0x1.293725bb804a5p+0, -0x1.31b994d3a4f85p-3}, {0x1.27dfa38a1ce4dp+0, -0x1.28753bc11aba5p-3},
+    {0x1.268b37cd60127p+0, -0x1.1f3b925f25d41p-3}, {0x1.2539d7e9177b2p+0, -0x1.160c8024b27b1p-3},
+    {0x1.23eb79717605bp+0, -0x1.0ce7ecdccc28dp-3}, {0x1.22a0122a0122ap+0, -0x1.03cdc0a51ec0dp-3},
+    {0x1.21579804855e6p+0, -0x1.f57bc7d9005dbp-4}, {0x1.2012012012012p+0, -0x1.e3707ee30487bp-4},
+    {0x1.1ecf43c7fb84cp+0, -0x1.d179788219364p-4}, {0x1.1d8f5672e4abdp+0, -0x1.bf968769fca11p-4},
+    {0x1.1c522fc1ce059p+0, -0x1.adc77ee5aea8cp-4}, {0x1.1b17c67f2bae3p+0, -0x1.9c0c32d4d2548p-4},
+    {0x1.19e0119e0119ep+0, -0x1.8a6477a91dc29p-4}, {0x1.18ab083902bdbp+0, -0x1.78d02263d82d3p-4},
+    {0x1.1778a191bd684p+0, -0x1.674f089365a7ap-4}, {0x1.1648d50fc3201p+0, -0x1.55e10050e0384p-4},
+    {0x1.151b9a3fdd5c9p+0, -0x1.4485e03dbdfadp-4}, {0x1.13f0e8d344724p+0, -0x1.333d7f8183f4bp-4},
+    {0x1.12c8b89edc0acp+0, -0x1.2207b5c78549ep-4}, {0x1.11a3019a74826p+0, -0x1.10e45b3cae831p-4},
+    {0x1.107fbbe011080p+0, -0x1.ffa6911ab9301p-5}, {0x1.0f5edfab325a2p+0, -0x1.dda8adc67ee4ep-5},
+    {0x1.0e40655826011p+0, -0x1.bbcebfc68f420p-5}, {0x1.0d24456359e3ap+0, -0x1.9a187b573de7cp-5},
+    {0x1.0c0a7868b4171p+0, -0x1.788595a3577bap-5}, {0x1.0af2f722eecb5p+0, -0x1.5715c4c03ceefp-5},
+    {0x1.09ddba6af8360p+0, -0x1.35c8bfaa1306bp-5}, {0x1.08cabb37565e2p+0, -0x1.149e3e4005a8dp-5},
+    {0x1.07b9f29b8eae2p+0, -0x1.e72bf2813ce51p-6}, {0x1.06ab59c7912fbp+0, -0x1.a55f548c5c43fp-6},
+    {0x1.059eea0727586p+0, -0x1.63d6178690bd6p-6}, {0x1.04949cc1664c5p+0, -0x1.228fb1fea2e28p-6},
+    {0x1.038c6b78247fcp+0, -0x1.c317384c75f06p-7}, {0x1.02864fc7729e9p+0, -0x1.41929f96832f0p-7},
+    {0x1.0182436517a37p+0, -0x1.8121214586b54p-8}, {0x1.0080402010080p+0, -0x1.0040155d5889ep-9},
+};
 
 template <bool TABLE>
 struct Coef {
@@ -298,67 +387,54 @@ struct Coef {
     }
 };
 
-// 1/x for positive normal x: hardware reciprocal and two Newton steps
-__device__ __forceinline__ double rcp_nr(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-
-// e^{-a}, a >= 0: Cody-Waite reduction a = k ln2 + r with |r| <= ln2/2, then the
-// degree-13 Taylor polynomial of e^{-r} (truncation below 2^-57 relative)
+// e^{-a}, a >= 0, by Tang's table-driven method (ACM TOMS 15(2), 1989): a = N ln2/64 + r
+// with |r| <= ln2/128 (Cody-Waite, two-part ln2/64), N = 64k + j, and
+// e^{-a} = 2^{-k} 2^{-j/64} e^{-r}, with e^{-r} from its degree-6 Taylor polynomial
+// (truncation below 2^-64 relative)
 template <bool TABLE>
 __device__ __forceinline__ double exp_neg(double a) {
     const Coef<TABLE> t;
     const double ac = a < 1100.0 ? a : 1100.0;
-    const double k = rint(ac * t[kInvLn2At]);
-    double r = fma(-k, t[kLn2HiAt], ac);
-    r = fma(-k, t[kLn2LoAt], r);
+    const double N = rint(ac * t[k64InvLn2At]);
+    double r = fma(-N, t[kLn2d64HiAt], ac);
+    r = fma(-N, t[kLn2d64LoAt], r);
     const double x = -r;
     double p = t[kExpAt];
 #pragma unroll
     for (int j = 1; j < kExpTerms; j++) p = fma(p, x, t[kExpAt + j]);
-    return ldexp(p, -(int)k);
+    p = fma(p, x, 1.0);
+    const int Ni = (int)N;
+    return ldexp(kExp2Frac[Ni & 63] * p, -(Ni >> 6));
 }
 
-// ln x for finite x > 0 of normal magnitude: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
-// ln m = 2 atanh(s) = 2 s sum_j s^{2j} / (2j + 1) with s = (m - 1)/(m + 1), |s| < 0.1716
+// ln m for m in [1/2, 1), by Tang's table-driven method (ACM TOMS 16(4), 1990): with F
+// the centre of m's interval of width 1/256 (m's leading 8 mantissa bits and a 1 after
+// them), f = m - F is exact, u = f / F (|u| < 2^-8), and ln m = ln F + ln(1 + u), the
+// latter from its degree-7 series (truncation below 2^-67)
 template <bool TABLE>
-__device__ __forceinline__ double log_pos(double x) {
-    double m = __builtin_amdgcn_frexp_mant(x);
-    int e = __builtin_amdgcn_frexp_exp(x);
-    if (m < 0.70710678118654752) {
-        m = m + m;
-        e -= 1;
-    }
-    const double num = m - 1.0, den = m + 1.0;
-    const double rd = rcp_nr(den);
-    double s = num * rd;
-    s = fma(fma(-den, s, num), rd, s);
-    const double z = s * s;
+__device__ __forceinline__ double log_mant(double m) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(m);
+    const uint32_t hi = (uint32_t)(bits >> 32);
+    const double F = __longlong_as_double((long long)((uint64_t)((hi & 0xffffe000u) | 0x1000u) << 32));
+    const double2 cl = kLogCentre[(hi >> 13) & 127u];
+    const double u = (m - F) * cl.x;
     const Coef<TABLE> t;
     double p = t[kLogAt];
 #pragma unroll
-    for (int j = 1; j < kLogTerms; j++) p = fma(p, z, t[kLogAt + j]);
-    const double lm = (s + s) * p;
-    const double de = (double)e;
-    return fma(de, t[kLn2HiAt], fma(de, t[kLn2LoAt], lm));
+    for (int j = 1; j < kLogTerms; j++) p = fma(p, u, t[kLogAt + j]);
+    p = fma(p, u, 1.0);
+    return fma(p, u, cl.y);
 }
 
-// ln(N0 / N1) for N0, N1 >= 0 not both zero: the mantissas' ratio (in (1/2, 2)) goes
-// through ln, the exponents' difference is added as a multiple of ln 2
+// ln(N0 / N1) for N0, N1 >= 0 not both zero: N = m 2^e with m in [1/2, 1); the
+// exponents' difference is added as a multiple of ln 2
 template <bool TABLE>
 __device__ __forceinline__ double log_ratio(double n0, double n1) {
     const double m0 = __builtin_amdgcn_frexp_mant(n0), m1 = __builtin_amdgcn_frexp_mant(n1);
     const int e0 = __builtin_amdgcn_frexp_exp(n0), e1 = __builtin_amdgcn_frexp_exp(n1);
-    const double r = rcp_nr(m1);
-    double q = m0 * r;
-    q = fma(fma(-m1, q, m0), r, q);
     const double de = (double)(e0 - e1);
     const Coef<TABLE> t;
-    double la = fma(de, t[kLn2HiAt], fma(de, t[kLn2LoAt], log_pos<TABLE>(q)));
+    double la = fma(de, t[kLn2HiAt], fma(de, t[kLn2LoAt], log_mant<TABLE>(m0) - log_mant<TABLE>(m1)));
     if (n1 == 0.0) la = 1000.0;
     if (n0 == 0.0) la = -1000.0;
     return la;
@@ -700,14 +776,14 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     const bool degenerate = !(D > 0.0) || !isfinite(D);
     if (degenerate) pnf = 1.0;   // every probability underflowed: keep the soft input
 
-    // eq. (LLRi): list codewords weighted by their APPs, plus the soft input weighted by P_nf
+    // eq. (LLRi): list codewords weighted by their APPs, plus the soft input weighted by
+    // P_nf.  Both sums are taken times 1 + rho, which leaves their ratio unchanged, so the
+    // soft input's p(bit = y) = 1/(1 + rho) and p(bit != y) = rho/(1 + rho) enter as 1 and rho.
     double N0[NB], N1[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const double qs = rcp_nr(1.0 + rho[b]);   // p(bit = y | soft input)
-        const double qf = rho[b] * qs;            // p(bit != y | soft input)
-        N0[b] = pnf * (ybit[b] ? qf : qs);
-        N1[b] = pnf * (ybit[b] ? qs : qf);
+        N0[b] = 0.0;
+        N1[b] = 0.0;
     }
     if (!degenerate) {
         const double invD = 1.0 / D;
@@ -727,6 +803,13 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
                 N0[b] += one ? 0.0 : P;
             }
         }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const double opr = 1.0 + rho[b];
+        const double sy = pnf, sf = pnf * rho[b];
+        N0[b] = fma(opr, N0[b], ybit[b] ? sf : sy);
+        N1[b] = fma(opr, N1[b], ybit[b] ? sy : sf);
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
