@@ -713,15 +713,38 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
                 }
             }
         }
-        uint64_t m = __ballot(act && s == 0u);
+        const bool hit = act && s == 0u;
+        uint64_t m = __ballot(hit);
         int cut = kWave - 1;
+        if constexpr (!STOP) {
+            // every hit that still fits in the list writes its own entry (slot = hits so far
+            // plus the hits of lower lanes); the L-th hit, if there is one, is the cut
+            if (m != 0ull) {
+                const int nh = __popcll(m);
+                const uint32_t slot = (uint32_t)found + __builtin_amdgcn_mbcnt_hi(
+                                          (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (hit && slot < (uint32_t)L) {
+                    S.tau_l[slot] = tau;
+                    S.q_l[slot] = base + (uint32_t)lane + 1u;
+                    S.pat_l[slot] = e;
+                }
+                if (found + nh >= L) {
+                    uint64_t mm = m;
+                    for (int k = found + 1; k < L; k++) mm &= mm - 1ull;
+                    cut = __builtin_ctzll(mm);
+                    found = L;
+                } else {
+                    found += nh;
+                }
+            }
+        }
         // tested nonzero-pattern mass before this chunk (only needed by the list-BLER stop)
         const bool check = STOP && m != 0ull;
         double s_before = 0.0;
         if constexpr (STOP) {
             if (check) s_before = bcast0(wave_sum(s_lane));
         }
-        while (m != 0ull && found < L && !stopped) {
+        while (STOP && m != 0ull && found < L && !stopped) {
             const int h = __builtin_ctzll(m);
             m &= m - 1ull;
             const uint32_t hx = __builtin_amdgcn_readlane(e.x, h);
