@@ -611,6 +611,9 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
             S.ent_r[myrank[b]].z = c.hcol[i];
             put_rho(S, myrank[b], rho[b]);
             S.pi_r[myrank[b]] = (uint8_t)i;
+        } else if (i < NS) {
+            // ranks n+1 .. NS carry rho = 0, so that step 3 folds NS ranks without a guard
+            put_rho(S, i + 1, 0.0);
         }
         if (i < SOGRAND_NMAX) S.zmask[i] = 0u;
     }
@@ -622,12 +625,13 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
 
     // 3. parity-class masses: adding bit i maps (E, O) to (E + O rho_i, O + (1 + E) rho_i);
     //    two disjoint bit sets combine as E = E1 + E2 + E1 E2 + O1 O2, O = O1 + O2 + E1 O2 + O1 E2.
-    //    Lane t folds ranks 8t+1 .. 8t+8 in turn, then NS/8 lanes combine pairwise.
-    double E = 0.0, O = 0.0;
+    //    Lane t folds ranks 8t+1 .. 8t+8 in turn, then NS/8 lanes combine pairwise (lanes
+    //    past NS/8 repeat the last group; their sums are never combined into lane 0's).
+    const int grp = lane < NS / 8 ? lane : NS / 8 - 1;
+    double E = 0.0, O = rho_at(S, 8 * grp + 1);   // the first rank from (0, 0): (0, rho)
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-        const int r = 8 * lane + j + 1;
-        const double rr = r <= n ? rho_at(S, r < SOGRAND_NMAX ? r : SOGRAND_NMAX) : 0.0;
+    for (int j = 1; j < 8; j++) {
+        const double rr = rho_at(S, 8 * grp + j + 1);
         const double e2 = E + O * rr;
         const double o2 = O + (1.0 + E) * rr;
         E = e2;
@@ -817,13 +821,18 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
             const int i = lane + kWave * b;
             zm[b] = i < SOGRAND_NMAX ? S.zmask[i] : 0u;
         }
+        // bit l of zm: the bit of list codeword l is 1 (y XOR its error pattern); the
+        // products with 0.0 and 1.0 are exact, so each sum gets exactly its own terms
+#pragma unroll
+        for (int b = 0; b < NB; b++) zm[b] ^= ybit[b] ? 0xffffffffu : 0u;
+#pragma unroll 2
         for (int l = 0; l < found; l++) {
             const double P = S.tau_l[l] * invD;
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                const bool one = (ybit[b] ^ (int)((zm[b] >> l) & 1u)) != 0;
-                N1[b] += one ? P : 0.0;
-                N0[b] += one ? 0.0 : P;
+                const double one = (double)((zm[b] >> l) & 1u);
+                N1[b] = fma(P, one, N1[b]);
+                N0[b] = fma(P, 1.0 - one, N0[b]);
             }
         }
     }
