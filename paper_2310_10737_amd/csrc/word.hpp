@@ -148,6 +148,20 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// inclusive prefix sum over lanes: lane l gets v(0) + ... + v(l), added in lane order
+// at distances 1, 2, 4, ..., 32 (Hillis-Steele)
+__device__ __forceinline__ double wave_scan_add(double v, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t u = (uint64_t)__double_as_longlong(v);
+        const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)u, d);
+        const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(u >> 32), d);
+        const double t = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
 __device__ __forceinline__ double bcast0(double v) {
     uint64_t u = (uint64_t)__double_as_longlong(v);
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
@@ -718,20 +732,22 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
             }
         }
         const bool hit = act && s == 0u;
-        uint64_t m = __ballot(hit);
+        const uint64_t m = __ballot(hit);
         int cut = kWave - 1;
-        if constexpr (!STOP) {
+        if (m != 0ull) {
             // every hit that still fits in the list writes its own entry (slot = hits so far
-            // plus the hits of lower lanes); the L-th hit, if there is one, is the cut
-            if (m != 0ull) {
-                const int nh = __popcll(m);
-                const uint32_t slot = (uint32_t)found + __builtin_amdgcn_mbcnt_hi(
-                                          (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                if (hit && slot < (uint32_t)L) {
-                    S.tau_l[slot] = tau;
-                    S.q_l[slot] = base + (uint32_t)lane + 1u;
-                    S.pat_l[slot] = e;
-                }
+            // plus the hits of lower lanes); with the list-BLER stop, entries past the stop
+            // are written too and ignored
+            const int nh = __popcll(m);
+            const uint32_t slot = (uint32_t)found + __builtin_amdgcn_mbcnt_hi(
+                                      (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (hit && slot < (uint32_t)L) {
+                S.tau_l[slot] = tau;
+                S.q_l[slot] = base + (uint32_t)lane + 1u;
+                S.pat_l[slot] = e;
+            }
+            if constexpr (!STOP) {
+                // the L-th hit, if there is one, is the cut
                 if (found + nh >= L) {
                     uint64_t mm = m;
                     for (int k = found + 1; k < L; k++) mm &= mm - 1ull;
@@ -740,42 +756,32 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
                 } else {
                     found += nh;
                 }
-            }
-        }
-        // tested nonzero-pattern mass before this chunk (only needed by the list-BLER stop)
-        const bool check = STOP && m != 0ull;
-        double s_before = 0.0;
-        if constexpr (STOP) {
-            if (check) s_before = bcast0(wave_sum(s_lane));
-        }
-        while (STOP && m != 0ull && found < L && !stopped) {
-            const int h = __builtin_ctzll(m);
-            m &= m - 1ull;
-            const uint32_t hx = __builtin_amdgcn_readlane(e.x, h);
-            const uint32_t hy = __builtin_amdgcn_readlane(e.y, h);
-            const uint32_t hz = __builtin_amdgcn_readlane(e.z, h);
-            const uint32_t hw = __builtin_amdgcn_readlane(e.w, h);
-            const double th = readlane_f64(tau, h);
-            if (lane == 0) {
-                S.tau_l[found] = th;
-                S.q_l[found] = base + (uint32_t)h + 1u;
-                S.pat_l[found] = make_uint4(hx, hy, hz, hw);
-            }
-            found++;
-            if (found == L) cut = h;
-            else if (STOP && check) {
-                // list-BLER stop: Corollary 1 for the list so far, with the mass tested up
-                // to and including this query (class mass relative to p(0|r), nonzero
-                // patterns only)
+            } else {
+                // list-BLER stop, tested at each hit before the L-th in query order: Corollary 1
+                // for the list so far, with the mass tested up to and including the hit (class
+                // mass relative to p(0|r), nonzero patterns only)
                 const double T = c.even ? (par ? O : E) : (E + O);
-                const double pre = (act && (e.x & 0xffu) != 0u && lane <= h) ? tau : 0.0;
-                double Mi = T - (s_before + bcast0(wave_sum(pre)));
-                if (!(Mi > 0.0)) Mi = 0.0;
-                double Di = Mi * c.phi;
-                for (int l = 0; l < found; l++) Di += S.tau_l[l];
-                if ((Mi * c.phi) / Di < pstop) {
-                    stopped = true;
-                    cut = h;
+                const double s_before = bcast0(wave_sum(s_lane));
+                const double tested = wave_scan_add((act && (e.x & 0xffu) != 0u) ? tau : 0.0, lane);
+                wave_sync();
+                uint64_t mm = m;
+                while (mm != 0ull) {
+                    const int h = __builtin_ctzll(mm);
+                    mm &= mm - 1ull;
+                    found++;
+                    if (found == L) {
+                        cut = h;
+                        break;
+                    }
+                    double Mi = T - (s_before + readlane_f64(tested, h));
+                    if (!(Mi > 0.0)) Mi = 0.0;
+                    double Di = Mi * c.phi;
+                    for (int l = 0; l < found; l++) Di += S.tau_l[l];
+                    if ((Mi * c.phi) / Di < pstop) {
+                        stopped = true;
+                        cut = h;
+                        break;
+                    }
                 }
             }
         }
@@ -799,9 +805,10 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     if (!(M > 0.0)) M = 0.0;
     double D = M * c.phi;
     for (int l = 0; l < found; l++) D += S.tau_l[l];
-    double pnf = (M * c.phi) / D;
     const bool degenerate = !(D > 0.0) || !isfinite(D);
-    if (degenerate) pnf = 1.0;   // every probability underflowed: keep the soft input
+    const double invD = 1.0 / (degenerate ? 1.0 : D);
+    // every probability underflowed: keep the soft input
+    const double pnf = degenerate ? 1.0 : (M * c.phi) * invD;
 
     // eq. (LLRi): list codewords weighted by their APPs, plus the soft input weighted by
     // P_nf.  Both sums are taken times 1 + rho, which leaves their ratio unchanged, so the
@@ -813,7 +820,6 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         N1[b] = 0.0;
     }
     if (!degenerate) {
-        const double invD = 1.0 / D;
         mark_found(S, found, lane);
         uint32_t zm[NB];
 #pragma unroll
