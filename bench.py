@@ -41,8 +41,8 @@ PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # VALU lane-operations: 256 CUs x 64 l
 SNRS = ((2.5, 1), (3.0, 2), (3.5, 3))
 N, K, L, QCAP, ITERS = 64, 57, 4, 10000, 6
 MIX_CODES = ((32, 26), (64, 57), (128, 120))
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "product_pass_64x57_hbm_bytes.md")
-KERNEL_SOURCES = ("word.hpp", "decode.hip", "internal.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "product_64x57_hbm_bytes.md")
+KERNEL_SOURCES = ("word.hpp", "decode.hip", "batched.hip", "internal.hpp")
 
 
 def ops_per_word(n: int, lst: int) -> int:
@@ -81,8 +81,9 @@ def kernel_digest() -> str:
 
 
 def recorded_traffic(form: str):
-    """HBM bytes per launch of the row/column pass kernel, from the committed counter summary,
-    if it was taken on the current kernel sources (else None)."""
+    """HBM bytes per launch of the form's dominant kernel (the row/column pass kernel, or the
+    persistent kernel), from the committed counter summary, if it was taken on the current
+    kernel sources (else None)."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
@@ -285,7 +286,8 @@ def bench_product(args, sg, np, torch, synth):
     # roofline of the dominant kernel of the chosen form: the row/column pass kernel of the
     # plain forms, the persistent kernel of the batched forms
     if best_name.startswith("batched"):
-        roof = roofline("batched", "k_batched (persistent)", best["kernels"], best["work"], args.steps, N, L)
+        roof = roofline("batched", "k_batched (persistent)", best["kernels"], best["work"], args.steps, N, L,
+                        traffic=recorded_traffic(best_name))
     else:
         roof = roofline("product_pass", "k_product_pass (row and column instantiations)", best["kernels"],
                         best["work"], args.steps, N, L, traffic=recorded_traffic(best_name))
@@ -468,12 +470,18 @@ def bench_component(args, sg, np, torch, synth):
     cpu = None
     if not args.no_cpu and args.cpu_words > 0:
         import oracle
+        from concurrent.futures import ThreadPoolExecutor
         m = min(args.cpu_words, W)
+        threads = min(16, len(os.sched_getaffinity(0)))
+        sample = llr[:m].astype(np.float32).astype(np.float64)
+        parts = np.array_split(sample, threads)
         t0 = time.perf_counter()
-        oracle.decode_component(code, llr[:m].astype(np.float32).astype(np.float64), 4, qcap)
+        # the oracle's C entry point releases the interpreter lock, so the threads run in parallel
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda part: oracle.decode_component(code, part, 4, qcap), parts))
         dt = time.perf_counter() - t0
-        cpu = dict(value=m * 120 / dt, unit="info bits/s", cores=1, kind="oracle",
-                   sample=f"first {m} words, L=4, {dt:.1f} s wall")
+        cpu = dict(value=m * 120 / dt, unit="info bits/s", cores=threads, kind="oracle",
+                   sample=f"first {m} words in {threads} equal parts, L=4, {dt:.1f} s wall")
     config = {"workload": f"{W} independent eBCH [128,120] words, BPSK-AWGN 4.0 dB, query cap {qcap}, "
                           "L=4 FP32 storage (L=1 and FP64 in forms)", "form": "L4_f32", "parallelism": "single GPU"}
     return base_line(args, "decoded info bits/s (component words)", head["info_bits_per_s"], "info bits/s",
@@ -583,7 +591,7 @@ def main() -> int:
     ap.add_argument("--list-bler-stop", type=float, default=0.0,
                     help="product workload: end a word's search once its predicted list-BLER is below this")
     ap.add_argument("--cpu-frames", type=int, default=None, help="oracle sample: frames (per Eb/N0 for product)")
-    ap.add_argument("--cpu-words", type=int, default=1 << 14, help="oracle sample: component words")
+    ap.add_argument("--cpu-words", type=int, default=1 << 20, help="oracle sample: component words")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="plain_f64,plain_f32,batched_f64,batched_f32")
     ap.add_argument("--tune", action="store_true",
@@ -601,7 +609,7 @@ def main() -> int:
     if args.frames is None:
         args.frames = 10000
     if args.cpu_frames is None:
-        args.cpu_frames = {"product": 10000, "mixed": 240}.get(args.workload, 0)
+        args.cpu_frames = {"product": 10000, "mixed": 4000}.get(args.workload, 0)
 
     import numpy as np
     import torch
