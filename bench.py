@@ -18,6 +18,10 @@ Other workloads, each printing its own line:
              (seed 6), codes uniform over the three above, Eb/N0 uniform in
              [2.5, 4.0] dB, FP32, L = 4, cap 10^5, 6 iterations, served by
              continuous batching; p50/p99 latency from arrival to result.
+  gldpc      the (1024, 640) QC-GLDPC code with [32,26] eBCH check nodes at
+             Eb/N0 = 2.0, 2.25 and 2.5 dB, 10^4 frames each (seeds 11-13),
+             L = 4, cap 10^4, alpha = 0.6, 20 iterations, list-BLER stop 10^-5
+             (the paper's GLDPC settings); plain FP64 and FP32 storage.
 
 Prints one JSON line.  `value` is decoded information bits per second of the
 fastest form whose BLER matches the plain binary64 form (product workload).
@@ -489,6 +493,82 @@ def bench_component(args, sg, np, torch, synth):
 
 
 # --------------------------------------------------------------------------------------------
+# gldpc: the (1024, 640) QC-GLDPC code with [32,26] eBCH check nodes
+# --------------------------------------------------------------------------------------------
+GLDPC_SNRS = ((2.0, 11), (2.25, 12), (2.5, 13))
+GLDPC_ALPHA, GLDPC_ITERS, GLDPC_STOP = 0.6, 20, 1e-5
+
+
+def bench_gldpc(args, sg, np, torch, synth):
+    dev = torch.device("cuda:0")
+    code = synth.ebch(32, 26)
+    g = synth.gldpc(code)
+    gcode = sg.Code.ebch(32, 26)
+    n = code.n
+    F = args.frames
+    llr_parts, cw_parts = [], []
+    for snr, seed in GLDPC_SNRS:
+        llr, cw, _ = synth.gldpc_frames(g, snr, seed, np.arange(F))
+        llr_parts.append(llr)
+        cw_parts.append(cw)
+    llr_all = np.concatenate(llr_parts)
+    cw_all = torch.from_numpy(np.concatenate(cw_parts)).to(dev)
+    x64 = torch.from_numpy(llr_all).to(dev)
+    x32 = x64.float()
+    total = x64.shape[0]
+    info_bits_per_step = total * g.dim
+    forms = {}
+    for form in [f for f in args.forms.split(",") if f.startswith("plain")]:
+        x = x64 if form.endswith("f64") else x32
+        out = dict(hard=torch.empty((total, n, n), dtype=torch.uint8, device=dev), llr_app=None,
+                   success=torch.empty(total, dtype=torch.uint8, device=dev),
+                   half_iters=torch.empty(total, dtype=torch.int16, device=dev),
+                   sum_queries=torch.empty(total, dtype=torch.int64, device=dev),
+                   sum_max_queries=torch.empty(total, dtype=torch.int64, device=dev))
+        step = (lambda x_, o_: lambda: sg.sogrand_decode_gldpc(
+            gcode, x_, list_max=L, query_cap=QCAP, max_iter=GLDPC_ITERS, alpha=GLDPC_ALPHA, outputs=o_,
+            list_bler_stop=GLDPC_STOP))(x, out)
+        ms, kern, work = timed(step, args.steps, args.warmup, sg, count=not args.no_count)
+        err = torch.any((out["hard"] != cw_all).view(total, -1), dim=1).cpu().numpy()
+        hi = out["half_iters"].double().cpu().numpy()
+        sq = out["sum_queries"].double().cpu().numpy()
+        smq = out["sum_max_queries"].double().cpu().numpy()
+        per_snr = {}
+        for j, (snr, _) in enumerate(GLDPC_SNRS):
+            sl = slice(j * F, (j + 1) * F)
+            k_err = int(err[sl].sum())
+            per_snr[str(snr)] = dict(
+                bler=k_err / F, bler_ci95=wilson(k_err, F), frames=F,
+                avg_iterations=float(hi[sl].mean() / 2), queries_per_bit=float(sq[sl].mean() / (n * n)),
+                parallel_queries_per_bit=float(smq[sl].mean() / (n * n)))
+        forms[form] = dict(ms_per_step=ms, info_bits_per_s=info_bits_per_step / (ms / 1e3), per_snr=per_snr,
+                           kernels=kern, work=work)
+    best_name = min(forms, key=lambda k: forms[k]["ms_per_step"])
+    best = forms[best_name]
+    roof = roofline("product_pass", "k_product_pass (QC-GLDPC layout, both block rows)", best["kernels"],
+                    best["work"], args.steps, n, L)
+    cpu = None
+    if not args.no_cpu and args.cpu_frames > 0:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        cf = min(args.cpu_frames, F)
+        sample = np.concatenate([llr_all[j * F:j * F + cf] for j in range(len(GLDPC_SNRS))])
+        t0 = time.perf_counter()
+        oracle.decode_gldpc(code, sample, L, QCAP, GLDPC_ITERS, GLDPC_ALPHA, pstop=GLDPC_STOP, nthreads=threads)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=sample.shape[0] * g.dim / dt, unit="info bits/s", cores=threads, kind="oracle",
+                   sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall")
+    config = {"workload": f"QC-GLDPC (1024, {g.dim}) with [32,26] eBCH check nodes (the paper's (1024,640)), "
+                          f"BPSK-AWGN 2.0/2.25/2.5 dB, {F} frames each, L=4, query cap 1e4, alpha 0.6, "
+                          "20 iterations, list-BLER stop 1e-5",
+              "form": best_name, "info_bits_per_frame": g.dim, "frames_per_step": total,
+              "parallelism": "single GPU"}
+    return base_line(args, "decoded info bits/s (QC-GLDPC)", best["info_bits_per_s"], "info bits/s",
+                     best["ms_per_step"], "f64", config, roof, cpu,
+                     forms={k: {kk: vv for kk, vv in v.items() if kk != "work"} for k, v in forms.items()})
+
+
+# --------------------------------------------------------------------------------------------
 # serve: open-loop Poisson arrivals through continuous batching
 # --------------------------------------------------------------------------------------------
 def bench_serve(args, sg, np, torch, synth):
@@ -580,7 +660,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="product", choices=["product", "mixed", "component", "serve"])
+    ap.add_argument("--workload", default="product", choices=["product", "mixed", "component", "serve", "gldpc"])
     ap.add_argument("--frames", type=int, default=None, help="frames per Eb/N0 (product) or in total (mixed)")
     ap.add_argument("--words", type=int, default=1 << 20, help="component words")
     ap.add_argument("--requests", type=int, default=100000, help="serving requests")
@@ -609,7 +689,7 @@ def main() -> int:
     if args.frames is None:
         args.frames = 10000
     if args.cpu_frames is None:
-        args.cpu_frames = {"product": 10000, "mixed": 4000}.get(args.workload, 0)
+        args.cpu_frames = {"product": 10000, "mixed": 4000, "gldpc": 3000}.get(args.workload, 0)
 
     import numpy as np
     import torch
@@ -617,7 +697,8 @@ def main() -> int:
     import paper_2310_10737_amd as sg
     import synth
 
-    fn = dict(product=bench_product, mixed=bench_mixed, component=bench_component, serve=bench_serve)[args.workload]
+    fn = dict(product=bench_product, mixed=bench_mixed, component=bench_component, serve=bench_serve,
+              gldpc=bench_gldpc)[args.workload]
     line = fn(args, sg, np, torch, synth)
     print(json.dumps(line), flush=True)
     return 0

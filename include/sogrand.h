@@ -157,6 +157,29 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
                            uint64_t *sum_max_queries, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* QC-GLDPC codes (section "Performance evaluation", GLDPC decoding)        */
+/* ------------------------------------------------------------------------ */
+/* Decodes nframes frames of the (n^2, n^2 - 2n(n-k)) quasi-cyclic GLDPC code
+   whose adjacency matrix has the block rows [I(0) ... I(0)] and
+   [I(0) I(1) ... I(n-1)], I(i) the n x n identity rotated right by i positions,
+   with `code` at every check node.  Variable node j*n + c is column c of block
+   j; check node r of the first block row takes its bit j from variable node
+   j*n + r, check node r of the second from j*n + (r + j) mod n.  llr_ch: DEVICE
+   [nframes][n*n] channel LLRs by variable node (precision per params).
+   Decoding is the block turbo loop of sogrand_decode_product with the two
+   block rows in place of rows and columns: half-iteration h decodes every
+   check node of the first (h odd) or second (h even) block row on L_Ch + L_A,
+   each variable node taking L_A = alpha * L_E from its check node in the other
+   block row; after each half the hard decision of L_APP is tested (every check
+   node of both block rows a codeword).  The paper's GLDPC runs use alpha = 0.6,
+   max_iter = 20 and list_bler_stop = 1e-5.  Outputs, by variable node, and
+   errors as for sogrand_decode_product. */
+int sogrand_decode_gldpc(const sogrand_code_t *code, const sogrand_params_t *params,
+                         size_t nframes, const void *llr_ch, uint8_t *hard, void *llr_app,
+                         uint8_t *success, uint16_t *half_iters, uint64_t *sum_queries,
+                         uint64_t *sum_max_queries, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Batched product decoding: mixed codes, one persistent launch             */
 /* ------------------------------------------------------------------------ */
 /* Launch shape of the persistent kernel.  Each workgroup (waves_per_group

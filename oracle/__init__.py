@@ -1,9 +1,10 @@
 """CPU oracle for SOGRAND decoding -- TEST INFRASTRUCTURE ONLY.
 
 The oracle (``sogrand_oracle.c``) is a plain sequential C implementation of
-soft-output GRAND list decoding and of block-turbo product decoding, written
-from the paper's definitions (arXiv 2310.10737: Corollary 1, eq. (LLRi), the
-block turbo decoding steps).  Only ``tests/``, the package smoke check and the
+soft-output GRAND list decoding and of block-turbo decoding of product codes
+and QC-GLDPC codes, written from the paper's definitions (arXiv 2310.10737:
+Corollary 1, eq. (LLRi), the block turbo decoding steps, the QC-GLDPC adjacency
+matrix of the performance evaluation).  Only ``tests/``, the package smoke check and the
 benchmark's ``cpu_baseline`` leg may import it.  It shares no code with the GPU
 library and never imports it.
 
@@ -47,10 +48,13 @@ def lib():
         L.oracle_decode_component.restype = ctypes.c_int
         L.oracle_decode_component.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_long, P,
                                               ctypes.c_int, ctypes.c_long, ctypes.c_double] + [P] * 10
-        L.oracle_decode_product.restype = ctypes.c_int
-        L.oracle_decode_product.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_long, P,
-                                            ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                                            ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int]
+        for fn in (L.oracle_decode_product, L.oracle_decode_gldpc):
+            fn.restype = ctypes.c_int
+            fn.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_long, P,
+                           ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                           ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int]
+        L.oracle_vnode.restype = ctypes.c_int
+        L.oracle_vnode.argtypes = [ctypes.c_int] * 5
         _lib = L
     return _lib
 
@@ -107,10 +111,8 @@ def decode_component(code, llr, list_max: int = 4, qcap: int = 1000, want_z: boo
     return out
 
 
-def decode_product(code, llr_ch, list_max: int = 4, qcap: int = 1000, max_iter: int = 4,
-                   alpha: float = 0.5, early_stop: bool = True, store_f32: bool = False,
-                   want_app: bool = False, nthreads: int = 1, pstop: float = 0.0):
-    """Block-turbo decode of frames llr_ch (F, n, n) float64."""
+def _two_family(fn, name, code, llr_ch, list_max, qcap, max_iter, alpha, early_stop, store_f32, want_app,
+                nthreads, pstop):
     llr_ch = np.ascontiguousarray(llr_ch, dtype=np.float64)
     F, n, n2 = llr_ch.shape
     assert n == n2 == code.n
@@ -119,10 +121,35 @@ def decode_product(code, llr_ch, list_max: int = 4, qcap: int = 1000, max_iter: 
         success=np.zeros(F, np.uint8), half_iters=np.zeros(F, np.uint16),
         sum_queries=np.zeros(F, np.uint64), sum_max_queries=np.zeros(F, np.uint64),
     )
-    rc = lib().oracle_decode_product(
-        code.n, code.k, _p(_hcols(code)), F, _p(llr_ch), list_max, qcap, float(pstop), max_iter, alpha,
-        int(early_stop), int(store_f32), _p(out["hard"]), _p(out["llr_app"]), _p(out["success"]),
-        _p(out["half_iters"]), _p(out["sum_queries"]), _p(out["sum_max_queries"]), nthreads)
+    rc = fn(code.n, code.k, _p(_hcols(code)), F, _p(llr_ch), list_max, qcap, float(pstop), max_iter, alpha,
+            int(early_stop), int(store_f32), _p(out["hard"]), _p(out["llr_app"]), _p(out["success"]),
+            _p(out["half_iters"]), _p(out["sum_queries"]), _p(out["sum_max_queries"]), nthreads)
     if rc:
-        raise ValueError("oracle_decode_product rejected its arguments")
+        raise ValueError(f"{name} rejected its arguments")
     return out
+
+
+def decode_product(code, llr_ch, list_max: int = 4, qcap: int = 1000, max_iter: int = 4,
+                   alpha: float = 0.5, early_stop: bool = True, store_f32: bool = False,
+                   want_app: bool = False, nthreads: int = 1, pstop: float = 0.0):
+    """Block-turbo decode of product-code frames llr_ch (F, n, n) float64, row-major."""
+    return _two_family(lib().oracle_decode_product, "oracle_decode_product", code, llr_ch, list_max, qcap,
+                       max_iter, alpha, early_stop, store_f32, want_app, nthreads, pstop)
+
+
+def decode_gldpc(code, llr_ch, list_max: int = 4, qcap: int = 1000, max_iter: int = 20,
+                 alpha: float = 0.6, early_stop: bool = True, store_f32: bool = False,
+                 want_app: bool = False, nthreads: int = 1, pstop: float = 0.0):
+    """The same loop over QC-GLDPC frames llr_ch (F, n, n) float64: element [j, c] is variable
+    node j*n + c (column c of block j of the adjacency matrix)."""
+    return _two_family(lib().oracle_decode_gldpc, "oracle_decode_gldpc", code, llr_ch, list_max, qcap,
+                       max_iter, alpha, early_stop, store_f32, want_app, nthreads, pstop)
+
+
+def vnode(topo: int, n: int, fam: int, line: int, j: int) -> int:
+    """Variable node of bit j of component word `line` of family `fam` (topo 0: product code,
+    rows then columns; topo 1: QC-GLDPC, first then second block row)."""
+    v = lib().oracle_vnode(topo, n, fam, line, j)
+    if v < 0:
+        raise ValueError("oracle_vnode rejected its arguments")
+    return v

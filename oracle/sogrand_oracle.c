@@ -42,6 +42,17 @@
  *    decision of L_APP is checked after every half-iteration (all rows and
  *    columns must be codewords); otherwise L_A = alpha L_E.  max_iter counts
  *    full row+column iterations.
+ *  - QC-GLDPC codes (Sec. "Performance evaluation": the (n^2, n^2-2n(n-k))
+ *    code whose adjacency matrix has the block rows [I(0) ... I(0)] and
+ *    [I(0) I(1) ... I(n-1)], I(i) the n x n identity rotated right by i, so
+ *    row r of I(i) has its one in column (r+i) mod n).  Variable node j*n + c
+ *    is column c of block j; check node r of the first block row meets the
+ *    variable nodes j*n + r, check node r of the second j*n + (r+j) mod n, and
+ *    bit j of either component word is the one from block j.  The two block
+ *    rows take the places of rows and columns in the block turbo loop above
+ *    (first block row on odd h), each variable node taking its a-priori LLR
+ *    from the other block row's last extrinsic output; validity requires every
+ *    check node of both block rows.
  */
 #include <math.h>
 #include <pthread.h>
@@ -425,11 +436,12 @@ int oracle_decode_component(int n, int k, const uint64_t *hcols, long nwords, co
 }
 
 /* ------------------------------------------------------------------------ */
-/* product code, block turbo decoding                                       */
+/* product codes and QC-GLDPC codes, block turbo decoding                 */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     const ocode *c;
     const oorders *os;
+    int topo;    /* 0: product code, 1: QC-GLDPC */
     long nframes;
     const double *llr_ch;
     int list_max, max_iter, early_stop, store_f32;
@@ -450,6 +462,31 @@ static int line_is_codeword(const ocode *c, const uint8_t *bits, long stride) {
     return s == 0;
 }
 
+/* Variable node (index into the frame) of bit j of component word `line` of
+   family `fam` (0: rows / first block row, 1: columns / second block row). */
+static long vnode(int topo, int n, int fam, int line, int j) {
+    if (topo == 0) return fam == 0 ? (long)line * n + j : (long)j * n + line;
+    return fam == 0 ? (long)j * n + line : (long)j * n + (line + j) % n;
+}
+
+int oracle_vnode(int topo, int n, int fam, int line, int j) {
+    if (topo < 0 || topo > 1 || n < 1 || fam < 0 || fam > 1 || line < 0 || line >= n || j < 0 || j >= n)
+        return -1;
+    return (int)vnode(topo, n, fam, line, j);
+}
+
+/* every component word of both families of the hard decision C is a codeword */
+static int frame_is_codeword(const ocode *c, int topo, const uint8_t *C) {
+    const int n = c->n;
+    uint8_t w[ONMAX];
+    for (int fam = 0; fam < 2; fam++)
+        for (int line = 0; line < n; line++) {
+            for (int j = 0; j < n; j++) w[j] = C[vnode(topo, n, fam, line, j)];
+            if (!line_is_codeword(c, w, 1)) return 0;
+        }
+    return 1;
+}
+
 static void decode_frame(const oprod_job *J, long f, oscratch *sc, double *LA, double *LE,
                          double *LAPP, uint8_t *C, double *lam, double *app, double *ext,
                          uint8_t *hd, uint32_t *fq, double *pf) {
@@ -460,12 +497,11 @@ static void decode_frame(const oprod_job *J, long f, oscratch *sc, double *LA, d
     uint64_t sq = 0, smq = 0;
     int ok = 0, h;
     for (h = 1; h <= 2 * J->max_iter; h++) {
-        const int rows = (h & 1);
+        const int fam = (h & 1) ? 0 : 1;   /* rows / first block row on odd h */
         uint32_t qmax = 0;
         for (int line = 0; line < n; line++) {
-            /* element (line, j) for rows, (j, line) for columns */
             for (int j = 0; j < n; j++) {
-                int idx = rows ? line * n + j : j * n + line;
+                long idx = vnode(J->topo, n, fam, line, j);
                 lam[j] = Lch[idx] + LA[idx];
             }
             uint32_t q; int32_t nf; double pnf;
@@ -474,18 +510,14 @@ static void decode_frame(const oprod_job *J, long f, oscratch *sc, double *LA, d
             sq += q;
             if (q > qmax) qmax = q;
             for (int j = 0; j < n; j++) {
-                int idx = rows ? line * n + j : j * n + line;
+                long idx = vnode(J->topo, n, fam, line, j);
                 LAPP[idx] = app[j];
                 LE[idx] = ext[j];
                 C[idx] = hd[j];
             }
         }
         smq += qmax;
-        int valid = 1;
-        for (int i = 0; i < n && valid; i++) {
-            if (!line_is_codeword(c, C + i * n, 1)) valid = 0;
-            else if (!line_is_codeword(c, C + i, n)) valid = 0;
-        }
+        const int valid = frame_is_codeword(c, J->topo, C);
         ok = valid;
         if ((valid && J->early_stop) || h == 2 * J->max_iter) break;
         for (int i = 0; i < n * n; i++) {
@@ -530,17 +562,18 @@ static void *prod_worker(void *arg) {
 /* Product decode of nframes frames [nframes][n][n] of channel LLRs.
    store_f32 != 0 stores the exchanged a-priori LLRs in binary32 (the caller
    passes binary32-representable channel LLRs).  llr_app may be NULL. */
-int oracle_decode_product(int n, int k, const uint64_t *hcols, long nframes, const double *llr_ch,
-                          int list_max, long qcap, double pstop, int max_iter, double alpha, int early_stop,
-                          int store_f32, uint8_t *hard, double *llr_app, uint8_t *success,
-                          uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq, int nthreads) {
+static int decode_two_families(int topo, int n, int k, const uint64_t *hcols, long nframes,
+                               const double *llr_ch, int list_max, long qcap, double pstop, int max_iter,
+                               double alpha, int early_stop, int store_f32, uint8_t *hard, double *llr_app,
+                               uint8_t *success, uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq,
+                               int nthreads) {
     ocode c;
     if (code_init(&c, n, k, hcols)) return -1;
     if (list_max < 1 || qcap < 1 || max_iter < 1 || !(pstop >= 0.0 && pstop <= 1.0)) return -1;
     oorders os;
     orders_build(&os, &c, qcap);
-    oprod_job J = { &c, &os, nframes, llr_ch, list_max, max_iter, early_stop, store_f32, qcap, pstop, alpha,
-                    hard, llr_app, success, half_iters, sum_q, sum_maxq, 0 };
+    oprod_job J = { &c, &os, topo, nframes, llr_ch, list_max, max_iter, early_stop, store_f32, qcap, pstop,
+                    alpha, hard, llr_app, success, half_iters, sum_q, sum_maxq, 0 };
     if (nthreads < 1) nthreads = 1;
     if (nthreads == 1) {
         prod_worker(&J);
@@ -552,4 +585,25 @@ int oracle_decode_product(int n, int k, const uint64_t *hcols, long nframes, con
     }
     orders_free(&os);
     return 0;
+}
+
+/* Block turbo decoding of (n^2, k^2) product-code frames, row-major [F][n][n]. */
+int oracle_decode_product(int n, int k, const uint64_t *hcols, long nframes, const double *llr_ch,
+                          int list_max, long qcap, double pstop, int max_iter, double alpha, int early_stop,
+                          int store_f32, uint8_t *hard, double *llr_app, uint8_t *success,
+                          uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq, int nthreads) {
+    return decode_two_families(0, n, k, hcols, nframes, llr_ch, list_max, qcap, pstop, max_iter, alpha,
+                               early_stop, store_f32, hard, llr_app, success, half_iters, sum_q, sum_maxq,
+                               nthreads);
+}
+
+/* The same loop over (n^2, n^2 - 2n(n-k)) QC-GLDPC frames, variable node j*n + c
+   (column c of block j) at index j*n + c of [F][n*n]. */
+int oracle_decode_gldpc(int n, int k, const uint64_t *hcols, long nframes, const double *llr_ch,
+                        int list_max, long qcap, double pstop, int max_iter, double alpha, int early_stop,
+                        int store_f32, uint8_t *hard, double *llr_app, uint8_t *success,
+                        uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq, int nthreads) {
+    return decode_two_families(1, n, k, hcols, nframes, llr_ch, list_max, qcap, pstop, max_iter, alpha,
+                               early_stop, store_f32, hard, llr_app, success, half_iters, sum_q, sum_maxq,
+                               nthreads);
 }

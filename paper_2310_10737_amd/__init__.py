@@ -12,7 +12,8 @@ import os
 
 __all__ = [
     "SograndError", "Code", "params", "sched", "lib", "library_path", "profile_begin", "profile_end",
-    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_batched", "pack_frames",
+    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_gldpc", "sogrand_decode_batched",
+    "pack_frames",
     "Server", "sogrand_clock_ns", "SOGRAND_F64", "SOGRAND_F32",
 ]
 
@@ -26,7 +27,7 @@ _lib = None
 EXPORTS = [
     "sogrand_last_error", "sogrand_version", "sogrand_params_default",
     "sogrand_code_create", "sogrand_code_create_ebch", "sogrand_code_info", "sogrand_code_destroy",
-    "sogrand_decode_component", "sogrand_decode_product",
+    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_gldpc",
     "sogrand_sched_default", "sogrand_decode_batched",
     "sogrand_clock_ns", "sogrand_serve_create", "sogrand_serve_submit", "sogrand_serve_poll",
     "sogrand_serve_stats", "sogrand_serve_replay", "sogrand_serve_destroy",
@@ -127,6 +128,7 @@ def lib():
     L.sogrand_code_destroy.restype = None
     L.sogrand_decode_component.argtypes = [P, P, SZ] + [P] * 11
     L.sogrand_decode_product.argtypes = [P, P, SZ] + [P] * 8
+    L.sogrand_decode_gldpc.argtypes = [P, P, SZ] + [P] * 8
     L.sogrand_sched_default.argtypes = [P]
     L.sogrand_sched_default.restype = None
     L.sogrand_decode_batched.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 9
@@ -271,7 +273,21 @@ def sogrand_decode_component(code: Code, llr_in, list_max=4, query_cap=1000, fou
 
 def sogrand_decode_product(code: Code, llr_ch, list_max=4, query_cap=1000, max_iter=4, alpha=0.5,
                            early_stop=True, want_app=False, outputs=None, stream=None, list_bler_stop=0.0):
-    """Block-turbo decode of frames llr_ch (F, n, n); returns a dict of tensors."""
+    """Block-turbo decode of product-code frames llr_ch (F, n, n); returns a dict of tensors."""
+    return _decode_frames(lib().sogrand_decode_product, code, llr_ch, list_max, query_cap, max_iter, alpha,
+                          early_stop, want_app, outputs, stream, list_bler_stop)
+
+
+def sogrand_decode_gldpc(code: Code, llr_ch, list_max=4, query_cap=1000, max_iter=20, alpha=0.6,
+                         early_stop=True, want_app=False, outputs=None, stream=None, list_bler_stop=0.0):
+    """The same loop over QC-GLDPC frames llr_ch (F, n, n), element [j, c] being variable node
+    j*n + c (column c of block j of the adjacency matrix); returns a dict of tensors."""
+    return _decode_frames(lib().sogrand_decode_gldpc, code, llr_ch, list_max, query_cap, max_iter, alpha,
+                          early_stop, want_app, outputs, stream, list_bler_stop)
+
+
+def _decode_frames(fn, code, llr_ch, list_max, query_cap, max_iter, alpha, early_stop, want_app, outputs,
+                   stream, list_bler_stop):
     import torch
     if not llr_ch.is_cuda or not llr_ch.is_contiguous() or llr_ch.dim() != 3 or \
             llr_ch.shape[1] != code.n or llr_ch.shape[2] != code.n:
@@ -290,7 +306,7 @@ def sogrand_decode_product(code: Code, llr_ch, list_max=4, query_cap=1000, max_i
         out.update(outputs)
     p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
                early_stop=early_stop, precision=_precision_of(llr_ch), list_bler_stop=list_bler_stop)
-    _check(lib().sogrand_decode_product(
+    _check(fn(
         code.handle, ctypes.byref(p), F, _ptr(llr_ch), _ptr(out["hard"]), _ptr(out["llr_app"]),
         _ptr(out["success"]), _ptr(out["half_iters"]), _ptr(out["sum_queries"]),
         _ptr(out["sum_max_queries"]), _stream(stream)))

@@ -95,13 +95,17 @@ struct ProductArgs {
     size_t nframes;
     const void *llr_ch;     // [F][n][n]
     // Work buffers, each [F][n][n], laid out so that every pass reads its lines
-    // contiguously: L_Ch transposed (written by the first row pass), the a-priori
-    // LLRs for the row passes (row-major, written by column passes) and for the
-    // column passes (transposed, written by row passes).
+    // contiguously ("line-major": element i of line l at l * n + i): L_Ch in the
+    // second family's line order (written by the first pass), the a-priori LLRs for
+    // the first family's passes (written by the second family's passes) and for the
+    // second family's passes (written by the first family's).  For a product code the
+    // first family is the rows, so its line-major order is the frame's own.
     void *ch_t;
     void *la_rm;
     void *la_cm;
+    void *ch_a;             // QC-GLDPC only: L_Ch in the first family's line order
     int first;              // this launch is the first row pass (no a-priori LLRs yet)
+    int topo;               // kProduct or kGldpc
     void *llr_app;          // [F][n][n] or NULL
     uint8_t *hard;          // [F][n][n]
     uint64_t *masks;        // [F][n][2] hard decision of each line of the last pass
@@ -129,9 +133,33 @@ __global__ __launch_bounds__(kBlock) void k_product_init(ProductArgs a) {
     }
 }
 
-// One wave per line: ROWS decodes row `line` of L_Ch + L_A, otherwise column `line`.
-template <typename T, int NS, bool ROWS, int WPB, bool STOP>
+// The two families of component words.  Product code: the rows (first family) and
+// the columns.  QC-GLDPC (performance-evaluation section: adjacency matrix with block
+// rows [I(0) ... I(0)] and [I(0) I(1) ... I(n-1)], I(i) the identity rotated right by
+// i): variable node j*n + c is column c of block j; word `line` of the first block
+// row takes its bit j from variable node j*n + line, of the second from
+// j*n + (line + j) mod n.
+constexpr int kProduct = 0, kGldpc = 1;
+
+template <int TOPO, bool FIRST_FAMILY>
+struct Lines {
+    // frame position (variable node) of bit i of word `line`
+    static __device__ __forceinline__ uint32_t vn(uint32_t line, uint32_t i, uint32_t n) {
+        if constexpr (TOPO == kProduct) return FIRST_FAMILY ? line * n + i : i * n + line;
+        else return FIRST_FAMILY ? i * n + line : i * n + (line + i) % n;
+    }
+    // line-major position of the same variable node among the other family's words
+    static __device__ __forceinline__ uint32_t cross(uint32_t line, uint32_t i, uint32_t n) {
+        if constexpr (TOPO == kProduct) return i * n + line;
+        else return (FIRST_FAMILY ? (line + n - i) % n : (line + i) % n) * n + i;
+    }
+};
+
+// One wave per word: ROWS decodes word `line` of the first family (the rows of a
+// product code) of L_Ch + L_A, otherwise of the second.
+template <typename T, int NS, bool ROWS, int WPB, bool STOP, int TOPO>
 __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
+    using LN = Lines<TOPO, ROWS>;
     constexpr int NB = Lanes<NS>::NB;
     __shared__ WaveLds lds[WPB];
     const int lane = threadIdx.x & (kWave - 1);
@@ -141,27 +169,35 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
     // the host keeps nframes * n below 2^31
     const uint32_t wid = (uint32_t)logical_block(a.xcd) * WPB + (uint32_t)wave;
     const uint32_t f = wid / n;
-    const int line = (int)(wid - f * n);
+    const uint32_t line = wid - f * n;
     if (f >= a.nframes) return;
     if (a.done[f]) return;
     const size_t fo = (size_t)f * n * n;   // element offset of frame f
-    // inputs are read along the line (element i of the line at line * n + i); the
-    // a-priori LLRs for the other direction are written across (at i * n + line)
-    const T *ch = static_cast<const T *>(ROWS ? a.llr_ch : a.ch_t) + fo;
+    // inputs are read along the word (line-major); the a-priori LLRs for the other
+    // family are written across.  A product code's rows read L_Ch from the frame
+    // itself; a QC-GLDPC's first pass gathers it and keeps both line-major copies.
+    const bool first = ROWS && a.first;
+    const T *ch;
+    if constexpr (TOPO == kProduct) ch = static_cast<const T *>(ROWS ? a.llr_ch : a.ch_t) + fo;
+    else ch = static_cast<const T *>(ROWS ? a.ch_a : a.ch_t) + fo;
     const T *la_in = static_cast<const T *>(ROWS ? a.la_rm : a.la_cm) + fo;
     T *la_out = static_cast<T *>(ROWS ? a.la_cm : a.la_rm) + fo;
-    const bool first = ROWS && a.first;
     double lam[NB];
-    int pos[NB];   // row-major position of the lane's elements in the frame
+    uint32_t pos[NB];   // frame position of the lane's bits
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const int i = lane + kWave * b;
-        pos[b] = ROWS ? line * n + i : i * n + line;
+        const uint32_t i = (uint32_t)(lane + kWave * b);
+        pos[b] = LN::vn(line, i, n);
         lam[b] = 0.0;
         if (i < n) {
-            const T c = ch[line * n + i];
+            T c;
+            if (TOPO == kGldpc && first) c = static_cast<const T *>(a.llr_ch)[fo + pos[b]];
+            else c = ch[line * n + i];
             lam[b] = first ? (double)c : (double)c + (double)la_in[line * n + i];
-            if (first) static_cast<T *>(a.ch_t)[fo + (size_t)i * n + line] = c;
+            if (first) {
+                static_cast<T *>(a.ch_t)[fo + LN::cross(line, i, n)] = c;
+                if (TOPO == kGldpc) static_cast<T *>(a.ch_a)[fo + line * n + i] = c;
+            }
         }
     }
     double lapp[NB];
@@ -171,13 +207,13 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
     uint64_t hm[2] = {0ull, 0ull};
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const int i = lane + kWave * b;
+        const uint32_t i = (uint32_t)(lane + kWave * b);
         const bool v = i < n;
         const bool neg = v && lapp[b] < 0.0;
         hm[b] = __ballot(neg);
         if (!v) continue;
         const double le = lapp[b] - lam[b];
-        la_out[i * n + line] = (T)(a.alpha * le);
+        la_out[LN::cross(line, i, n)] = (T)(a.alpha * le);
         if (a.llr_app) static_cast<T *>(a.llr_app)[fo + pos[b]] = (T)lapp[b];
         a.hard[fo + pos[b]] = neg;
     }
@@ -189,8 +225,8 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
     }
 }
 
-// One wave per frame after half-iteration h: every line of the last pass and every
-// cross line must have a zero syndrome.
+// One wave per frame after half-iteration h: every word of the last pass and every
+// word of the other family must have a zero syndrome.
 __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, int last) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -210,11 +246,15 @@ __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, 
             const uint64_t bit = i < 64 ? (m0 >> i) & 1ull : (m1 >> (i - 64)) & 1ull;
             if (bit) s ^= a.code.hcol[i];
         }
-        // x as a cross line: bit x of every line
+        // x as a word of the other family: its bit l is bit `bit` of the last pass's
+        // word `src` (product: bit x of word l; QC-GLDPC: bit l of word (x + l) mod n
+        // after a first-family pass, (x - l) mod n after a second-family pass)
         uint32_t t = 0;
         for (int l = 0; l < n; l++) {
-            const uint64_t w = x < 64 ? mk[l * 2] : mk[l * 2 + 1];
-            if ((w >> (x & 63)) & 1ull) t ^= a.code.hcol[l];
+            const int src = a.topo == kProduct ? l : ((h & 1) ? (x + l) % n : (x - l + n) % n);
+            const int bit = a.topo == kProduct ? x : l;
+            const uint64_t w = bit < 64 ? mk[src * 2] : mk[src * 2 + 1];
+            if ((w >> (bit & 63)) & 1ull) t ^= a.code.hcol[l];
         }
         bad |= (s != 0u) || (t != 0u);
     }
@@ -275,18 +315,23 @@ static void launch_component(const ComponentArgs &a, int ns, dim3 g, hipStream_t
     else launch_component_s<T, false>(a, ns, g, st);
 }
 
-template <typename T, bool ROWS, bool STOP>
-static void launch_pass_s(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
+template <typename T, bool ROWS, bool STOP, int TOPO>
+static void launch_pass_t(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
     constexpr int W = kWavesPerBlock;
-    if (ns == 32) hipLaunchKernelGGL((k_product_pass<T, 32, ROWS, W, STOP>), g, dim3(kWave * W), 0, st, a);
-    else if (ns == 64) hipLaunchKernelGGL((k_product_pass<T, 64, ROWS, W, STOP>), g, dim3(kWave * W), 0, st, a);
-    else hipLaunchKernelGGL((k_product_pass<T, 128, ROWS, W, STOP>), g, dim3(kWave * W), 0, st, a);
+    if (ns == 32) hipLaunchKernelGGL((k_product_pass<T, 32, ROWS, W, STOP, TOPO>), g, dim3(kWave * W), 0, st, a);
+    else if (ns == 64) hipLaunchKernelGGL((k_product_pass<T, 64, ROWS, W, STOP, TOPO>), g, dim3(kWave * W), 0, st, a);
+    else hipLaunchKernelGGL((k_product_pass<T, 128, ROWS, W, STOP, TOPO>), g, dim3(kWave * W), 0, st, a);
 }
 
 template <typename T, bool ROWS>
 static void launch_pass(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
-    if (a.pstop > 0.0) launch_pass_s<T, ROWS, true>(a, ns, g, st);
-    else launch_pass_s<T, ROWS, false>(a, ns, g, st);
+    if (a.topo == kProduct) {
+        if (a.pstop > 0.0) launch_pass_t<T, ROWS, true, kProduct>(a, ns, g, st);
+        else launch_pass_t<T, ROWS, false, kProduct>(a, ns, g, st);
+    } else {
+        if (a.pstop > 0.0) launch_pass_t<T, ROWS, true, kGldpc>(a, ns, g, st);
+        else launch_pass_t<T, ROWS, false, kGldpc>(a, ns, g, st);
+    }
 }
 
 }  // namespace sg
@@ -334,11 +379,14 @@ int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t 
     return SOGRAND_OK;
 }
 
-int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
-                           const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
-                           uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
-                           void *stream) {
-    using namespace sg;
+}  // extern "C"
+
+namespace sg {
+
+// The block turbo loop over either family layout (see Lines).
+static int decode_frames(int topo, const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
+                         const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
+                         uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries, void *stream) {
     SG_TRY(check_params(params));
     if (!code) return fail(SOGRAND_EINVAL, "code is NULL");
     if (nframes == 0) return SOGRAND_OK;
@@ -354,10 +402,10 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
     SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &a.code));
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t esz = params->precision == SOGRAND_F64 ? sizeof(double) : sizeof(float);
-    // work buffer layout: ch_t | la_rm | la_cm | masks | done | halfmax | sumq | summax | half_iters
+    // work buffer layout: ch_t | la_rm | la_cm | [ch_a] | masks | done | halfmax | sumq | summax | half_iters
     const size_t plane = (nframes * n * n * esz + 255) & ~(size_t)255;
-    const size_t off_ct = 0, off_lr = plane, off_lc = 2 * plane;
-    const size_t off_mk = 3 * plane;
+    const size_t off_ct = 0, off_lr = plane, off_lc = 2 * plane, off_ca = 3 * plane;
+    const size_t off_mk = (topo == kGldpc ? 4 : 3) * plane;
     const size_t off_dn = (off_mk + nframes * n * 2 * sizeof(uint64_t) + 255) & ~(size_t)255;
     const size_t off_hm = (off_dn + nframes * sizeof(uint32_t) + 255) & ~(size_t)255;
     const size_t off_sq = (off_hm + nframes * sizeof(uint32_t) + 255) & ~(size_t)255;
@@ -376,7 +424,9 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
     a.ch_t = ws + off_ct;
     a.la_rm = ws + off_lr;
     a.la_cm = ws + off_lc;
+    a.ch_a = topo == kGldpc ? ws + off_ca : nullptr;
     a.first = 0;
+    a.topo = topo;
     a.llr_app = llr_app;
     a.hard = hard;
     a.masks = reinterpret_cast<uint64_t *>(ws + off_mk);
@@ -419,6 +469,26 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
     }
     (void)hipFreeAsync(ws, st);
     return rc;
+}
+
+}  // namespace sg
+
+extern "C" {
+
+int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
+                           const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
+                           uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
+                           void *stream) {
+    return sg::decode_frames(sg::kProduct, code, params, nframes, llr_ch, hard, llr_app, success, half_iters,
+                             sum_queries, sum_max_queries, stream);
+}
+
+int sogrand_decode_gldpc(const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
+                         const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
+                         uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
+                         void *stream) {
+    return sg::decode_frames(sg::kGldpc, code, params, nframes, llr_ch, hard, llr_app, success, half_iters,
+                             sum_queries, sum_max_queries, stream);
 }
 
 }  // extern "C"

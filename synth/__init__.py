@@ -26,6 +26,19 @@ whose bit r is H[r][j]; its rows are alpha^{(2i-1)j} written in the field's
 polynomial basis, reduced to full rank, plus the all-ones row.  The decoder's
 membership test H c = 0 does not depend on which basis of the dual code is used.
 
+QC-GLDPC codes
+--------------
+The (n^2, n^2 - 2n(n-k)) quasi-cyclic GLDPC codes of the performance evaluation
+have the adjacency matrix with block rows [I(0) ... I(0)] and [I(0) I(1) ...
+I(n-1)], I(i) the n x n identity rotated right by i positions (row r of I(i) has
+its one in column (r + i) mod n).  Each of its 2n rows is a component code whose
+bit j sits in block j.  `gldpc` builds the code's parity-check matrix from that
+description and a systematic generator of its null space by Gaussian
+elimination; frames are [n][n] arrays whose element [j, c] is variable node
+j*n + c.  The design dimension n^2 - 2n(n-k) counts every check as independent;
+the null space can be larger (for the [32,26] eBCH component, 646 rather than
+640), and its true dimension is used.
+
 Channel
 -------
 BPSK maps bit 0 to +1 and bit 1 to -1.  With overall rate R and Eb/N0 in dB,
@@ -56,7 +69,7 @@ import numpy as np
 __all__ = [
     "Code", "ebch", "code_from_generator", "encode", "encode_product",
     "splitmix_stream", "info_bits", "gaussians", "sigma2", "bpsk_awgn_llr",
-    "product_frames", "component_words", "PRIM_POLY",
+    "product_frames", "component_words", "PRIM_POLY", "Gldpc", "gldpc", "gldpc_frames",
 ]
 
 MASK64 = (1 << 64) - 1
@@ -309,6 +322,105 @@ def encode_product(code: Code, info: np.ndarray) -> np.ndarray:
     rows = _gf2_matmul(np.asarray(info), code.G)                 # (F, k, n)
     cols = _gf2_matmul(np.swapaxes(rows, -1, -2), code.G)        # (F, n, n): [col j][row i]
     return np.ascontiguousarray(np.swapaxes(cols, -1, -2))
+
+
+# ----------------------------------------------------------------------------
+# QC-GLDPC codes
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass(frozen=True)
+class Gldpc:
+    """A QC-GLDPC code over a component code: G (dim, n*n) systematic on info_pos."""
+    component: Code
+    dim: int
+    G: np.ndarray
+    info_pos: tuple
+
+    @property
+    def n(self) -> int:
+        return self.component.n
+
+
+def _gldpc_checks(code: Code) -> np.ndarray:
+    """(2n(n-k), n*n) parity-check matrix of the QC-GLDPC code over `code`."""
+    n, r = code.n, code.r
+    Hc = code.H()
+    rows = []
+    for block_row in range(2):
+        for cn in range(n):
+            # bit j of check node cn lies in block j, at column cn (first block row)
+            # or at column (cn + j) mod n (second block row: the identity rotated by j)
+            cols = [j * n + ((cn + (j if block_row else 0)) % n) for j in range(n)]
+            for q in range(r):
+                row = np.zeros(n * n, dtype=np.uint8)
+                row[cols] = Hc[q]
+                rows.append(row)
+    return np.array(rows, dtype=np.uint8)
+
+
+_GLDPC_CACHE: dict = {}
+
+
+def gldpc(code: Code) -> Gldpc:
+    """QC-GLDPC code with `code` as every component, and a systematic generator."""
+    key = (code.name, code.n, code.k)
+    if key in _GLDPC_CACHE:
+        return _GLDPC_CACHE[key]
+    H = _gldpc_checks(code)
+    m, N = H.shape
+    A = H.copy()
+    piv = []
+    row = 0
+    for col in range(N):
+        nz = np.nonzero(A[row:, col])[0]
+        if nz.size == 0:
+            continue
+        p = row + nz[0]
+        if p != row:
+            A[[row, p]] = A[[p, row]]
+        hit = np.nonzero(A[:, col])[0]
+        hit = hit[hit != row]
+        A[hit] ^= A[row]
+        piv.append(col)
+        row += 1
+        if row == m:
+            break
+    free = [c for c in range(N) if c not in set(piv)]
+    # one generator row per free column: 1 there, and the pivot columns that cancel it
+    G = np.zeros((len(free), N), dtype=np.uint8)
+    for i, f in enumerate(free):
+        G[i, f] = 1
+        for r_, pc in enumerate(piv):
+            G[i, pc] = A[r_, f]
+    if np.any(_gf2_matmul(G, H.T)):
+        raise AssertionError("QC-GLDPC generator: G H^T != 0")
+    g = Gldpc(code, len(free), G, tuple(free))
+    _GLDPC_CACHE[key] = g
+    return g
+
+
+def gldpc_frames(g: Gldpc, ebn0_db, seed: int, frame_ids, batch: int = 4096):
+    """QC-GLDPC frames over BPSK-AWGN at rate dim/n^2.  Returns (llr (F,n,n) float64,
+    codewords (F,n,n) uint8, info (F,dim) uint8); element [j, c] is variable node j*n + c."""
+    frame_ids = np.asarray(frame_ids, dtype=np.uint64)
+    F = frame_ids.shape[0]
+    n = g.n
+    rate = g.dim / (n * n)
+    eb = np.broadcast_to(np.asarray(ebn0_db, dtype=np.float64), (F,))
+    llr = np.empty((F, n, n), dtype=np.float64)
+    cw = np.empty((F, n, n), dtype=np.uint8)
+    info = np.empty((F, g.dim), dtype=np.uint8)
+    for s in range(0, F, batch):
+        ids = frame_ids[s:s + batch]
+        u = info_bits(seed, ids, g.dim)
+        c = _gf2_matmul(u, g.G).reshape(-1, n, n)
+        z = gaussians(seed, ids, n * n).reshape(-1, n, n)
+        s2 = 1.0 / (2.0 * rate * 10.0 ** (eb[s:s + batch] / 10.0))
+        x = 1.0 - 2.0 * c.astype(np.float64)
+        r = x + np.sqrt(s2)[:, None, None] * z
+        llr[s:s + batch] = 2.0 * r / s2[:, None, None]
+        cw[s:s + batch] = c
+        info[s:s + batch] = u
+    return llr, cw, info
 
 
 # ----------------------------------------------------------------------------
