@@ -22,6 +22,10 @@ Other workloads, each printing its own line:
              Eb/N0 = 2.0, 2.25 and 2.5 dB, 10^4 frames each (seeds 11-13),
              L = 4, cap 10^4, alpha = 0.6, 20 iterations, list-BLER stop 10^-5
              (the paper's GLDPC settings); plain FP64 and FP32 storage.
+  rician     [64,57]^2 over block Rician fading (N_c = 256, t = 8, K = 6) with
+             Gray QPSK and a random interleaver, Eb/N0 = 6, 8, 10 dB, 10^4
+             frames each (seeds 21-23), L = 4, cap 10^4, alpha = 0.5, 20
+             iterations, list-BLER stop 10^-5 (the paper's fading settings).
 
 Prints one JSON line.  `value` is decoded information bits per second of the
 fastest form whose BLER matches the plain binary64 form (product workload).
@@ -569,6 +573,93 @@ def bench_gldpc(args, sg, np, torch, synth):
 
 
 # --------------------------------------------------------------------------------------------
+# rician: [64,57]^2 over block Rician fading with QPSK (N_c = 256, t = 8, K = 6)
+# --------------------------------------------------------------------------------------------
+RICIAN_SNRS = ((6.0, 21), (8.0, 22), (10.0, 23))
+RICIAN_K, RICIAN_NC, RICIAN_ITERS, RICIAN_STOP = 6.0, 256, 20, 1e-5
+
+
+def bench_rician(args, sg, np, torch, synth):
+    dev = torch.device("cuda:0")
+    code = synth.ebch(N, K)
+    gcode = sg.Code.ebch(N, K)
+    F = args.frames
+    llr_parts, cw_parts = [], []
+    for snr, seed in RICIAN_SNRS:
+        llr, cw, _ = synth.rician_product_frames(code, snr, RICIAN_K, RICIAN_NC, seed, np.arange(F))
+        llr_parts.append(llr)
+        cw_parts.append(cw)
+    llr_all = np.concatenate(llr_parts)
+    cw_all = torch.from_numpy(np.concatenate(cw_parts)).to(dev)
+    x64 = torch.from_numpy(llr_all).to(dev)
+    x32 = x64.float()
+    total = x64.shape[0]
+    info_bits_per_step = total * K * K
+    fcode = torch.zeros(total, dtype=torch.uint8, device=dev)
+    foff = torch.arange(total, dtype=torch.int64, device=dev) * (N * N)
+    forms = {}
+    for form in [f for f in args.forms.split(",") if f in ("plain_f64", "plain_f32", "batched_f32")]:
+        x = x64 if form.endswith("f64") else x32
+        out = dict(hard=torch.empty((total, N, N), dtype=torch.uint8, device=dev), llr_app=None,
+                   success=torch.empty(total, dtype=torch.uint8, device=dev),
+                   half_iters=torch.empty(total, dtype=torch.int16, device=dev),
+                   sum_queries=torch.empty(total, dtype=torch.int64, device=dev),
+                   sum_max_queries=torch.empty(total, dtype=torch.int64, device=dev))
+        if form.startswith("plain"):
+            step = (lambda x_, o_: lambda: sg.sogrand_decode_product(
+                gcode, x_, list_max=L, query_cap=QCAP, max_iter=RICIAN_ITERS, outputs=o_,
+                list_bler_stop=RICIAN_STOP))(x, out)
+        else:
+            out["hard"] = out["hard"].view(-1)
+            out["status"] = torch.zeros(1, dtype=torch.int32, device=dev)
+            step = (lambda x_, o_: lambda: sg.sogrand_decode_batched(
+                [gcode], fcode, foff, x_.view(-1), list_max=L, query_cap=QCAP, max_iter=RICIAN_ITERS,
+                outputs=o_, list_bler_stop=RICIAN_STOP))(x, out)
+        ms, kern, work = timed(step, args.steps, args.warmup, sg, count=not args.no_count)
+        if "status" in out and int(out["status"].item()) != 0:
+            raise SystemExit(f"{form}: batched kernel reported status {int(out['status'].item())}")
+        err = torch.any((out["hard"].view(total, N, N) != cw_all).view(total, -1), dim=1).cpu().numpy()
+        hi = out["half_iters"].double().cpu().numpy()
+        sq = out["sum_queries"].double().cpu().numpy()
+        smq = out["sum_max_queries"].double().cpu().numpy()
+        per_snr = {}
+        for j, (snr, _) in enumerate(RICIAN_SNRS):
+            sl = slice(j * F, (j + 1) * F)
+            k_err = int(err[sl].sum())
+            per_snr[str(snr)] = dict(
+                bler=k_err / F, bler_ci95=wilson(k_err, F), frames=F,
+                avg_iterations=float(hi[sl].mean() / 2), queries_per_bit=float(sq[sl].mean() / (N * N)),
+                parallel_queries_per_bit=float(smq[sl].mean() / (N * N)))
+        forms[form] = dict(ms_per_step=ms, info_bits_per_s=info_bits_per_step / (ms / 1e3), per_snr=per_snr,
+                           kernels=kern, work=work)
+    best_name = min(forms, key=lambda k: forms[k]["ms_per_step"])
+    best = forms[best_name]
+    if best_name.startswith("batched"):
+        roof = roofline("batched", "k_batched (persistent)", best["kernels"], best["work"], args.steps, N, L)
+    else:
+        roof = roofline("product_pass", "k_product_pass (row and column instantiations)", best["kernels"],
+                        best["work"], args.steps, N, L)
+    cpu = None
+    if not args.no_cpu and args.cpu_frames > 0:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        cf = min(args.cpu_frames, F)
+        sample = np.concatenate([llr_all[j * F:j * F + cf] for j in range(len(RICIAN_SNRS))])
+        t0 = time.perf_counter()
+        oracle.decode_product(code, sample, L, QCAP, RICIAN_ITERS, pstop=RICIAN_STOP, nthreads=threads)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=sample.shape[0] * K * K / dt, unit="info bits/s", cores=threads, kind="oracle",
+                   sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall")
+    config = {"workload": f"eBCH [64,57]^2 product code, block Rician fading (N_c 256, t 8, K 6) with Gray QPSK "
+                          f"and a random interleaver, Eb/N0 6/8/10 dB, {F} frames each, L=4, query cap 1e4, "
+                          "alpha 0.5, 20 iterations, list-BLER stop 1e-5",
+              "form": best_name, "frames_per_step": total, "parallelism": "single GPU"}
+    return base_line(args, "decoded info bits/s (block Rician fading)", best["info_bits_per_s"], "info bits/s",
+                     best["ms_per_step"], "f64", config, roof, cpu,
+                     forms={k: {kk: vv for kk, vv in v.items() if kk != "work"} for k, v in forms.items()})
+
+
+# --------------------------------------------------------------------------------------------
 # serve: open-loop Poisson arrivals through continuous batching
 # --------------------------------------------------------------------------------------------
 def bench_serve(args, sg, np, torch, synth):
@@ -660,7 +751,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="product", choices=["product", "mixed", "component", "serve", "gldpc"])
+    ap.add_argument("--workload", default="product", choices=["product", "mixed", "component", "serve", "gldpc", "rician"])
     ap.add_argument("--frames", type=int, default=None, help="frames per Eb/N0 (product) or in total (mixed)")
     ap.add_argument("--words", type=int, default=1 << 20, help="component words")
     ap.add_argument("--requests", type=int, default=100000, help="serving requests")
@@ -689,7 +780,7 @@ def main() -> int:
     if args.frames is None:
         args.frames = 10000
     if args.cpu_frames is None:
-        args.cpu_frames = {"product": 10000, "mixed": 4000, "gldpc": 3000}.get(args.workload, 0)
+        args.cpu_frames = {"product": 10000, "mixed": 4000, "gldpc": 3000, "rician": 3000}.get(args.workload, 0)
 
     import numpy as np
     import torch
@@ -698,7 +789,7 @@ def main() -> int:
     import synth
 
     fn = dict(product=bench_product, mixed=bench_mixed, component=bench_component, serve=bench_serve,
-              gldpc=bench_gldpc)[args.workload]
+              gldpc=bench_gldpc, rician=bench_rician)[args.workload]
     line = fn(args, sg, np, torch, synth)
     print(json.dumps(line), flush=True)
     return 0

@@ -45,6 +45,20 @@ BPSK maps bit 0 to +1 and bit 1 to -1.  With overall rate R and Eb/N0 in dB,
 sigma^2 = 1 / (2 R 10^(EbN0/10)), r = x + sigma * N(0,1), and the channel LLR is
 L_Ch = log p(r|0)/p(r|1) = 2 r / sigma^2 (the SISO section's definition of L_Ch).
 
+Block Rician fading with QPSK
+-----------------------------
+The block fading section's channel: a frame of N coded bits is interleaved by a
+random permutation (its own for every frame), mapped in pairs (c1, c2) to Gray
+QPSK x = Delta (1 - 2 c1) + j Delta (1 - 2 c2) with Delta = 1, and sent as N/2
+symbols over t coherence blocks of N_c symbols (N = 2 t N_c).  Block b has
+H = sqrt(K/(K+1)) + sqrt(1/(K+1)) H_Ra, H_Ra ~ CN(0, 1) (real and imaginary
+parts of variance 1/2, so E|H|^2 = 1), and y = H x + z with z ~ CN(0, 2 sigma^2).
+With the coefficient known to the receiver, L(c1) = 2 Delta Re(y h*) / sigma^2 and
+L(c2) = 2 Delta Im(y h*) / sigma^2, de-interleaved back to code order.  Eb/N0 sets
+sigma^2 = Delta^2 / (2 R Eb/N0), since Es/N0 = Delta^2 E|H|^2 / sigma^2 and a
+symbol carries 2R information bits.  Streams: the permutation comes from stream 3
+(ranks of its outputs), the fading from stream 2, the noise from stream 1.
+
 Random numbers
 --------------
 Counter-based SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom
@@ -70,6 +84,7 @@ __all__ = [
     "Code", "ebch", "code_from_generator", "encode", "encode_product",
     "splitmix_stream", "info_bits", "gaussians", "sigma2", "bpsk_awgn_llr",
     "product_frames", "component_words", "PRIM_POLY", "Gldpc", "gldpc", "gldpc_frames",
+    "rician_qpsk_llr", "rician_product_frames",
 ]
 
 MASK64 = (1 << 64) - 1
@@ -461,9 +476,9 @@ def info_bits(seed: int, frames, count: int) -> np.ndarray:
     return (splitmix_stream(seed, frames, 0, count) >> np.uint64(63)).astype(np.uint8)
 
 
-def gaussians(seed: int, frames, count: int) -> np.ndarray:
+def gaussians(seed: int, frames, count: int, stream: int = 1) -> np.ndarray:
     npair = (count + 1) // 2
-    o = splitmix_stream(seed, frames, 1, 2 * npair)
+    o = splitmix_stream(seed, frames, stream, 2 * npair)
     u1 = ((o[:, 0::2] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
     u2 = (o[:, 1::2] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
     rad = np.sqrt(-2.0 * np.log(u1))
@@ -471,6 +486,57 @@ def gaussians(seed: int, frames, count: int) -> np.ndarray:
     z[:, 0::2] = rad * np.cos(2.0 * np.pi * u2)
     z[:, 1::2] = rad * np.sin(2.0 * np.pi * u2)
     return z[:, :count]
+
+
+def rician_qpsk_llr(cw: np.ndarray, ebn0_db, rate: float, K: float, nc: int, seed: int, frame_ids) -> np.ndarray:
+    """Channel LLRs (F, N) float64 of codewords cw (F, N) sent over block Rician fading with QPSK
+    (module docstring); N = 2 t nc."""
+    cw = np.asarray(cw, dtype=np.uint8)
+    F, N = cw.shape
+    if N % (2 * nc):
+        raise ValueError("N must be a multiple of 2 * nc")
+    ids = np.asarray(frame_ids, dtype=np.uint64)
+    nsym, t = N // 2, N // (2 * nc)
+    eb = np.broadcast_to(np.asarray(ebn0_db, dtype=np.float64), (F,))
+    s2 = 1.0 / (2.0 * rate * 10.0 ** (eb / 10.0))                              # Delta = 1
+    perm = np.argsort(splitmix_stream(seed, ids, 3, N), axis=1, kind="stable")  # interleaved bit i = code bit perm[i]
+    b = np.take_along_axis(cw, perm, axis=1)
+    x = (1.0 - 2.0 * b[:, 0::2]) + 1j * (1.0 - 2.0 * b[:, 1::2])
+    g = gaussians(seed, ids, 2 * t, stream=2)
+    h_ra = np.sqrt(0.5) * (g[:, 0::2] + 1j * g[:, 1::2])
+    h = np.sqrt(K / (K + 1.0)) + np.sqrt(1.0 / (K + 1.0)) * h_ra              # (F, t)
+    hs = np.repeat(h, nc, axis=1)                                               # (F, nsym)
+    z = gaussians(seed, ids, 2 * nsym, stream=1)
+    noise = np.sqrt(s2)[:, None] * (z[:, 0::2] + 1j * z[:, 1::2])
+    y = hs * x + noise
+    yh = y * np.conj(hs)
+    li = np.empty((F, N), dtype=np.float64)
+    li[:, 0::2] = 2.0 * yh.real / s2[:, None]
+    li[:, 1::2] = 2.0 * yh.imag / s2[:, None]
+    llr = np.empty_like(li)
+    np.put_along_axis(llr, perm, li, axis=1)
+    return llr
+
+
+def rician_product_frames(code: Code, ebn0_db, K: float, nc: int, seed: int, frame_ids, batch: int = 4096):
+    """Product-code frames over block Rician fading with QPSK.  Returns (llr (F,n,n), codewords
+    (F,n,n) uint8, info (F,k,k) uint8)."""
+    frame_ids = np.asarray(frame_ids, dtype=np.uint64)
+    F = frame_ids.shape[0]
+    n, k = code.n, code.k
+    eb = np.broadcast_to(np.asarray(ebn0_db, dtype=np.float64), (F,))
+    llr = np.empty((F, n, n), dtype=np.float64)
+    cw = np.empty((F, n, n), dtype=np.uint8)
+    info = np.empty((F, k, k), dtype=np.uint8)
+    for s in range(0, F, batch):
+        ids = frame_ids[s:s + batch]
+        u = info_bits(seed, ids, k * k).reshape(-1, k, k)
+        c = encode_product(code, u)
+        llr[s:s + batch] = rician_qpsk_llr(c.reshape(len(ids), -1), eb[s:s + batch], (k * k) / (n * n), K, nc,
+                                           seed, ids).reshape(-1, n, n)
+        cw[s:s + batch] = c
+        info[s:s + batch] = u
+    return llr, cw, info
 
 
 def sigma2(ebn0_db: float, rate: float) -> float:

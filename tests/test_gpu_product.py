@@ -123,3 +123,26 @@ def test_full_size_product_workload_sampled(sg):
             print(f"[gpu]   BLER {bler:.4g}; mean half-iters {out['half_iters'].double().mean().item():.2f}",
                   flush=True)
             del x, out
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_product_parity_rician(sg, f32):
+    """[32,26]^2 over block Rician fading with QPSK (N_c = 256, t = 2, K = 8) with the paper's fading
+    settings (alpha 0.5, I_max 20, list-BLER stop 1e-4): deep fades give the decoder inputs far
+    from the AWGN ones."""
+    import torch
+    code = synth.ebch(32, 26)
+    llr, cw, _ = synth.rician_product_frames(code, 6.0, 8.0, 256, 31, np.arange(60))
+    if f32:
+        llr = llr.astype(np.float32).astype(np.float64)
+    label = f"rician {code.name}^2 f32={f32}"
+    print(f"[gpu] product {label}", flush=True)
+    gcode = sg.Code.from_hcols(code.n, code.k, code.hcols)
+    x = torch.from_numpy(llr).to(dtype=torch.float32 if f32 else torch.float64, device="cuda").contiguous()
+    out = sg.sogrand_decode_product(gcode, x, list_max=4, query_cap=10000, max_iter=20, want_app=True,
+                                    list_bler_stop=1e-4)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    r = oracle.decode_product(code, llr, 4, 10000, 20, store_f32=f32, want_app=True, pstop=1e-4, nthreads=8)
+    compare_product(g, r, f32, label)
+    assert r["half_iters"].max() > 2

@@ -109,3 +109,38 @@ def test_channel_llr_scale():
     ber = np.mean((llr < 0) != (cw == 1))
     q = 0.5 * math.erfc(1 / math.sqrt(2 * s2))
     assert abs(ber - q) < 0.003
+
+
+# ---------------------------------------------------------------- block Rician fading with QPSK
+def test_rician_noiseless_signs_follow_the_codeword():
+    code = synth.ebch(32, 26)
+    llr, cw, _ = synth.rician_product_frames(code, 80.0, 8.0, 256, 3, np.arange(6))
+    assert np.all((llr < 0) == (cw == 1))
+
+
+@pytest.mark.parametrize("K", [0.0, 6.0])
+def test_rician_llr_statistics(K):
+    """All-zero codewords: every LLR has mean 2 E|H|^2 / sigma^2 = 2 / sigma^2 (E|H|^2 = 1 for any
+    K), and the per-coherence-block mean LLR spreads like |H|^2, whose variance is
+    (2K + 1) / (K + 1)^2 for a Rician factor K (1 for Rayleigh)."""
+    F, N, nc, rate, eb = 4000, 1024, 64, 0.5, 4.0
+    s2 = 1.0 / (2.0 * rate * 10.0 ** (eb / 10.0))
+    ids = np.arange(F, dtype=np.uint64)
+    llr = synth.rician_qpsk_llr(np.zeros((F, N), np.uint8), eb, rate, K, nc, 9, ids)
+    mu = 2.0 / s2
+    assert abs(llr.mean() / mu - 1.0) < 0.02
+    # regroup code bits by coherence block: interleaved bit i is code bit perm[i], symbol i // 2
+    perm = np.argsort(synth.splitmix_stream(9, ids, 3, N), axis=1, kind="stable")
+    inter = np.take_along_axis(llr, perm, axis=1)
+    block_mean = inter.reshape(F, N // (2 * nc), 2 * nc).mean(axis=2) / mu
+    expect = (2 * K + 1) / (K + 1) ** 2 + s2 / (2 * nc)      # |H|^2 spread plus the noise left in the mean
+    assert abs(block_mean.var() / expect - 1.0) < 0.08
+
+
+def test_rician_large_k_is_awgn():
+    """K -> infinity leaves H = 1: each LLR is 2 (x + n) / sigma^2 with n ~ N(0, sigma^2), as for BPSK."""
+    F, N, rate, eb = 2000, 1024, 0.5, 3.0
+    s2 = 1.0 / (2.0 * rate * 10.0 ** (eb / 10.0))
+    llr = synth.rician_qpsk_llr(np.zeros((F, N), np.uint8), eb, rate, 1e12, 256, 4, np.arange(F))
+    assert abs(llr.mean() / (2.0 / s2) - 1.0) < 0.01
+    assert abs(llr.var() / (4.0 / s2) - 1.0) < 0.02
