@@ -183,97 +183,56 @@ def mixed_frames_f32(nks, lo, hi, seed, F, np):
 
 
 # --------------------------------------------------------------------------------------------
-# product: [64,57]^2 at three Eb/N0, plain and batched forms
+# frame workloads (product, gldpc, rician): frames of one code at a few Eb/N0, several forms
 # --------------------------------------------------------------------------------------------
-def bench_product(args, sg, np, torch, synth):
-    dev = torch.device("cuda:0")
-    code = synth.ebch(N, K)
-    gcode = sg.Code.ebch(N, K)
-    F = args.frames
-    llr_parts, cw_parts = [], []
-    for snr, seed in SNRS:
-        llr, cw, _ = synth.product_frames(code, snr, seed, np.arange(F))
-        llr_parts.append(llr)
-        cw_parts.append(cw)
-    llr_all = np.concatenate(llr_parts)
-    cw_all = torch.from_numpy(np.concatenate(cw_parts)).to(dev)
-    del cw_parts
-    x64 = torch.from_numpy(llr_all).to(dev)
-    x32 = x64.float()
-    total = x64.shape[0]
-    info_bits_per_step = total * K * K
+def frame_outputs(torch, total, n, dev):
+    return dict(hard=torch.empty((total, n, n), dtype=torch.uint8, device=dev), llr_app=None,
+                success=torch.empty(total, dtype=torch.uint8, device=dev),
+                half_iters=torch.empty(total, dtype=torch.int16, device=dev),
+                sum_queries=torch.empty(total, dtype=torch.int64, device=dev),
+                sum_max_queries=torch.empty(total, dtype=torch.int64, device=dev))
 
-    def outputs():
-        return dict(
-            hard=torch.empty((total, N, N), dtype=torch.uint8, device=dev), llr_app=None,
-            success=torch.empty(total, dtype=torch.uint8, device=dev),
-            half_iters=torch.empty(total, dtype=torch.int16, device=dev),
-            sum_queries=torch.empty(total, dtype=torch.int64, device=dev),
-            sum_max_queries=torch.empty(total, dtype=torch.int64, device=dev))
 
-    fcode = torch.zeros(total, dtype=torch.uint8, device=dev)
-    foff = torch.arange(total, dtype=torch.int64, device=dev) * (N * N)
+def per_snr_stats(out, cw_all, snrs, F, n):
+    """BLER (with its 95 % Wilson interval), iterations and queries per coded bit for each Eb/N0
+    group of F consecutive frames."""
+    import torch
+    total = cw_all.shape[0]
+    err = torch.any((out["hard"].view(total, n, n) != cw_all).view(total, -1), dim=1).cpu().numpy()
+    hi = out["half_iters"].double().cpu().numpy()
+    sq = out["sum_queries"].double().cpu().numpy()
+    smq = out["sum_max_queries"].double().cpu().numpy()
+    res = {}
+    for j, (snr, _) in enumerate(snrs):
+        sl = slice(j * F, (j + 1) * F)
+        k_err = int(err[sl].sum())
+        res[str(snr)] = dict(bler=k_err / F, bler_ci95=wilson(k_err, F), frames=F,
+                             avg_iterations=float(hi[sl].mean() / 2),
+                             queries_per_bit=float(sq[sl].mean() / (n * n)),
+                             parallel_queries_per_bit=float(smq[sl].mean() / (n * n)))
+    return res
 
-    iters, stop = args.iters, args.list_bler_stop
 
-    def run_batched(x, out, sc):
-        sg.sogrand_decode_batched([gcode], fcode, foff, x.view(-1), list_max=L, query_cap=QCAP, max_iter=iters,
-                                  sched_=sc, outputs=out, list_bler_stop=stop)
-
-    def tune(x):
-        """Times candidate launch shapes on the first 3000 frames; returns the fastest."""
-        m = min(3000, total)
-        xs = x[:m].contiguous().view(-1)
-        best = None
-        for w, f, ch, g in [(8, 2, 1, 3), (4, 2, 1, 6), (8, 3, 1, 3), (4, 2, 1, 8), (8, 2, 2, 3), (4, 1, 1, 6)]:
-            sc = sg.sched(w, f, ch, g)
-            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, iters, sched_=sc, list_bler_stop=stop)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, iters, sched_=sc, list_bler_stop=stop)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            if best is None or dt < best[0]:
-                best = (dt, sc)
-        return best[1]
-
+def time_forms(args, sg, names, make_step, out_of, cw_all, snrs, F, n, info_bits_per_step):
+    """Times each form's step; make_step(form, out) returns (step, sched or None)."""
     forms = {}
-    for form in args.forms.split(","):
-        x = x64 if form.endswith("f64") else x32
-        out = outputs()
-        if form.startswith("plain"):
-            step = (lambda x_, o_: lambda: sg.sogrand_decode_product(
-                gcode, x_, list_max=L, query_cap=QCAP, max_iter=iters, outputs=o_, list_bler_stop=stop))(x, out)
-            sc = None
-        elif form.startswith("batched"):
-            out["hard"] = out["hard"].view(-1)
-            out["status"] = torch.zeros(1, dtype=torch.int32, device=dev)
-            sc = tune(x) if args.tune else sg.sched()
-            step = (lambda x_, o_, s_: lambda: run_batched(x_, o_, s_))(x, out, sc)
-        else:
-            raise SystemExit(f"unknown form {form}")
+    for form in names:
+        out = out_of(form)
+        step, sc = make_step(form, out)
         ms, kern, work = timed(step, args.steps, args.warmup, sg, count=not args.no_count)
         if "status" in out and int(out["status"].item()) != 0:
             raise SystemExit(f"{form}: batched kernel reported status {int(out['status'].item())}")
-        err = torch.any((out["hard"].view(total, N, N) != cw_all).view(total, -1), dim=1).cpu().numpy()
-        hi = out["half_iters"].double().cpu().numpy()
-        sq = out["sum_queries"].double().cpu().numpy()
-        smq = out["sum_max_queries"].double().cpu().numpy()
-        per_snr = {}
-        for j, (snr, _) in enumerate(SNRS):
-            sl = slice(j * F, (j + 1) * F)
-            k_err = int(err[sl].sum())
-            per_snr[str(snr)] = dict(
-                bler=k_err / F, bler_ci95=wilson(k_err, F), frames=F,
-                avg_iterations=float(hi[sl].mean() / 2), queries_per_bit=float(sq[sl].mean() / (N * N)),
-                parallel_queries_per_bit=float(smq[sl].mean() / (N * N)))
         forms[form] = dict(ms_per_step=ms, info_bits_per_s=info_bits_per_step / (ms / 1e3),
-                           per_snr=per_snr, kernels=kern, work=work)
+                           per_snr=per_snr_stats(out, cw_all, snrs, F, n), kernels=kern, work=work)
         if sc is not None:
             forms[form]["sched"] = dict(waves_per_group=sc.waves_per_group, frames_per_group=sc.frames_per_group,
                                         steal_chunk=sc.steal_chunk, groups_per_cu=sc.groups_per_cu)
+    return forms
 
-    # matched BLER: every Eb/N0 inside the plain binary64 form's 95% interval
+
+def choose_form(forms):
+    """The fastest form whose BLER lies inside the plain binary64 form's 95 % interval at every
+    Eb/N0; adds bler_matches_plain_f64 and, for batched forms, speedup_vs_plain."""
     base = forms.get("plain_f64")
     best_name, best = None, None
     for name, f in forms.items():
@@ -290,15 +249,110 @@ def bench_product(args, sg, np, torch, synth):
         if f"plain_{prec}" in forms and f"batched_{prec}" in forms:
             forms[f"batched_{prec}"]["speedup_vs_plain"] = (forms[f"plain_{prec}"]["ms_per_step"]
                                                             / forms[f"batched_{prec}"]["ms_per_step"])
+    return best_name, best
 
-    # roofline of the dominant kernel of the chosen form: the row/column pass kernel of the
-    # plain forms, the persistent kernel of the batched forms
+
+def dominant_roofline(args, best_name, best, n, traffic=None):
+    """Roofline of the chosen form's dominant kernel: the pass kernel of the plain forms, the
+    persistent kernel of the batched forms."""
     if best_name.startswith("batched"):
-        roof = roofline("batched", "k_batched (persistent)", best["kernels"], best["work"], args.steps, N, L,
-                        traffic=recorded_traffic(best_name))
-    else:
-        roof = roofline("product_pass", "k_product_pass (row and column instantiations)", best["kernels"],
-                        best["work"], args.steps, N, L, traffic=recorded_traffic(best_name))
+        return roofline("batched", "k_batched (persistent)", best["kernels"], best["work"], args.steps, n, L,
+                        traffic=traffic)
+    return roofline("product_pass", "k_product_pass (both word families)", best["kernels"], best["work"],
+                    args.steps, n, L, traffic=traffic)
+
+
+def oracle_baseline(args, np, llr_all, ngroups, F, decode, info_bits_per_frame):
+    """The oracle over the first cpu_frames frames of each Eb/N0 group, on up to 16 threads."""
+    if args.no_cpu or args.cpu_frames <= 0:
+        return None
+    threads = min(16, len(os.sched_getaffinity(0)))
+    cf = min(args.cpu_frames, F)
+    sample = np.concatenate([llr_all[j * F:j * F + cf] for j in range(ngroups)])
+    t0 = time.perf_counter()
+    decode(sample, threads)
+    dt = time.perf_counter() - t0
+    return dict(value=sample.shape[0] * info_bits_per_frame / dt, unit="info bits/s", cores=threads, kind="oracle",
+                sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall")
+
+
+def load_frames(np, torch, make, snrs, F, dev):
+    llr_parts, cw_parts = [], []
+    for snr, seed in snrs:
+        llr, cw = make(snr, seed)
+        llr_parts.append(llr)
+        cw_parts.append(cw)
+    llr_all = np.concatenate(llr_parts)
+    cw_all = torch.from_numpy(np.concatenate(cw_parts)).to(dev)
+    x64 = torch.from_numpy(llr_all).to(dev)
+    return llr_all, cw_all, x64, x64.float()
+
+
+def plain_or_batched(sg, torch, gcode, total, n, dev, x64, x32, iters, stop, alpha=0.5, decode=None, sched_of=None):
+    """(out_of, make_step) for the forms plain_f64/f32 (decode: sogrand_decode_product or
+    sogrand_decode_gldpc) and batched_f64/f32 (product codes only)."""
+    decode = decode or sg.sogrand_decode_product
+    fcode = torch.zeros(total, dtype=torch.uint8, device=dev)
+    foff = torch.arange(total, dtype=torch.int64, device=dev) * (n * n)
+
+    def out_of(form):
+        out = frame_outputs(torch, total, n, dev)
+        if form.startswith("batched"):
+            out["hard"] = out["hard"].view(-1)
+            out["status"] = torch.zeros(1, dtype=torch.int32, device=dev)
+        return out
+
+    def make_step(form, out):
+        x = x64 if form.endswith("f64") else x32
+        if form.startswith("plain"):
+            return (lambda: decode(gcode, x, list_max=L, query_cap=QCAP, max_iter=iters, alpha=alpha, outputs=out,
+                                   list_bler_stop=stop)), None
+        if form.startswith("batched"):
+            sc = sched_of(x) if sched_of else sg.sched()
+            return (lambda: sg.sogrand_decode_batched([gcode], fcode, foff, x.view(-1), list_max=L, query_cap=QCAP,
+                                                      max_iter=iters, alpha=alpha, sched_=sc, outputs=out,
+                                                      list_bler_stop=stop)), sc
+        raise SystemExit(f"unknown form {form}")
+    return out_of, make_step, fcode, foff
+
+
+# --------------------------------------------------------------------------------------------
+# product: [64,57]^2 at three Eb/N0, plain and batched forms
+# --------------------------------------------------------------------------------------------
+def bench_product(args, sg, np, torch, synth):
+    dev = torch.device("cuda:0")
+    code = synth.ebch(N, K)
+    gcode = sg.Code.ebch(N, K)
+    F = args.frames
+    llr_all, cw_all, x64, x32 = load_frames(
+        np, torch, lambda snr, seed: synth.product_frames(code, snr, seed, np.arange(F))[:2], SNRS, F, dev)
+    total = x64.shape[0]
+    iters, stop = args.iters, args.list_bler_stop
+
+    def tune(x):
+        """Times candidate launch shapes on the first 3000 frames; returns the fastest."""
+        m = min(3000, total)
+        xs = x[:m].contiguous().view(-1)
+        best = None
+        for w, f, ch, g in [(8, 2, 4, 3), (8, 2, 2, 3), (8, 3, 4, 3), (8, 2, 4, 2), (4, 2, 4, 6), (8, 2, 1, 3)]:
+            sc = sg.sched(w, f, ch, g)
+            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, iters, sched_=sc, list_bler_stop=stop)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, iters, sched_=sc, list_bler_stop=stop)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, sc)
+        return best[1]
+
+    out_of, make_step, fcode, foff = plain_or_batched(sg, torch, gcode, total, N, dev, x64, x32, iters, stop,
+                                                      sched_of=tune if args.tune else None)
+    forms = time_forms(args, sg, args.forms.split(","), make_step, out_of, cw_all, SNRS, F, N, total * K * K)
+    best_name, best = choose_form(forms)
+    # the recorded HBM bytes were counted on the default configuration only
+    default_cfg = iters == ITERS and stop == 0.0 and F == 10000
+    roof = dominant_roofline(args, best_name, best, N, traffic=recorded_traffic(best_name) if default_cfg else None)
 
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
@@ -308,17 +362,10 @@ def bench_product(args, sg, np, torch, synth):
         torch.cuda.synchronize()
         del src, dst
 
-    cpu = None
-    if not args.no_cpu and args.cpu_frames > 0:
+    def oracle_decode(sample, threads):
         import oracle
-        threads = min(16, len(os.sched_getaffinity(0)))
-        cf = min(args.cpu_frames, F)
-        sample = np.concatenate([llr_all[j * F:j * F + cf] for j in range(len(SNRS))])
-        t0 = time.perf_counter()
         oracle.decode_product(code, sample, L, QCAP, iters, nthreads=threads, pstop=stop)
-        dt = time.perf_counter() - t0
-        cpu = dict(value=sample.shape[0] * K * K / dt, unit="info bits/s", cores=threads, kind="oracle",
-                   sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall")
+    cpu = oracle_baseline(args, np, llr_all, len(SNRS), F, oracle_decode, K * K)
 
     storage = "f32" if best_name.endswith("f32") else "f64"
     settings = f"L=4, query cap 1e4, {iters} iterations, alpha 0.5"
@@ -372,7 +419,7 @@ def bench_mixed(args, sg, np, torch, synth):
     m = min(2000, F)
     end = int(offs[m - 1] + codes[cidx[m - 1]].n ** 2)
     best = None
-    for w, f, ch, g in [(8, 2, 1, 3), (4, 2, 1, 6), (8, 4, 1, 2), (4, 2, 1, 4), (8, 2, 1, 2)]:
+    for w, f, ch, g in [(8, 2, 4, 3), (8, 2, 4, 2), (8, 2, 2, 3), (4, 2, 4, 5), (8, 2, 1, 3)]:
         sc = sg.sched(w, f, ch, g)
         t0 = time.perf_counter()
         sg.sogrand_decode_batched(gcodes, fc[:m], fo[:m], x[:end], L, qcap, ITERS, sched_=sc)
@@ -508,60 +555,21 @@ def bench_gldpc(args, sg, np, torch, synth):
     code = synth.ebch(32, 26)
     g = synth.gldpc(code)
     gcode = sg.Code.ebch(32, 26)
-    n = code.n
-    F = args.frames
-    llr_parts, cw_parts = [], []
-    for snr, seed in GLDPC_SNRS:
-        llr, cw, _ = synth.gldpc_frames(g, snr, seed, np.arange(F))
-        llr_parts.append(llr)
-        cw_parts.append(cw)
-    llr_all = np.concatenate(llr_parts)
-    cw_all = torch.from_numpy(np.concatenate(cw_parts)).to(dev)
-    x64 = torch.from_numpy(llr_all).to(dev)
-    x32 = x64.float()
+    n, F = code.n, args.frames
+    llr_all, cw_all, x64, x32 = load_frames(
+        np, torch, lambda snr, seed: synth.gldpc_frames(g, snr, seed, np.arange(F))[:2], GLDPC_SNRS, F, dev)
     total = x64.shape[0]
-    info_bits_per_step = total * g.dim
-    forms = {}
-    for form in [f for f in args.forms.split(",") if f.startswith("plain")]:
-        x = x64 if form.endswith("f64") else x32
-        out = dict(hard=torch.empty((total, n, n), dtype=torch.uint8, device=dev), llr_app=None,
-                   success=torch.empty(total, dtype=torch.uint8, device=dev),
-                   half_iters=torch.empty(total, dtype=torch.int16, device=dev),
-                   sum_queries=torch.empty(total, dtype=torch.int64, device=dev),
-                   sum_max_queries=torch.empty(total, dtype=torch.int64, device=dev))
-        step = (lambda x_, o_: lambda: sg.sogrand_decode_gldpc(
-            gcode, x_, list_max=L, query_cap=QCAP, max_iter=GLDPC_ITERS, alpha=GLDPC_ALPHA, outputs=o_,
-            list_bler_stop=GLDPC_STOP))(x, out)
-        ms, kern, work = timed(step, args.steps, args.warmup, sg, count=not args.no_count)
-        err = torch.any((out["hard"] != cw_all).view(total, -1), dim=1).cpu().numpy()
-        hi = out["half_iters"].double().cpu().numpy()
-        sq = out["sum_queries"].double().cpu().numpy()
-        smq = out["sum_max_queries"].double().cpu().numpy()
-        per_snr = {}
-        for j, (snr, _) in enumerate(GLDPC_SNRS):
-            sl = slice(j * F, (j + 1) * F)
-            k_err = int(err[sl].sum())
-            per_snr[str(snr)] = dict(
-                bler=k_err / F, bler_ci95=wilson(k_err, F), frames=F,
-                avg_iterations=float(hi[sl].mean() / 2), queries_per_bit=float(sq[sl].mean() / (n * n)),
-                parallel_queries_per_bit=float(smq[sl].mean() / (n * n)))
-        forms[form] = dict(ms_per_step=ms, info_bits_per_s=info_bits_per_step / (ms / 1e3), per_snr=per_snr,
-                           kernels=kern, work=work)
-    best_name = min(forms, key=lambda k: forms[k]["ms_per_step"])
-    best = forms[best_name]
-    roof = roofline("product_pass", "k_product_pass (QC-GLDPC layout, both block rows)", best["kernels"],
-                    best["work"], args.steps, n, L)
-    cpu = None
-    if not args.no_cpu and args.cpu_frames > 0:
+    out_of, make_step, _, _ = plain_or_batched(sg, torch, gcode, total, n, dev, x64, x32, GLDPC_ITERS, GLDPC_STOP,
+                                               alpha=GLDPC_ALPHA, decode=sg.sogrand_decode_gldpc)
+    names = [f for f in args.forms.split(",") if f.startswith("plain")]
+    forms = time_forms(args, sg, names, make_step, out_of, cw_all, GLDPC_SNRS, F, n, total * g.dim)
+    best_name, best = choose_form(forms)
+    roof = dominant_roofline(args, best_name, best, n)
+
+    def oracle_decode(sample, threads):
         import oracle
-        threads = min(16, len(os.sched_getaffinity(0)))
-        cf = min(args.cpu_frames, F)
-        sample = np.concatenate([llr_all[j * F:j * F + cf] for j in range(len(GLDPC_SNRS))])
-        t0 = time.perf_counter()
         oracle.decode_gldpc(code, sample, L, QCAP, GLDPC_ITERS, GLDPC_ALPHA, pstop=GLDPC_STOP, nthreads=threads)
-        dt = time.perf_counter() - t0
-        cpu = dict(value=sample.shape[0] * g.dim / dt, unit="info bits/s", cores=threads, kind="oracle",
-                   sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall")
+    cpu = oracle_baseline(args, np, llr_all, len(GLDPC_SNRS), F, oracle_decode, g.dim)
     config = {"workload": f"QC-GLDPC (1024, {g.dim}) with [32,26] eBCH check nodes (the paper's (1024,640)), "
                           f"BPSK-AWGN 2.0/2.25/2.5 dB, {F} frames each, L=4, query cap 1e4, alpha 0.6, "
                           "20 iterations, list-BLER stop 1e-5",
@@ -584,72 +592,20 @@ def bench_rician(args, sg, np, torch, synth):
     code = synth.ebch(N, K)
     gcode = sg.Code.ebch(N, K)
     F = args.frames
-    llr_parts, cw_parts = [], []
-    for snr, seed in RICIAN_SNRS:
-        llr, cw, _ = synth.rician_product_frames(code, snr, RICIAN_K, RICIAN_NC, seed, np.arange(F))
-        llr_parts.append(llr)
-        cw_parts.append(cw)
-    llr_all = np.concatenate(llr_parts)
-    cw_all = torch.from_numpy(np.concatenate(cw_parts)).to(dev)
-    x64 = torch.from_numpy(llr_all).to(dev)
-    x32 = x64.float()
+    llr_all, cw_all, x64, x32 = load_frames(
+        np, torch, lambda snr, seed: synth.rician_product_frames(code, snr, RICIAN_K, RICIAN_NC, seed,
+                                                                 np.arange(F))[:2], RICIAN_SNRS, F, dev)
     total = x64.shape[0]
-    info_bits_per_step = total * K * K
-    fcode = torch.zeros(total, dtype=torch.uint8, device=dev)
-    foff = torch.arange(total, dtype=torch.int64, device=dev) * (N * N)
-    forms = {}
-    for form in [f for f in args.forms.split(",") if f in ("plain_f64", "plain_f32", "batched_f32")]:
-        x = x64 if form.endswith("f64") else x32
-        out = dict(hard=torch.empty((total, N, N), dtype=torch.uint8, device=dev), llr_app=None,
-                   success=torch.empty(total, dtype=torch.uint8, device=dev),
-                   half_iters=torch.empty(total, dtype=torch.int16, device=dev),
-                   sum_queries=torch.empty(total, dtype=torch.int64, device=dev),
-                   sum_max_queries=torch.empty(total, dtype=torch.int64, device=dev))
-        if form.startswith("plain"):
-            step = (lambda x_, o_: lambda: sg.sogrand_decode_product(
-                gcode, x_, list_max=L, query_cap=QCAP, max_iter=RICIAN_ITERS, outputs=o_,
-                list_bler_stop=RICIAN_STOP))(x, out)
-        else:
-            out["hard"] = out["hard"].view(-1)
-            out["status"] = torch.zeros(1, dtype=torch.int32, device=dev)
-            step = (lambda x_, o_: lambda: sg.sogrand_decode_batched(
-                [gcode], fcode, foff, x_.view(-1), list_max=L, query_cap=QCAP, max_iter=RICIAN_ITERS,
-                outputs=o_, list_bler_stop=RICIAN_STOP))(x, out)
-        ms, kern, work = timed(step, args.steps, args.warmup, sg, count=not args.no_count)
-        if "status" in out and int(out["status"].item()) != 0:
-            raise SystemExit(f"{form}: batched kernel reported status {int(out['status'].item())}")
-        err = torch.any((out["hard"].view(total, N, N) != cw_all).view(total, -1), dim=1).cpu().numpy()
-        hi = out["half_iters"].double().cpu().numpy()
-        sq = out["sum_queries"].double().cpu().numpy()
-        smq = out["sum_max_queries"].double().cpu().numpy()
-        per_snr = {}
-        for j, (snr, _) in enumerate(RICIAN_SNRS):
-            sl = slice(j * F, (j + 1) * F)
-            k_err = int(err[sl].sum())
-            per_snr[str(snr)] = dict(
-                bler=k_err / F, bler_ci95=wilson(k_err, F), frames=F,
-                avg_iterations=float(hi[sl].mean() / 2), queries_per_bit=float(sq[sl].mean() / (N * N)),
-                parallel_queries_per_bit=float(smq[sl].mean() / (N * N)))
-        forms[form] = dict(ms_per_step=ms, info_bits_per_s=info_bits_per_step / (ms / 1e3), per_snr=per_snr,
-                           kernels=kern, work=work)
-    best_name = min(forms, key=lambda k: forms[k]["ms_per_step"])
-    best = forms[best_name]
-    if best_name.startswith("batched"):
-        roof = roofline("batched", "k_batched (persistent)", best["kernels"], best["work"], args.steps, N, L)
-    else:
-        roof = roofline("product_pass", "k_product_pass (row and column instantiations)", best["kernels"],
-                        best["work"], args.steps, N, L)
-    cpu = None
-    if not args.no_cpu and args.cpu_frames > 0:
+    out_of, make_step, _, _ = plain_or_batched(sg, torch, gcode, total, N, dev, x64, x32, RICIAN_ITERS, RICIAN_STOP)
+    names = [f for f in args.forms.split(",") if f in ("plain_f64", "plain_f32", "batched_f32")]
+    forms = time_forms(args, sg, names, make_step, out_of, cw_all, RICIAN_SNRS, F, N, total * K * K)
+    best_name, best = choose_form(forms)
+    roof = dominant_roofline(args, best_name, best, N)
+
+    def oracle_decode(sample, threads):
         import oracle
-        threads = min(16, len(os.sched_getaffinity(0)))
-        cf = min(args.cpu_frames, F)
-        sample = np.concatenate([llr_all[j * F:j * F + cf] for j in range(len(RICIAN_SNRS))])
-        t0 = time.perf_counter()
         oracle.decode_product(code, sample, L, QCAP, RICIAN_ITERS, pstop=RICIAN_STOP, nthreads=threads)
-        dt = time.perf_counter() - t0
-        cpu = dict(value=sample.shape[0] * K * K / dt, unit="info bits/s", cores=threads, kind="oracle",
-                   sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall")
+    cpu = oracle_baseline(args, np, llr_all, len(RICIAN_SNRS), F, oracle_decode, K * K)
     config = {"workload": f"eBCH [64,57]^2 product code, block Rician fading (N_c 256, t 8, K 6) with Gray QPSK "
                           f"and a random interleaver, Eb/N0 6/8/10 dB, {F} frames each, L=4, query cap 1e4, "
                           "alpha 0.5, 20 iterations, list-BLER stop 1e-5",

@@ -195,7 +195,7 @@ typedef struct {
     int groups_per_cu;     /* 1..64 */
 } sogrand_sched_t;
 
-/* A measured default (8 waves, 2 frames, 1 line, 3 groups per CU). */
+/* A measured default (8 waves, 2 frames, 4 lines, 3 groups per CU). */
 void sogrand_sched_default(sogrand_sched_t *s);
 
 /* Block turbo decoding (section "Iterative decoding") of nframes frames whose

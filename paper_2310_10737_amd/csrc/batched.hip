@@ -349,7 +349,7 @@ void sogrand_sched_default(sogrand_sched_t *s) {
     if (!s) return;
     s->waves_per_group = 8;
     s->frames_per_group = 2;
-    s->steal_chunk = 1;
+    s->steal_chunk = 4;
     s->groups_per_cu = 3;
 }
 
