@@ -71,3 +71,28 @@ def test_gldpc_empty_and_bad_shape(sg):
     assert out["hard"].shape == (0, 32, 32)
     with pytest.raises(ValueError):
         sg.sogrand_decode_gldpc(gcode, torch.zeros((2, 32, 16), dtype=torch.float64, device="cuda"))
+
+
+def test_full_size_gldpc_workload_sampled(sg):
+    """The QC-GLDPC benchmark workload at full size (1e4 frames at each of 2.0/2.25/2.5 dB, alpha 0.6,
+    I_max 20, stop 1e-5, binary32 storage) in the launch the benchmark times; sampled frames vs the
+    oracle."""
+    import torch
+    code = synth.ebch(32, 26)
+    g = synth.gldpc(code)
+    gcode = sg.Code.ebch(32, 26)
+    rng = np.random.default_rng(3)
+    for snr, seed in ((2.0, 11), (2.25, 12), (2.5, 13)):
+        print(f"[gpu] full gldpc {snr} dB", flush=True)
+        llr, cw, _ = synth.gldpc_frames(g, snr, seed, np.arange(10000))
+        x = torch.from_numpy(llr).to(dtype=torch.float32, device="cuda")
+        out = sg.sogrand_decode_gldpc(gcode, x, list_max=4, query_cap=10000, max_iter=20, alpha=0.6,
+                                      list_bler_stop=1e-5)
+        torch.cuda.synchronize()
+        sample = np.sort(rng.choice(10000, size=20, replace=False))
+        got = {k: v.cpu().numpy()[sample] for k, v in out.items() if v is not None}
+        ref = oracle.decode_gldpc(code, llr[sample].astype(np.float32).astype(np.float64), 4, 10000, 20, 0.6,
+                                  store_f32=True, pstop=1e-5, nthreads=8)
+        for key in ("success", "half_iters", "sum_queries", "sum_max_queries", "hard"):
+            np.testing.assert_array_equal(got[key].astype(np.int64), ref[key].astype(np.int64), err_msg=key)
+        del x, out

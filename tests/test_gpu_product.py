@@ -146,3 +146,34 @@ def test_product_parity_rician(sg, f32):
     r = oracle.decode_product(code, llr, 4, 10000, 20, store_f32=f32, want_app=True, pstop=1e-4, nthreads=8)
     compare_product(g, r, f32, label)
     assert r["half_iters"].max() > 2
+
+
+def test_full_size_batched_workload_sampled(sg):
+    """The default benchmark line's form: all 3e4 [64,57]^2 frames in one persistent launch with the
+    default launch shape and binary32 storage.  Every frame equals the plain path's decode, and
+    sampled frames equal the oracle's."""
+    import torch
+    code = synth.ebch(64, 57)
+    gcode = sg.Code.ebch(64, 57)
+    parts = [synth.product_frames(code, snr, seed, np.arange(10000))[0] for snr, seed in ((2.5, 1), (3.0, 2), (3.5, 3))]
+    llr = np.concatenate(parts)
+    F = llr.shape[0]
+    x = torch.from_numpy(llr).to(dtype=torch.float32, device="cuda")
+    print("[gpu] full batched [64,57]^2 f32", flush=True)
+    fc = torch.zeros(F, dtype=torch.uint8, device="cuda")
+    fo = torch.arange(F, dtype=torch.int64, device="cuda") * (64 * 64)
+    b = sg.sogrand_decode_batched([gcode], fc, fo, x.view(-1), list_max=4, query_cap=10000, max_iter=6)
+    p = sg.sogrand_decode_product(gcode, x, list_max=4, query_cap=10000, max_iter=6)
+    torch.cuda.synchronize()
+    assert int(b["status"].item()) == 0
+    for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
+        assert torch.equal(b[key].to(torch.int64), p[key].to(torch.int64)), key
+    assert torch.equal(b["hard"].view(F, 64, 64), p["hard"])
+    rng = np.random.default_rng(2)
+    sample = np.sort(rng.choice(F, size=24, replace=False))
+    r = oracle.decode_product(code, llr[sample].astype(np.float32).astype(np.float64), 4, 10000, 6,
+                              store_f32=True, nthreads=8)
+    for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
+        np.testing.assert_array_equal(b[key].cpu().numpy()[sample].astype(np.int64), r[key].astype(np.int64),
+                                      err_msg=key)
+    np.testing.assert_array_equal(b["hard"].view(F, 64, 64).cpu().numpy()[sample], r["hard"])
