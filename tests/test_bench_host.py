@@ -41,3 +41,29 @@ def test_recorded_traffic_requires_matching_kernel_sources(tmp_path, monkeypatch
     assert bench.recorded_traffic("plain_f64") is None
     f.write_text("bytes_per_launch[plain_f32]: 1.5e9\nsource_sha256: " + "0" * 64 + "\n")
     assert bench.recorded_traffic("plain_f32") is None
+
+
+def _form(ms, blers):
+    return dict(ms_per_step=ms, info_bits_per_s=1e3 / ms,
+                per_snr={str(s): dict(bler=b, bler_ci95=bench.wilson(int(round(b * 10000)), 10000))
+                         for s, b in blers.items()})
+
+
+def test_choose_form_takes_the_fastest_form_at_matched_bler():
+    forms = {"plain_f64": _form(23.0, {2.5: 0.88, 3.0: 0.0133}),
+             "plain_f32": _form(22.0, {2.5: 0.88, 3.0: 0.0133}),
+             "batched_f32": _form(19.0, {2.5: 0.88, 3.0: 0.0133}),
+             "batched_f64": _form(18.0, {2.5: 0.88, 3.0: 0.05})}     # faster, but its BLER is off
+    name, best = bench.choose_form(forms)
+    assert name == "batched_f32" and best is forms["batched_f32"]
+    assert forms["batched_f64"]["bler_matches_plain_f64"] is False
+    assert forms["batched_f32"]["speedup_vs_plain"] == pytest.approx(22.0 / 19.0)
+    assert forms["batched_f64"]["speedup_vs_plain"] == pytest.approx(23.0 / 18.0)
+
+
+def test_every_workload_is_selectable():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0
+    for w in ("product", "mixed", "component", "serve", "gldpc", "rician"):
+        assert w in r.stdout
