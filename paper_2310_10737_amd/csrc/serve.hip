@@ -174,20 +174,28 @@ __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
     const char *slot = a.arena + d.slot;
     const uint64_t *mk = reinterpret_cast<const uint64_t *>(slot + sl.masks);
     const uint32_t *hcol = load_uniform(&a.codes[d.code].hcol);
+    // the line masks and H columns are staged in LDS with coalesced loads, so that the
+    // syndrome loops below read them without a dependent memory access per bit
+    __shared__ uint64_t mk_s[kWavesPerBlock][2 * SOGRAND_NMAX];
+    __shared__ uint32_t hc_s[kWavesPerBlock][SOGRAND_NMAX];
+    const int wave = threadIdx.x / kWave;
+    for (int t = lane; t < 2 * n; t += kWave) mk_s[wave][t] = mk[t];
+    for (int t = lane; t < n; t += kWave) hc_s[wave][t] = hcol[t];
+    wave_sync();
     bool bad = false;
     for (int b = 0; b < 2; b++) {
         const int x = lane + kWave * b;
         if (x >= n) continue;
-        const uint64_t m0 = mk[x * 2], m1 = mk[x * 2 + 1];
+        const uint64_t m0 = mk_s[wave][x * 2], m1 = mk_s[wave][x * 2 + 1];
         uint32_t s = 0;
         for (int j = 0; j < n; j++) {
             const uint64_t bit = j < 64 ? (m0 >> j) & 1ull : (m1 >> (j - 64)) & 1ull;
-            if (bit) s ^= hcol[j];
+            if (bit) s ^= hc_s[wave][j];
         }
         uint32_t t = 0;
         for (int l = 0; l < n; l++) {
-            const uint64_t w = x < 64 ? mk[l * 2] : mk[l * 2 + 1];
-            if ((w >> (x & 63)) & 1ull) t ^= hcol[l];
+            const uint64_t w = mk_s[wave][l * 2 + (x >> 6)];
+            if ((w >> (x & 63)) & 1ull) t ^= hc_s[wave][l];
         }
         bad |= (s != 0u) || (t != 0u);
     }
