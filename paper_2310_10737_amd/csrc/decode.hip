@@ -234,7 +234,16 @@ __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, 
     if (f >= a.nframes) return;
     if (a.done[f]) return;
     const int n = a.code.n;
-    const uint64_t *mk = a.masks + f * n * 2;
+    // the frame's line masks and the H columns are staged in LDS with coalesced loads,
+    // so that the syndrome loops below read them without a memory access per bit
+    __shared__ uint64_t mk_s[kWavesPerBlock][2 * SOGRAND_NMAX];
+    __shared__ uint32_t hc_s[kWavesPerBlock][SOGRAND_NMAX];
+    const uint64_t *mk_g = a.masks + f * n * 2;
+    for (int t = lane; t < 2 * n; t += kWave) mk_s[wave][t] = mk_g[t];
+    for (int t = lane; t < n; t += kWave) hc_s[wave][t] = a.code.hcol[t];
+    wave_sync();
+    const uint64_t *mk = mk_s[wave];
+    const uint32_t *hcol = hc_s[wave];
     bool bad = false;
     for (int b = 0; b < 2; b++) {
         const int x = lane + kWave * b;
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, 
         uint32_t s = 0;
         for (int i = 0; i < n; i++) {
             const uint64_t bit = i < 64 ? (m0 >> i) & 1ull : (m1 >> (i - 64)) & 1ull;
-            if (bit) s ^= a.code.hcol[i];
+            if (bit) s ^= hcol[i];
         }
         // x as a word of the other family: its bit l is bit `bit` of the last pass's
         // word `src` (product: bit x of word l; QC-GLDPC: bit l of word (x + l) mod n
@@ -254,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, 
             const int src = a.topo == kProduct ? l : ((h & 1) ? (x + l) % n : (x - l + n) % n);
             const int bit = a.topo == kProduct ? x : l;
             const uint64_t w = bit < 64 ? mk[src * 2] : mk[src * 2 + 1];
-            if ((w >> (bit & 63)) & 1ull) t ^= a.code.hcol[l];
+            if ((w >> (bit & 63)) & 1ull) t ^= hcol[l];
         }
         bad |= (s != 0u) || (t != 0u);
     }
