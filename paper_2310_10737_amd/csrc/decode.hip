@@ -1,6 +1,6 @@
 // SOGRAND component decoding and plain block-turbo product decoding on gfx950:
 // one launch per half-iteration plus a per-frame validity check.
-#include "word.hpp"
+#include "pair.hpp"
 
 namespace sg {
 
@@ -225,6 +225,64 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
     }
 }
 
+// Words of up to 32 bits, two per wave (decode_pair): lanes 0-31 take global word
+// 2p and lanes 32-63 word 2p + 1 of pair p.  A half whose word lies past the last
+// frame, or in a frame that has stopped, takes part without testing patterns.
+template <typename T, bool ROWS, int WPB, bool STOP, int TOPO>
+__global__ __launch_bounds__(kWave * WPB) void k_product_pass_pair(ProductArgs a) {
+    using LN = Lines<TOPO, ROWS>;
+    __shared__ PairLds lds[WPB][2];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = WPB == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const uint32_t hl = (uint32_t)(lane & 31);
+    const bool upper = lane >= 32;
+    PairLds &S = lds[wave][upper ? 1 : 0];
+    const uint32_t n = (uint32_t)a.code.n;
+    // the host keeps nframes * n below 2^31
+    const uint32_t pair = (uint32_t)logical_block(a.xcd) * WPB + (uint32_t)wave;
+    const uint32_t gl = pair * 2u + (upper ? 1u : 0u);
+    const uint32_t f = gl / n;
+    const uint32_t line = gl - f * n;
+    const bool live = f < a.nframes && !a.done[f];
+    if (__ballot(live) == 0ull) return;
+    const size_t fo = (size_t)f * n * n;
+    const bool first = ROWS && a.first;
+    const T *ch;
+    if constexpr (TOPO == kProduct) ch = static_cast<const T *>(ROWS ? a.llr_ch : a.ch_t) + fo;
+    else ch = static_cast<const T *>(ROWS ? a.ch_a : a.ch_t) + fo;
+    const T *la_in = static_cast<const T *>(ROWS ? a.la_rm : a.la_cm) + fo;
+    T *la_out = static_cast<T *>(ROWS ? a.la_cm : a.la_rm) + fo;
+    const uint32_t pos = LN::vn(line, hl, n);
+    double lam = 0.0;
+    if (live && hl < n) {
+        T c;
+        if (TOPO == kGldpc && first) c = static_cast<const T *>(a.llr_ch)[fo + pos];
+        else c = ch[line * n + hl];
+        lam = first ? (double)c : (double)c + (double)la_in[line * n + hl];
+        if (first) {
+            static_cast<T *>(a.ch_t)[fo + LN::cross(line, hl, n)] = c;
+            if (TOPO == kGldpc) static_cast<T *>(a.ch_a)[fo + line * n + hl] = c;
+        }
+    }
+    double lapp;
+    const WordStats st = decode_pair<STOP>(a.code, a.L, a.qcap, a.pstop, lam, !live, S, lapp, lane,
+                                           a.prof != nullptr);
+    if (live && a.prof && hl == 0) prof_add(a.prof, st);
+    const bool neg = live && hl < n && lapp < 0.0;
+    const uint64_t hm = __ballot(neg);
+    if (live && hl < n) {
+        la_out[LN::cross(line, hl, n)] = (T)(a.alpha * (lapp - lam));
+        if (a.llr_app) static_cast<T *>(a.llr_app)[fo + pos] = (T)lapp;
+        a.hard[fo + pos] = neg;
+    }
+    if (live && hl == 0) {
+        a.masks[((size_t)f * n + line) * 2 + 0] = upper ? (hm >> 32) : (hm & 0xffffffffull);
+        a.masks[((size_t)f * n + line) * 2 + 1] = 0ull;
+        atomicAdd(reinterpret_cast<unsigned long long *>(&a.sumq[f]), (unsigned long long)st.Q);
+        atomicMax(&a.halfmax[f], st.Q);
+    }
+}
+
 // One wave per frame after half-iteration h: every word of the last pass and every
 // word of the other family must have a zero syndrome.
 __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, int last) {
@@ -327,7 +385,7 @@ static void launch_component(const ComponentArgs &a, int ns, dim3 g, hipStream_t
 template <typename T, bool ROWS, bool STOP, int TOPO>
 static void launch_pass_t(const ProductArgs &a, int ns, dim3 g, hipStream_t st) {
     constexpr int W = kWavesPerBlock;
-    if (ns == 32) hipLaunchKernelGGL((k_product_pass<T, 32, ROWS, W, STOP, TOPO>), g, dim3(kWave * W), 0, st, a);
+    if (ns == 32) hipLaunchKernelGGL((k_product_pass_pair<T, ROWS, W, STOP, TOPO>), g, dim3(kWave * W), 0, st, a);
     else if (ns == 64) hipLaunchKernelGGL((k_product_pass<T, 64, ROWS, W, STOP, TOPO>), g, dim3(kWave * W), 0, st, a);
     else hipLaunchKernelGGL((k_product_pass<T, 128, ROWS, W, STOP, TOPO>), g, dim3(kWave * W), 0, st, a);
 }
@@ -405,7 +463,9 @@ static int decode_frames(int topo, const sogrand_code_t *code, const sogrand_par
     if (nframes > ((size_t)1 << 34) / ((size_t)n * n) || words >= ((size_t)1 << 31))
         return fail(SOGRAND_EINVAL, "nframes too large");
     const LaunchShape ls = launch_shape();
-    const size_t blocks = word_grid(words, ls);
+    const int ns = sort_width(n);
+    // words of up to 32 bits go two to a wave
+    const size_t blocks = word_grid(ns == 32 ? (words + 1) / 2 : words, ls);
     if (blocks > 0x7fffffffull) return fail(SOGRAND_EINVAL, "nframes too large for one launch");
     ProductArgs a;
     SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &a.code));
@@ -448,7 +508,6 @@ static int decode_frames(int topo, const sogrand_code_t *code, const sogrand_par
     a.early_stop = params->early_stop ? 1 : 0;
     a.prof = prof_counters(PK_PASS);
     a.xcd = ls.xcd;
-    const int ns = sort_width(n);
     const bool f64 = params->precision == SOGRAND_F64;
     int rc = SOGRAND_OK;
     {

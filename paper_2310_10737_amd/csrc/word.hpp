@@ -470,11 +470,13 @@ __device__ __forceinline__ void mark_found(WaveLds &S, int found, int lane) {
     wave_sync();
 }
 
-__device__ __forceinline__ double rho_at(const WaveLds &S, int r) {
+template <class LDS>
+__device__ __forceinline__ double rho_at(const LDS &S, int r) {
     return __longlong_as_double((long long)(((uint64_t)S.ent_r[r].y << 32) | S.ent_r[r].x));
 }
 
-__device__ __forceinline__ void put_rho(WaveLds &S, int r, double v) {
+template <class LDS>
+__device__ __forceinline__ void put_rho(LDS &S, int r, double v) {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
     S.ent_r[r].x = (uint32_t)u;
     S.ent_r[r].y = (uint32_t)(u >> 32);
