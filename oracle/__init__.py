@@ -153,3 +153,33 @@ def vnode(topo: int, n: int, fam: int, line: int, j: int) -> int:
     if v < 0:
         raise ValueError("oracle_vnode rejected its arguments")
     return v
+
+
+def forney_app(llr, found_z, n_found):
+    """Forney's approximation of the probability that each list codeword is correct (eq.
+    (missingterm), section "Background on SO"): its likelihood divided by the sum of the list's
+    likelihoods, the codewords outside the list counted as zero.
+
+    With BPSK over AWGN and lambda = 2r/sigma^2, the likelihood of the codeword y XOR z (y the hard
+    decision) over that of y is exp(-sum over i with z_i = 1 of |lambda_i|), which is what is summed
+    here.  llr (W, n), found_z (W, L, n) error patterns, n_found (W,).  Returns (W, L) float64, zero
+    past n_found; a word whose list is empty gets a row of NaN (the approximation needs a list).
+    """
+    a = np.abs(np.asarray(llr, dtype=np.float64))
+    z = np.asarray(found_z).astype(np.float64)
+    W, L, n = z.shape
+    nf = np.asarray(n_found).astype(np.int64)
+    valid = np.arange(L)[None, :] < nf[:, None]
+    loglik = -(z * a[:, None, :]).sum(axis=2)
+    top = np.where(valid, loglik, -np.inf).max(axis=1, keepdims=True)
+    with np.errstate(invalid="ignore"):
+        lik = np.where(valid, np.exp(loglik - top), 0.0)
+        return lik / lik.sum(axis=1, keepdims=True)
+
+
+def forney_list_bler(llr, found_z, n_found, lprime: int):
+    """Predicted probability that the transmitted codeword is not among the first lprime entries of
+    the list, by Forney's approximation over the whole list (the paper's Fig. 2 uses a list of 5 to
+    predict the error of the first 4): one minus their summed forney_app."""
+    p = forney_app(llr, found_z, n_found)
+    return np.maximum(1.0 - p[:, :lprime].sum(axis=1), 0.0)
