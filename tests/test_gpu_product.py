@@ -79,6 +79,29 @@ def test_product_parity(sg, nk, ebn0, frames, L, qcap, iters, f32):
           flush=True)
 
 
+def hamming15():
+    base = synth.ebch(16, 11)
+    return synth.code_from_generator("Hamming[15,11]", base.G[:, :15], base.info_pos)
+
+
+@pytest.mark.parametrize("which,ebn0,frames,qcap", [("hamming15", 2.5, 41, 1000), ("ebch8", 2.0, 50, 100)])
+@pytest.mark.parametrize("f32", [False, True])
+def test_product_parity_short_and_odd_codes(sg, which, ebn0, frames, qcap, f32):
+    """Words of at most 32 bits go two to a wave.  With the odd length 15 and an odd frame count,
+    pairs straddle frames and the last pair is half empty; Hamming[15,11] is also not an even code,
+    so every weight is queried and the whole mass is the class.  [8,4] fills an eighth of a wave."""
+    code = hamming15() if which == "hamming15" else synth.ebch(8, 4)
+    llr, cw, _ = synth.product_frames(code, ebn0, 91, np.arange(frames))
+    if f32:
+        llr = llr.astype(np.float32).astype(np.float64)
+    label = f"{code.name}^2 @{ebn0}dB f32={f32}"
+    print(f"[gpu] product {label} frames={frames}", flush=True)
+    g = gpu_product(sg, code, llr, 4, qcap, 4, f32=f32)
+    r = oracle.decode_product(code, llr, 4, qcap, 4, store_f32=f32, want_app=True, nthreads=8)
+    compare_product(g, r, f32, label)
+    assert r["half_iters"].max() > 2
+
+
 def test_product_without_early_stop(sg):
     code = synth.ebch(32, 26)
     llr, _, _ = synth.product_frames(code, 3.0, 9, np.arange(20))
