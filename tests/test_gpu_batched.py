@@ -32,9 +32,14 @@ def mixed(F, seed, lo=2.0, hi=4.0, nks=NK):
     return codes, cidx, eb, offs, llr, cw
 
 
+def handle(sg, code):
+    """The library's code object for a synth code, built from its H columns."""
+    return sg.Code.from_hcols(code.n, code.k, code.hcols)
+
+
 def run_batched(sg, codes, cidx, offs, llr, f32=False, sched=None, L=4, qcap=10000, iters=6):
     import torch
-    gcodes = [sg.Code.ebch(c.n, c.k) for c in codes]
+    gcodes = [handle(sg, c) for c in codes]
     dt = torch.float32 if f32 else torch.float64
     x = torch.from_numpy(llr).to(dtype=dt, device="cuda")
     fc = torch.from_numpy(cidx).cuda()
@@ -56,7 +61,7 @@ def run_plain_per_code(sg, codes, cidx, offs, llr, f32=False, L=4, qcap=10000, i
             continue
         nn = code.n * code.n
         frames = np.stack([llr[o:o + nn] for o in offs[sel]]).reshape(-1, code.n, code.n)
-        g = sg.Code.ebch(code.n, code.k)
+        g = handle(sg, code)
         out = sg.sogrand_decode_product(g, torch.from_numpy(frames).to(dtype=dt, device="cuda"), list_max=L,
                                         query_cap=qcap, max_iter=iters)
         torch.cuda.synchronize()
@@ -78,6 +83,29 @@ def test_batched_equals_plain_per_frame(sg, f32):
     for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
         np.testing.assert_array_equal(b[key].astype(np.int64), p[key].astype(np.int64), err_msg=key)
     np.testing.assert_array_equal(b["hard"], p["hard"])
+
+
+def test_batched_equals_plain_for_short_and_odd_codes(sg):
+    """Non-even Hamming[15,11] (odd length), [8,4] and [64,57] frames in one launch, equal to the
+    plain path per code and, on a sample, to the oracle."""
+    base = synth.ebch(16, 11)
+    codes = [synth.code_from_generator("Hamming[15,11]", base.G[:, :15], base.info_pos), synth.ebch(8, 4),
+             synth.ebch(64, 57)]
+    cidx, eb, offs, llr, cw = synth.mixed_product_frames(codes, 2.0, 3.5, 13, np.arange(300))
+    print("[gpu] batched, Hamming[15,11] + [8,4] + [64,57], 300 frames", flush=True)
+    b = run_batched(sg, codes, cidx, offs, llr, qcap=3000, iters=4)
+    p = run_plain_per_code(sg, codes, cidx, offs, llr, qcap=3000, iters=4)
+    assert int(b["status"][0]) == 0
+    for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
+        np.testing.assert_array_equal(b[key].astype(np.int64), p[key].astype(np.int64), err_msg=key)
+    np.testing.assert_array_equal(b["hard"], p["hard"])
+    code = codes[0]
+    pick = np.nonzero(cidx == 0)[0][:8]
+    nn = code.n * code.n
+    frames = np.stack([llr[o:o + nn] for o in offs[pick]]).reshape(-1, code.n, code.n)
+    r = oracle.decode_product(code, frames, 4, 3000, 4, nthreads=8)
+    np.testing.assert_array_equal(b["sum_queries"][pick].astype(np.int64), r["sum_queries"].astype(np.int64))
+    np.testing.assert_array_equal(b["half_iters"][pick].astype(np.int64), r["half_iters"].astype(np.int64))
 
 
 def test_batched_matches_oracle_on_sample(sg):
