@@ -180,7 +180,7 @@ int sogrand_decode_gldpc(const sogrand_code_t *code, const sogrand_params_t *par
                          uint64_t *sum_max_queries, void *stream);
 
 /* ------------------------------------------------------------------------ */
-/* Batched product decoding: mixed codes, one persistent launch             */
+/* Batched decoding: mixed codes, one persistent launch                     */
 /* ------------------------------------------------------------------------ */
 /* Launch shape of the persistent kernel.  Each workgroup (waves_per_group
    waves) keeps frames_per_group frames in flight and its waves take
@@ -213,6 +213,19 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
                            uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
                            uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
                            uint32_t *status, const sogrand_sched_t *sched, void *stream);
+
+/* The same persistent decoding of QC-GLDPC frames (performance-evaluation
+   section; frames laid out by variable node as for sogrand_decode_gldpc): frame
+   f's n x n block at frame_offset[f] holds variable node j*n + c at element
+   [j][c], and its code's n words of the first block row and n of the second
+   alternate as the rows and columns of a product frame do.  Every frame is
+   decoded exactly as by sogrand_decode_gldpc.  Arguments, outputs and errors as
+   for sogrand_decode_batched. */
+int sogrand_decode_batched_gldpc(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                                 size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
+                                 uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                                 uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
+                                 uint32_t *status, const sogrand_sched_t *sched, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of product-frame decode requests            */

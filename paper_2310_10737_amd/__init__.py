@@ -13,7 +13,7 @@ import os
 __all__ = [
     "SograndError", "Code", "params", "sched", "lib", "library_path", "profile_begin", "profile_end",
     "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_gldpc", "sogrand_decode_batched",
-    "pack_frames",
+    "sogrand_decode_batched_gldpc", "pack_frames",
     "Server", "sogrand_clock_ns", "SOGRAND_F64", "SOGRAND_F32",
 ]
 
@@ -28,7 +28,7 @@ EXPORTS = [
     "sogrand_last_error", "sogrand_version", "sogrand_params_default",
     "sogrand_code_create", "sogrand_code_create_ebch", "sogrand_code_info", "sogrand_code_destroy",
     "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_gldpc",
-    "sogrand_sched_default", "sogrand_decode_batched",
+    "sogrand_sched_default", "sogrand_decode_batched", "sogrand_decode_batched_gldpc",
     "sogrand_clock_ns", "sogrand_serve_create", "sogrand_serve_submit", "sogrand_serve_poll",
     "sogrand_serve_stats", "sogrand_serve_replay", "sogrand_serve_destroy",
     "sogrand_profile_begin", "sogrand_profile_end",
@@ -132,6 +132,7 @@ def lib():
     L.sogrand_sched_default.argtypes = [P]
     L.sogrand_sched_default.restype = None
     L.sogrand_decode_batched.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 9
+    L.sogrand_decode_batched_gldpc.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 9
     L.sogrand_clock_ns.restype = ctypes.c_uint64
     L.sogrand_serve_create.argtypes = [P, SZ, P]
     L.sogrand_serve_submit.argtypes = [P, P, P, ctypes.c_uint64, P]
@@ -344,6 +345,21 @@ def sogrand_decode_batched(codes, frame_code, frame_offset, llr, list_max=4, que
     tensor, float64 or float32).  Returns a dict with hard (flat uint8 like llr),
     success, half_iters, sum_queries, sum_max_queries and status.
     """
+    return _batched(lib().sogrand_decode_batched, codes, frame_code, frame_offset, llr, list_max, query_cap,
+                    max_iter, alpha, early_stop, sched_, outputs, stream, list_bler_stop)
+
+
+def sogrand_decode_batched_gldpc(codes, frame_code, frame_offset, llr, list_max=4, query_cap=1000, max_iter=20,
+                                 alpha=0.6, early_stop=True, sched_=None, outputs=None, stream=None,
+                                 list_bler_stop=0.0):
+    """sogrand_decode_batched for QC-GLDPC frames (laid out by variable node, as for
+    sogrand_decode_gldpc)."""
+    return _batched(lib().sogrand_decode_batched_gldpc, codes, frame_code, frame_offset, llr, list_max, query_cap,
+                    max_iter, alpha, early_stop, sched_, outputs, stream, list_bler_stop)
+
+
+def _batched(fn, codes, frame_code, frame_offset, llr, list_max, query_cap, max_iter, alpha, early_stop, sched_,
+             outputs, stream, list_bler_stop):
     import torch
     if not (llr.is_cuda and llr.is_contiguous() and llr.dim() == 1):
         raise ValueError("llr must be a contiguous 1-D CUDA tensor")
@@ -365,7 +381,7 @@ def sogrand_decode_batched(codes, frame_code, frame_offset, llr, list_max=4, que
     p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
                early_stop=early_stop, precision=_precision_of(llr), list_bler_stop=list_bler_stop)
     sc = sched_ if sched_ is not None else sched()
-    _check(lib().sogrand_decode_batched(
+    _check(fn(
         handles, len(codes), ctypes.byref(p), F, _ptr(frame_code), _ptr(frame_offset), llr.numel(),
         _ptr(llr), _ptr(out["hard"]), _ptr(out["success"]), _ptr(out["half_iters"]), _ptr(out["sum_queries"]),
         _ptr(out["sum_max_queries"]), _ptr(out["status"]), ctypes.byref(sc), _stream(stream)))

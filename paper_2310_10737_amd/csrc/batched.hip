@@ -1,5 +1,5 @@
-// Batched block-turbo decoding of product frames of mixed codes in one
-// persistent launch.
+// Batched block-turbo decoding of product or QC-GLDPC frames of mixed codes in
+// one persistent launch.
 //
 // Each workgroup owns up to `slots` frames at a time (frame slots in LDS).  Its
 // waves steal ranges of `chunk` lines of the current half-iteration of any of
@@ -26,6 +26,7 @@ struct CodeTable {
 struct BatchArgs {
     const DevCode *codes;           // [ncodes], in device memory
     int ncodes;
+    int topo;                       // kProduct or kGldpc: every frame of the batch
     int L;
     uint32_t qcap;
     double pstop;                   // list-BLER stop threshold, 0 = off
@@ -122,9 +123,13 @@ __device__ void slot_refill(const BatchArgs &a, SlotLds &sl) {
     }
 }
 
-// Validity of the frame's hard decision after a half-iteration: every line of
-// the last pass and every cross line has a zero syndrome.
-__device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, int lane) {
+// Validity of the frame's hard decision after half-iteration h: every line of
+// the last pass and every line of the other family has a zero syndrome.  The
+// masks hold the last pass's lines.  Bit l of the other family's word x is, for a
+// product code, bit x of line l; for a QC-GLDPC code, bit l of line (x + l) mod n
+// after a first-family pass and of line (x - l) mod n after a second-family pass
+// (both families take bit l from block l).
+__device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, int lane, int h, int topo) {
     const int n = sl.n;
     bool bad = false;
     for (int b = 0; b < 2; b++) {
@@ -137,16 +142,31 @@ __device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, 
             if (bit) s ^= c.hcol[i];
         }
         uint32_t t = 0;
-        for (int l = 0; l < n; l++) {
-            const uint64_t w = x < 64 ? sl.masks[l][0] : sl.masks[l][1];
-            if ((w >> (x & 63)) & 1ull) t ^= c.hcol[l];
+        if (topo == kProduct) {
+            for (int l = 0; l < n; l++) {
+                const uint64_t w = x < 64 ? sl.masks[l][0] : sl.masks[l][1];
+                if ((w >> (x & 63)) & 1ull) t ^= c.hcol[l];
+            }
+        } else {
+            const bool after_first = (h & 1) != 0;
+            for (int l = 0; l < n; l++) {
+                int src = after_first ? x + l : x - l;
+                if (src >= n) src -= n;
+                if (src < 0) src += n;
+                const uint64_t w = l < 64 ? sl.masks[src][0] : sl.masks[src][1];
+                if ((w >> (l & 63)) & 1ull) t ^= c.hcol[l];
+            }
         }
         bad |= (s != 0u) || (t != 0u);
     }
     return __ballot(bad) == 0ull;
 }
 
-// Decodes line `line` of the slot's frame in half-iteration h (rows for odd h).
+// Decodes line `line` of the slot's frame in half-iteration h: a word of the
+// first family (product rows, the first block row of a QC-GLDPC code) for odd h,
+// of the second otherwise.  Frame positions are variable nodes: bit i of a
+// product row is line*n + i, of a column i*n + line; bit i of a QC-GLDPC word is
+// i*n + line in the first block row and i*n + (line + i) mod n in the second.
 template <typename T, int NS, bool STOP>
 __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl, const DevCode &c,
                                                 const DevCode *cdev, int frame,
@@ -161,7 +181,13 @@ __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl,
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
-        pos[b] = rows ? line * n + i : i * n + line;
+        if (a.topo == kProduct) {
+            pos[b] = rows ? line * n + i : i * n + line;
+        } else {
+            int col = rows ? line : line + i;
+            if (col >= n) col -= n;
+            pos[b] = i * n + col;
+        }
         // the a-priori LLRs are zero in the first half-iteration
         lam[b] = i < n ? (double)ch[pos[b]] + (h > 1 ? (double)la[pos[b]] : 0.0) : 0.0;
     }
@@ -275,7 +301,7 @@ void k_batched(BatchArgs a) {
 
         // this wave finished the half-iteration
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const bool valid = slot_valid(sl, c, lane);
+        const bool valid = slot_valid(sl, c, lane, h, a.topo);
         if (lane == 0) {
             sl.summax += sl.halfmax;
             sl.halfmax = 0;
@@ -341,24 +367,11 @@ static int check_sched(const sogrand_sched_t *s) {
     return SOGRAND_OK;
 }
 
-}  // namespace sg
-
-extern "C" {
-
-void sogrand_sched_default(sogrand_sched_t *s) {
-    if (!s) return;
-    s->waves_per_group = 8;
-    s->frames_per_group = 2;
-    s->steal_chunk = 4;
-    s->groups_per_cu = 3;
-}
-
-int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
-                           size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
-                           uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
-                           uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
-                           uint32_t *status, const sogrand_sched_t *sched, void *stream) {
-    using namespace sg;
+static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                          size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
+                          uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                          uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
+                          uint32_t *status, const sogrand_sched_t *sched, void *stream) {
     SG_TRY(check_params(params));
     if (!codes || ncodes < 1 || ncodes > kMaxCodes) return fail(SOGRAND_EINVAL, "ncodes outside 1..%d", kMaxCodes);
     if (nframes == 0) return SOGRAND_OK;
@@ -392,6 +405,7 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
     if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
         return fail(SOGRAND_ENOMEM, "work buffer allocation of %zu bytes failed", total);
     a.ncodes = ncodes;
+    a.topo = topo;
     a.L = params->list_max;
     a.qcap = params->query_cap;
     a.pstop = params->list_bler_stop;
@@ -428,6 +442,38 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
     if (hipGetLastError() != hipSuccess) rc = fail(SOGRAND_EDEVICE, "batched kernel launch failed");
     (void)hipFreeAsync(ws, st);
     return rc;
+}
+
+}  // namespace sg
+
+extern "C" {
+
+void sogrand_sched_default(sogrand_sched_t *s) {
+    if (!s) return;
+    s->waves_per_group = 8;
+    s->frames_per_group = 2;
+    s->steal_chunk = 4;
+    s->groups_per_cu = 3;
+}
+
+int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                           size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
+                           uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                           uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
+                           uint32_t *status, const sogrand_sched_t *sched, void *stream) {
+    return sg::decode_batched(sg::kProduct, codes, ncodes, params, nframes, frame_code, frame_offset, llr_len,
+                              llr_ch, hard, success, half_iters, sum_queries, sum_max_queries, status, sched,
+                              stream);
+}
+
+int sogrand_decode_batched_gldpc(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                                 size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
+                                 uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                                 uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
+                                 uint32_t *status, const sogrand_sched_t *sched, void *stream) {
+    return sg::decode_batched(sg::kGldpc, codes, ncodes, params, nframes, frame_code, frame_offset, llr_len,
+                              llr_ch, hard, success, half_iters, sum_queries, sum_max_queries, status, sched,
+                              stream);
 }
 
 }  // extern "C"

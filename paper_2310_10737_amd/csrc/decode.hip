@@ -139,7 +139,6 @@ __global__ __launch_bounds__(kBlock) void k_product_init(ProductArgs a) {
 // i): variable node j*n + c is column c of block j; word `line` of the first block
 // row takes its bit j from variable node j*n + line, of the second from
 // j*n + (line + j) mod n.
-constexpr int kProduct = 0, kGldpc = 1;
 
 template <int TOPO, bool FIRST_FAMILY>
 struct Lines {

@@ -46,6 +46,11 @@ struct Schedule {
     uint32_t *wmax[2] = {nullptr, nullptr};
 };
 
+// Frame topology: a product code (rows and columns) or a QC-GLDPC code (two block
+// rows of circulants); which variable nodes form each component word is described
+// where the kernels map words to frame positions.
+constexpr int kProduct = 0, kGldpc = 1;
+
 // Device-side view of a code and its schedule, passed by value to kernels.
 struct DevCode {
     const uint32_t *hcol;   // [n] parity-check column of each bit

@@ -96,3 +96,67 @@ def test_full_size_gldpc_workload_sampled(sg):
         for key in ("success", "half_iters", "sum_queries", "sum_max_queries", "hard"):
             np.testing.assert_array_equal(got[key].astype(np.int64), ref[key].astype(np.int64), err_msg=key)
         del x, out
+
+
+def batched_gldpc_inputs(seed, per_code):
+    """QC-GLDPC frames of [32,26] and [16,11] interleaved in one flat buffer."""
+    codes = [synth.ebch(32, 26), synth.ebch(16, 11)]
+    parts, cidx = [], []
+    for c, (code, (F, ebn0)) in enumerate(zip(codes, per_code)):
+        llr, _, _ = synth.gldpc_frames(synth.gldpc(code), ebn0, seed + c, np.arange(F))
+        parts.append(llr)
+        cidx.append(np.full(F, c, dtype=np.uint8))
+    order = np.argsort(np.concatenate([np.arange(p.shape[0]) * len(codes) + c for c, p in enumerate(parts)]),
+                       kind="stable")
+    frames = [f for p in parts for f in p]
+    cidx = np.concatenate(cidx)[order]
+    frames = [frames[i] for i in order]
+    sizes = np.array([f.size for f in frames], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = np.concatenate([f.reshape(-1) for f in frames])
+    return codes, cidx, offs, flat, frames
+
+
+@pytest.mark.parametrize("f32,stop", [(False, 0.0), (True, 1e-5)])
+def test_batched_gldpc_equals_plain(sg, f32, stop):
+    """The persistent form decodes every QC-GLDPC frame exactly as the plain path does, frames of two
+    codes in one launch, under two launch shapes."""
+    import torch
+    codes, cidx, offs, flat, frames = batched_gldpc_inputs(81, [(150, 2.25), (90, 2.0)])
+    dt = torch.float32 if f32 else torch.float64
+    gcodes = [sg.Code.from_hcols(c.n, c.k, c.hcols) for c in codes]
+    x = torch.from_numpy(flat).to(dtype=dt, device="cuda")
+    fc = torch.from_numpy(cidx).cuda()
+    fo = torch.from_numpy(offs).cuda()
+    print(f"[gpu] batched gldpc f32={f32} stop={stop} frames={len(frames)}", flush=True)
+    outs = []
+    for shape in (None, sg.sched(4, 3, 2, 2)):
+        o = sg.sogrand_decode_batched_gldpc(gcodes, fc, fo, x, list_max=4, query_cap=5000, max_iter=20, alpha=0.6,
+                                            list_bler_stop=stop, sched_=shape)
+        torch.cuda.synchronize()
+        assert int(o["status"][0]) == 0
+        outs.append({k: v.cpu().numpy() for k, v in o.items()})
+    for key in ("success", "half_iters", "sum_queries", "sum_max_queries", "hard"):
+        np.testing.assert_array_equal(outs[1][key], outs[0][key], err_msg=key)
+    b = outs[0]
+    for c, code in enumerate(codes):
+        sel = np.nonzero(cidx == c)[0]
+        llr = np.stack([frames[i] for i in sel])
+        p = sg.sogrand_decode_gldpc(gcodes[c], torch.from_numpy(llr).to(dtype=dt, device="cuda").contiguous(),
+                                    list_max=4, query_cap=5000, max_iter=20, alpha=0.6, list_bler_stop=stop)
+        torch.cuda.synchronize()
+        p = {k: v.cpu().numpy() for k, v in p.items() if v is not None}
+        for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
+            np.testing.assert_array_equal(b[key][sel].astype(np.int64), p[key].astype(np.int64), err_msg=key)
+        nn = code.n * code.n
+        hard = np.stack([b["hard"][offs[i]:offs[i] + nn] for i in sel]).reshape(p["hard"].shape)
+        np.testing.assert_array_equal(hard, p["hard"])
+        assert p["half_iters"].max() > 4
+    # a sample against the oracle
+    pick = np.nonzero(cidx == 0)[0][:10]
+    llr = np.stack([frames[i] for i in pick])
+    if f32:
+        llr = llr.astype(np.float32).astype(np.float64)
+    r = oracle.decode_gldpc(codes[0], llr, 4, 5000, 20, 0.6, store_f32=f32, pstop=stop, nthreads=8)
+    for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
+        np.testing.assert_array_equal(b[key][pick].astype(np.int64), r[key].astype(np.int64), err_msg=key)
