@@ -21,7 +21,8 @@ Other workloads, each printing its own line:
   gldpc      the (1024, 640) QC-GLDPC code with [32,26] eBCH check nodes at
              Eb/N0 = 2.0, 2.25 and 2.5 dB, 10^4 frames each (seeds 11-13),
              L = 4, cap 10^4, alpha = 0.6, 20 iterations, list-BLER stop 10^-5
-             (the paper's GLDPC settings); plain FP64 and FP32 storage.
+             (the paper's GLDPC settings); plain FP64 and FP32 storage and the
+             batched form with FP32 storage.
   rician     [64,57]^2 over block Rician fading (N_c = 256, t = 8, K = 6) with
              Gray QPSK and a random interleaver, Eb/N0 = 6, 8, 10 dB, 10^4
              frames each (seeds 21-23), L = 4, cap 10^4, alpha = 0.5, 20
@@ -288,10 +289,13 @@ def load_frames(np, torch, make, snrs, F, dev):
     return llr_all, cw_all, x64, x64.float()
 
 
-def plain_or_batched(sg, torch, gcode, total, n, dev, x64, x32, iters, stop, alpha=0.5, decode=None, sched_of=None):
+def plain_or_batched(sg, torch, gcode, total, n, dev, x64, x32, iters, stop, alpha=0.5, decode=None, sched_of=None,
+                     batched=None):
     """(out_of, make_step) for the forms plain_f64/f32 (decode: sogrand_decode_product or
-    sogrand_decode_gldpc) and batched_f64/f32 (product codes only)."""
+    sogrand_decode_gldpc) and batched_f64/f32 (batched: sogrand_decode_batched or
+    sogrand_decode_batched_gldpc)."""
     decode = decode or sg.sogrand_decode_product
+    batched = batched or sg.sogrand_decode_batched
     fcode = torch.zeros(total, dtype=torch.uint8, device=dev)
     foff = torch.arange(total, dtype=torch.int64, device=dev) * (n * n)
 
@@ -309,9 +313,8 @@ def plain_or_batched(sg, torch, gcode, total, n, dev, x64, x32, iters, stop, alp
                                    list_bler_stop=stop)), None
         if form.startswith("batched"):
             sc = sched_of(x) if sched_of else sg.sched()
-            return (lambda: sg.sogrand_decode_batched([gcode], fcode, foff, x.view(-1), list_max=L, query_cap=QCAP,
-                                                      max_iter=iters, alpha=alpha, sched_=sc, outputs=out,
-                                                      list_bler_stop=stop)), sc
+            return (lambda: batched([gcode], fcode, foff, x.view(-1), list_max=L, query_cap=QCAP, max_iter=iters,
+                                    alpha=alpha, sched_=sc, outputs=out, list_bler_stop=stop)), sc
         raise SystemExit(f"unknown form {form}")
     return out_of, make_step, fcode, foff
 
@@ -560,8 +563,9 @@ def bench_gldpc(args, sg, np, torch, synth):
         np, torch, lambda snr, seed: synth.gldpc_frames(g, snr, seed, np.arange(F))[:2], GLDPC_SNRS, F, dev)
     total = x64.shape[0]
     out_of, make_step, _, _ = plain_or_batched(sg, torch, gcode, total, n, dev, x64, x32, GLDPC_ITERS, GLDPC_STOP,
-                                               alpha=GLDPC_ALPHA, decode=sg.sogrand_decode_gldpc)
-    names = [f for f in args.forms.split(",") if f.startswith("plain")]
+                                               alpha=GLDPC_ALPHA, decode=sg.sogrand_decode_gldpc,
+                                               batched=sg.sogrand_decode_batched_gldpc)
+    names = [f for f in args.forms.split(",") if f in ("plain_f64", "plain_f32", "batched_f32")]
     forms = time_forms(args, sg, names, make_step, out_of, cw_all, GLDPC_SNRS, F, n, total * g.dim)
     best_name, best = choose_form(forms)
     roof = dominant_roofline(args, best_name, best, n)
