@@ -11,7 +11,7 @@
 // coordination is workgroup-local, so no cache maintenance across XCDs is
 // needed; frames are independent, so the result of a frame does not depend on
 // the schedule.
-#include "word.hpp"
+#include "pair.hpp"
 
 namespace sg {
 
@@ -212,9 +212,57 @@ __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl,
     return st;
 }
 
-// NSMAX: 64 when every code of the batch has n <= 64, else 128; the narrower
-// instantiation compiles without the wide-word path and keeps more waves resident
-// (six per SIMD, 80 registers, no spills; measured faster than five or seven).
+// Decodes lines `line` (lanes 0-31) and `line + 1` (lanes 32-63) of the slot's frame
+// in half-iteration h, two words of up to 32 bits per wave (decode_pair), at the
+// same frame positions as batch_line.  A half whose line is not below `last` takes
+// part without testing patterns.
+template <typename T, bool STOP>
+__device__ __forceinline__ WordStats batch_pair(const BatchArgs &a, SlotLds &sl, const DevCode &c, int frame, int h,
+                                                int line, int last, T *la, PairLds *P, int lane) {
+    const int n = c.n;
+    const bool rows = (h & 1) != 0;
+    const int hl = lane & 31;
+    const bool upper = lane >= 32;
+    const int ln = line + (upper ? 1 : 0);
+    const bool live = ln < last;
+    const uint64_t off = load_uniform(a.frame_offset + frame);
+    const T *ch = static_cast<const T *>(a.llr_ch) + off;
+    int pos;
+    if (a.topo == kProduct) {
+        pos = rows ? ln * n + hl : hl * n + ln;
+    } else {
+        int col = rows ? ln : ln + hl;
+        if (col >= n) col -= n;
+        pos = hl * n + col;
+    }
+    const bool v = live && hl < n;
+    const double lam = v ? (double)ch[pos] + (h > 1 ? (double)la[pos] : 0.0) : 0.0;
+    double lapp;
+    const WordStats st = decode_pair<STOP, true>(c, a.L, a.qcap, a.pstop, lam, !live, P[upper ? 1 : 0], lapp, lane,
+                                                 a.prof != nullptr);
+    const bool neg = v && lapp < 0.0;
+    const uint64_t hm = __ballot(neg);
+    if (v) {
+        la[pos] = (T)(a.alpha * (lapp - lam));
+        a.hard[off + pos] = neg;
+    }
+    if (live && hl == 0) {
+        sl.masks[ln][0] = upper ? (hm >> 32) : (hm & 0xffffffffull);
+        sl.masks[ln][1] = 0ull;
+    }
+    return st;
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// NSMAX: 32 when every code of the batch has n <= 32 (two words per wave), 64 when
+// n <= 64, else 128; the narrower instantiations compile without the wider paths
+// and keep more waves resident (six per SIMD, 80 registers, no spills; measured
+// faster than five or seven).
 template <typename T, int WPB, int NSMAX, bool STOP>
 __global__ __launch_bounds__(kWave * WPB) __attribute__((amdgpu_waves_per_eu(NSMAX > 64 ? 4 : 6)))
 void k_batched(BatchArgs a) {
@@ -280,13 +328,32 @@ void k_batched(BatchArgs a) {
         T *la = la_base + (size_t)sel * a.nmax * a.nmax;
         unsigned long long qsum = 0;
         uint32_t qmax = 0;
-        for (int line = first; line < last; line++) {
-            WordStats st;
-            if (NSMAX == 64 || n <= 64) st = batch_line<T, 64, STOP>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
-            else st = batch_line<T, 128, STOP>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
-            if (a.prof && lane == 0) prof_add(a.prof, st);
-            qsum += st.Q;
-            qmax = st.Q > qmax ? st.Q : qmax;
+        if constexpr (NSMAX == 32) {
+            static_assert(2 * sizeof(PairLds) <= sizeof(WaveLds), "two pair scratches per wave");
+            PairLds *P = reinterpret_cast<PairLds *>(&S);
+            for (int line = first; line < last; line += 2) {
+                const WordStats st = batch_pair<T, STOP>(a, sl, c, frame, h, line, last, la, P, lane);
+                const bool live = line + (lane >= 32 ? 1 : 0) < last;
+                if (live && a.prof && (lane & 31) == 0) prof_add(a.prof, st);
+                if (live) {
+                    qsum += st.Q;
+                    qmax = st.Q > qmax ? st.Q : qmax;
+                }
+            }
+            // the two halves' sums, for lane 0 to report
+            qsum = readlane_u64(qsum, 0) + readlane_u64(qsum, 32);
+            const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)qmax, 0);
+            const uint32_t m1 = (uint32_t)__builtin_amdgcn_readlane((int)qmax, 32);
+            qmax = m0 > m1 ? m0 : m1;
+        } else {
+            for (int line = first; line < last; line++) {
+                WordStats st;
+                if (NSMAX == 64 || n <= 64) st = batch_line<T, 64, STOP>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
+                else st = batch_line<T, 128, STOP>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
+                if (a.prof && lane == 0) prof_add(a.prof, st);
+                qsum += st.Q;
+                qmax = st.Q > qmax ? st.Q : qmax;
+            }
         }
         // the lines' global writes complete before they are counted as done
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -348,7 +415,10 @@ static void launch_batched_n(const BatchArgs &a, int wpb, int grid, hipStream_t 
 template <typename T>
 static void launch_batched(const BatchArgs &a, int wpb, int grid, hipStream_t st) {
     const bool stop = a.pstop > 0.0;
-    if (a.nmax <= 64) {
+    if (a.nmax <= 32) {
+        if (stop) launch_batched_n<T, 32, true>(a, wpb, grid, st);
+        else launch_batched_n<T, 32, false>(a, wpb, grid, st);
+    } else if (a.nmax <= 64) {
         if (stop) launch_batched_n<T, 64, true>(a, wpb, grid, st);
         else launch_batched_n<T, 64, false>(a, wpb, grid, st);
     } else {

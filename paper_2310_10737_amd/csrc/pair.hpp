@@ -91,8 +91,9 @@ __device__ __forceinline__ void mark_found_half(PairLds &S, int found, int hl) {
 // Decodes the lane's word (bit lane % 32 held in lam; the word's scratch is S, one per
 // half).  skip: this half holds no word (its lanes take part in the wave's steps, test
 // no pattern and their outputs are meaningless).  Returns the word's statistics in
-// every lane of its half and its APP LLR in lapp.
-template <bool STOP>
+// every lane of its half and its APP LLR in lapp.  TABLE: the elementary functions
+// read their coefficients through a pointer, as in decode_word (persistent kernels).
+template <bool STOP, bool TABLE = false>
 __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32_t qcap, double pstop, double lam,
                                                  bool skip, PairLds &S, double &lapp, int lane, bool count) {
     const int n = c.n;
@@ -107,7 +108,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
     const uint32_t s0 = half_xor(ybit ? c.hcol[hl] : 0u);
     const double a = fabs(lam);
     const uint64_t key = valid ? (uint64_t)__double_as_longlong(a) : ~0ull;
-    const double rho = valid ? exp_neg<false>(a) : 0.0;
+    const double rho = valid ? exp_neg<TABLE>(a) : 0.0;
 
     // 2. ranks by counting smaller keys of the same word, ties by bit index
     S.key_b[hl] = key;
@@ -318,7 +319,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
     const double sy = pnf, sf = pnf * rho;
     N0 = fma(opr, N0, ybit ? sf : sy);
     N1 = fma(opr, N1, ybit ? sy : sf);
-    double la = log_ratio<false>(N0, N1);
+    double la = log_ratio<TABLE>(N0, N1);
     if (!(la <= 1000.0)) la = 1000.0;
     if (!(la >= -1000.0)) la = -1000.0;
     lapp = la;

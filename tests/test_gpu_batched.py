@@ -85,14 +85,17 @@ def test_batched_equals_plain_per_frame(sg, f32):
     np.testing.assert_array_equal(b["hard"], p["hard"])
 
 
-def test_batched_equals_plain_for_short_and_odd_codes(sg):
-    """Non-even Hamming[15,11] (odd length), [8,4] and [64,57] frames in one launch, equal to the
-    plain path per code and, on a sample, to the oracle."""
+@pytest.mark.parametrize("with64", [True, False])
+def test_batched_equals_plain_for_short_and_odd_codes(sg, with64):
+    """Non-even Hamming[15,11] (odd length) and [8,4] frames, with [64,57] frames (one word per wave)
+    or without them (two words per wave), in one launch: equal to the plain path per code and, on a
+    sample, to the oracle."""
     base = synth.ebch(16, 11)
-    codes = [synth.code_from_generator("Hamming[15,11]", base.G[:, :15], base.info_pos), synth.ebch(8, 4),
-             synth.ebch(64, 57)]
+    codes = [synth.code_from_generator("Hamming[15,11]", base.G[:, :15], base.info_pos), synth.ebch(8, 4)]
+    if with64:
+        codes.append(synth.ebch(64, 57))
     cidx, eb, offs, llr, cw = synth.mixed_product_frames(codes, 2.0, 3.5, 13, np.arange(300))
-    print("[gpu] batched, Hamming[15,11] + [8,4] + [64,57], 300 frames", flush=True)
+    print(f"[gpu] batched, Hamming[15,11] + [8,4]{' + [64,57]' if with64 else ''}, 300 frames", flush=True)
     b = run_batched(sg, codes, cidx, offs, llr, qcap=3000, iters=4)
     p = run_plain_per_code(sg, codes, cidx, offs, llr, qcap=3000, iters=4)
     assert int(b["status"][0]) == 0
