@@ -14,7 +14,7 @@ __all__ = [
     "SograndError", "Code", "params", "sched", "lib", "library_path", "profile_begin", "profile_end",
     "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_gldpc", "sogrand_decode_batched",
     "sogrand_decode_batched_gldpc", "pack_frames",
-    "Server", "sogrand_clock_ns", "SOGRAND_F64", "SOGRAND_F32",
+    "Server", "sogrand_clock_ns", "measure_valu_rate", "SOGRAND_F64", "SOGRAND_F32",
 ]
 
 SOGRAND_F64 = 0
@@ -31,7 +31,7 @@ EXPORTS = [
     "sogrand_sched_default", "sogrand_decode_batched", "sogrand_decode_batched_gldpc",
     "sogrand_clock_ns", "sogrand_serve_create", "sogrand_serve_submit", "sogrand_serve_poll",
     "sogrand_serve_stats", "sogrand_serve_replay", "sogrand_serve_destroy",
-    "sogrand_profile_begin", "sogrand_profile_end",
+    "sogrand_profile_begin", "sogrand_profile_end", "sogrand_measure_valu_rate",
 ]
 
 SOGRAND_EAGAIN = -4
@@ -142,6 +142,7 @@ def lib():
     L.sogrand_serve_destroy.argtypes = [P]
     L.sogrand_profile_begin.argtypes = [I]
     L.sogrand_profile_end.argtypes = [P, I, P]
+    L.sogrand_measure_valu_rate.argtypes = [P, P, P]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -386,6 +387,14 @@ def _batched(fn, codes, frame_code, frame_offset, llr, list_max, query_cap, max_
         _ptr(llr), _ptr(out["hard"]), _ptr(out["success"]), _ptr(out["half_iters"]), _ptr(out["sum_queries"]),
         _ptr(out["sum_max_queries"]), _ptr(out["status"]), ctypes.byref(sc), _stream(stream)))
     return out
+
+
+def measure_valu_rate(stream=None) -> float:
+    """The device's measured VALU issue rate in lane-operations per second (integer XOR/ADD
+    chains on every SIMD; the denominator of the ALU roofline)."""
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    _check(lib().sogrand_measure_valu_rate(ctypes.byref(rate), ctypes.byref(ms), _stream(stream)))
+    return rate.value
 
 
 def sogrand_clock_ns() -> int:

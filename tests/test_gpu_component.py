@@ -86,6 +86,17 @@ def test_edge_cases(sg):
         run_pair(sg, c64, llr, 4, 500, label=f"ragged {W}")
 
 
+@pytest.mark.parametrize("nk", [(32, 26), (64, 57), (128, 120)])
+def test_nearly_equal_magnitudes(sg, nk):
+    """Magnitudes on a grid of 0.5, some moved by less than binary32 resolution: equal binary32
+    keys whose binary64 values differ must be ranked by the binary64 values."""
+    code = synth.ebch(*nk)
+    llr = np.round(synth.component_words(code, 2.0, 9, np.arange(60))[0] * 2) / 2
+    nudge = np.random.default_rng(2).integers(0, 4, size=llr.shape) * 2.0 ** -41
+    llr = llr + np.where(llr < 0, -1.0, 1.0) * nudge
+    run_pair(sg, code, llr, 4, 3000, label=f"{code.name} near-equal magnitudes")
+
+
 def test_empty_batch_is_a_no_op(sg):
     import torch
     code = sg.Code.ebch(32, 26)

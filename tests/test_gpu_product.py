@@ -102,6 +102,31 @@ def test_product_parity_short_and_odd_codes(sg, which, ebn0, frames, qcap, f32):
     assert r["half_iters"].max() > 2
 
 
+@pytest.mark.parametrize("nk", [(32, 26), (64, 57)])
+def test_product_parity_with_equal_and_nearly_equal_magnitudes(sg, nk):
+    """Channel LLRs on a grid of 0.5 (many equal magnitudes, zeros of both signs), some moved by
+    less than binary32 resolution, in frames that stop after the first row pass: the ranks must
+    follow the binary64 magnitudes, ties by bit index.  (Later half-iterations add a-priori LLRs
+    whose last bits differ between the two implementations; on such a grid, magnitudes that are
+    equal on one side can then differ by an ulp on the other, and the tie rule would order them
+    differently.  With unquantised channel noise such coincidences have no measurable chance.)"""
+    code = synth.ebch(*nk)
+    llr, _, _ = synth.product_frames(code, 6.0, 5, np.arange(40))
+    llr = np.round(llr * 2) / 2
+    llr[0, 0, :] = 0.0
+    llr[1, 0, :] = -0.0
+    nudge = np.random.default_rng(1).integers(0, 3, size=llr.shape) * 2.0 ** -40   # below binary32 resolution
+    llr = llr + np.sign(llr) * nudge
+    r = oracle.decode_product(code, llr, 4, 3000, 4, want_app=True, nthreads=8)
+    one = np.nonzero(r["half_iters"] == 1)[0]
+    assert one.size >= 30
+    llr = llr[one]
+    r = {k: v[one] for k, v in r.items() if v is not None}
+    print(f"[gpu] product ties {code.name}^2, {one.size} frames", flush=True)
+    g = gpu_product(sg, code, llr, 4, 3000, 4)
+    compare_product(g, r, label=f"ties {code.name}")
+
+
 def test_product_without_early_stop(sg):
     code = synth.ebch(32, 26)
     llr, _, _ = synth.product_frames(code, 3.0, 9, np.arange(20))
