@@ -129,7 +129,8 @@ __device__ void slot_refill(const BatchArgs &a, SlotLds &sl) {
 // product code, bit x of line l; for a QC-GLDPC code, bit l of line (x + l) mod n
 // after a first-family pass and of line (x - l) mod n after a second-family pass
 // (both families take bit l from block l).
-__device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, int lane, int h, int topo) {
+template <int TOPO>
+__device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, int lane, int h) {
     const int n = sl.n;
     bool bad = false;
     for (int b = 0; b < 2; b++) {
@@ -142,7 +143,7 @@ __device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, 
             if (bit) s ^= c.hcol[i];
         }
         uint32_t t = 0;
-        if (topo == kProduct) {
+        if constexpr (TOPO == kProduct) {
             for (int l = 0; l < n; l++) {
                 const uint64_t w = x < 64 ? sl.masks[l][0] : sl.masks[l][1];
                 if ((w >> (x & 63)) & 1ull) t ^= c.hcol[l];
@@ -167,7 +168,7 @@ __device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, 
 // of the second otherwise.  Frame positions are variable nodes: bit i of a
 // product row is line*n + i, of a column i*n + line; bit i of a QC-GLDPC word is
 // i*n + line in the first block row and i*n + (line + i) mod n in the second.
-template <typename T, int NS, bool STOP>
+template <typename T, int NS, bool STOP, int TOPO>
 __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl, const DevCode &c,
                                                 const DevCode *cdev, int frame,
                                                 int h, int line, T *la, WaveLds &S, int lane) {
@@ -181,7 +182,7 @@ __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl,
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
-        if (a.topo == kProduct) {
+        if constexpr (TOPO == kProduct) {
             pos[b] = rows ? line * n + i : i * n + line;
         } else {
             int col = rows ? line : line + i;
@@ -216,7 +217,7 @@ __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl,
 // in half-iteration h, two words of up to 32 bits per wave (decode_pair), at the
 // same frame positions as batch_line.  A half whose line is not below `last` takes
 // part without testing patterns.
-template <typename T, bool STOP>
+template <typename T, bool STOP, int TOPO>
 __device__ __forceinline__ WordStats batch_pair(const BatchArgs &a, SlotLds &sl, const DevCode &c, int frame, int h,
                                                 int line, int last, T *la, PairLds *P, int lane) {
     const int n = c.n;
@@ -228,7 +229,7 @@ __device__ __forceinline__ WordStats batch_pair(const BatchArgs &a, SlotLds &sl,
     const uint64_t off = load_uniform(a.frame_offset + frame);
     const T *ch = static_cast<const T *>(a.llr_ch) + off;
     int pos;
-    if (a.topo == kProduct) {
+    if constexpr (TOPO == kProduct) {
         pos = rows ? ln * n + hl : hl * n + ln;
     } else {
         int col = rows ? ln : ln + hl;
@@ -263,7 +264,7 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v,
 // n <= 64, else 128; the narrower instantiations compile without the wider paths
 // and keep more waves resident (six per SIMD, 80 registers, no spills; measured
 // faster than five or seven).
-template <typename T, int WPB, int NSMAX, bool STOP>
+template <typename T, int WPB, int NSMAX, bool STOP, int TOPO>
 __global__ __launch_bounds__(kWave * WPB) __attribute__((amdgpu_waves_per_eu(NSMAX > 64 ? 4 : 6)))
 void k_batched(BatchArgs a) {
     __shared__ WaveLds wl[WPB];
@@ -332,7 +333,7 @@ void k_batched(BatchArgs a) {
             static_assert(2 * sizeof(PairLds) <= sizeof(WaveLds), "two pair scratches per wave");
             PairLds *P = reinterpret_cast<PairLds *>(&S);
             for (int line = first; line < last; line += 2) {
-                const WordStats st = batch_pair<T, STOP>(a, sl, c, frame, h, line, last, la, P, lane);
+                const WordStats st = batch_pair<T, STOP, TOPO>(a, sl, c, frame, h, line, last, la, P, lane);
                 const bool live = line + (lane >= 32 ? 1 : 0) < last;
                 if (live && a.prof && (lane & 31) == 0) prof_add(a.prof, st);
                 if (live) {
@@ -348,8 +349,8 @@ void k_batched(BatchArgs a) {
         } else {
             for (int line = first; line < last; line++) {
                 WordStats st;
-                if (NSMAX == 64 || n <= 64) st = batch_line<T, 64, STOP>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
-                else st = batch_line<T, 128, STOP>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
+                if (NSMAX == 64 || n <= 64) st = batch_line<T, 64, STOP, TOPO>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
+                else st = batch_line<T, 128, STOP, TOPO>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
                 if (a.prof && lane == 0) prof_add(a.prof, st);
                 qsum += st.Q;
                 qmax = st.Q > qmax ? st.Q : qmax;
@@ -368,7 +369,7 @@ void k_batched(BatchArgs a) {
 
         // this wave finished the half-iteration
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const bool valid = slot_valid(sl, c, lane, h, a.topo);
+        const bool valid = slot_valid<TOPO>(sl, c, lane, h);
         if (lane == 0) {
             sl.summax += sl.halfmax;
             sl.halfmax = 0;
@@ -401,7 +402,10 @@ __global__ void k_batched_status(const uint32_t *error, uint32_t *status) {
 template <typename T, int WPB, int NSMAX, bool STOP>
 static void launch_batched_w(const BatchArgs &a, int grid, hipStream_t st) {
     const size_t dyn = sizeof(SlotLds) * a.slots;
-    hipLaunchKernelGGL((k_batched<T, WPB, NSMAX, STOP>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
+    if (a.topo == kProduct)
+        hipLaunchKernelGGL((k_batched<T, WPB, NSMAX, STOP, kProduct>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
+    else
+        hipLaunchKernelGGL((k_batched<T, WPB, NSMAX, STOP, kGldpc>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
 }
 
 template <typename T, int NSMAX, bool STOP>
