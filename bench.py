@@ -51,7 +51,7 @@ SNRS = ((2.5, 1), (3.0, 2), (3.5, 3))
 N, K, L, QCAP, ITERS = 64, 57, 4, 10000, 6
 MIX_CODES = ((32, 26), (64, 57), (128, 120))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "product_64x57_hbm_bytes.md")
-KERNEL_SOURCES = ("word.hpp", "decode.hip", "batched.hip", "internal.hpp")
+KERNEL_SOURCES = ("word.hpp", "pair.hpp", "decode.hip", "batched.hip", "internal.hpp")
 
 
 def ops_per_word(n: int, lst: int) -> int:
