@@ -97,6 +97,31 @@ def test_served_results_equal_alone(sg, f32):
             assert g["t_submit_ns"] <= g["t_admit_ns"] <= g["t_done_ns"]
 
 
+def test_served_short_and_odd_codes(sg):
+    """Requests of the non-even odd-length Hamming[15,11], of [8,4] and of [64,57] in one server:
+    each result equals the frame decoded alone."""
+    base = synth.ebch(16, 11)
+    codes = [synth.code_from_generator("Hamming[15,11]", base.G[:, :15], base.info_pos), synth.ebch(8, 4),
+             synth.ebch(64, 57)]
+    F, L, qcap, iters = 60, 4, 2000, 4
+    cidx, eb, offs, llr, cw = synth.mixed_product_frames(codes, 2.0, 3.5, 17, np.arange(F))
+    frames = [(int(cidx[f]), llr[offs[f]:offs[f] + codes[cidx[f]].n ** 2].reshape(codes[cidx[f]].n, -1))
+              for f in range(F)]
+    print(f"[gpu] serve {F} frames of Hamming[15,11], [8,4], [64,57]", flush=True)
+    gcodes = [sg.Code.from_hcols(c.n, c.k, c.hcols) for c in codes]
+    with sg.Server(64 << 20, list_max=L, query_cap=qcap, max_iter=iters, precision=sg.SOGRAND_F32) as srv:
+        got = serve_all(sg, srv, gcodes, frames, True)
+    assert len(got) == F
+    for ci, code in enumerate(codes):
+        sel = [f for f in range(F) if frames[f][0] == ci]
+        ref = alone(sg, code, gcodes[ci], [frames[f][1] for f in sel], True, L, qcap, iters)
+        for f, r in zip(sel, ref):
+            g = got[f]
+            assert g["status"] == 0 and g["n"] == code.n
+            assert (g["success"], g["half_iters"], g["queries"]) == (r["success"], r["half_iters"], r["queries"]), f
+            np.testing.assert_array_equal(g["hard"], r["hard"], err_msg=f"frame {f}")
+
+
 def test_served_matches_oracle_sample(sg):
     F, L, qcap, iters = 24, 4, 1000, 4
     code = synth.ebch(32, 26)
