@@ -757,6 +757,11 @@ def main() -> int:
         measured = sg.measure_valu_rate() / 1e12
         roof["peak_measured"] = measured
         roof["frac_of_measured"] = roof["achieved"] / measured
+    if roof and roof.get("traffic") and roof.get("avg_launch_ms"):
+        # the dominant kernel's HBM rate from the recorded bytes per launch, against 8 TB/s
+        rate = roof["traffic"] / (roof["avg_launch_ms"] / 1e3) / 1e9
+        roof["traffic_gb_per_s"] = rate
+        roof["traffic_frac_of_hbm"] = rate / 8000.0
     print(json.dumps(line), flush=True)
     return 0
 
