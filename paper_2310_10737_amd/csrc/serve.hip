@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_pass(ServeArgs a) {
 }
 
 // One wave per frame of the step: validity of the hard decision (every line of
-// the last pass and every cross line a codeword), the frame's verdict into host
+// the last pass and every cross line a codeword), the frame's outcome into host
 // memory, and for a finished frame its hard decision into the host copy.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
@@ -536,7 +536,7 @@ int sogrand_serve_create(const sogrand_params_t *params, size_t hbm_budget_bytes
     if (hipGetDevice(&s->device) != hipSuccess) return cleanup(fail(SOGRAND_EDEVICE, "no current device"));
     if (hipMalloc(reinterpret_cast<void **>(&s->arena), s->budget) != hipSuccess)
         return cleanup(fail(SOGRAND_ENOMEM, "slot arena of %zu bytes", s->budget));
-    // the device reads submitted LLRs from, and writes hard decisions and verdicts
+    // the device reads submitted LLRs from, and writes hard decisions and outcomes
     // to, these host allocations inside kernels: coherent and mapped
     const unsigned shared_flags = hipHostMallocMapped | hipHostMallocCoherent;
     if (hipHostMalloc(reinterpret_cast<void **>(&s->mirror), s->budget, shared_flags) != hipSuccess)
