@@ -339,13 +339,15 @@ int sogrand_profile_begin(int count_work);
    families in stats (*n_stats set).  Errors: EINVAL, EDEVICE. */
 int sogrand_profile_end(sogrand_kernel_stat_t *stats, int max_stats, int *n_stats);
 
-/* Measures the device's VALU issue rate, the denominator of the ALU roofline: a
-   kernel of eight independent 32-bit XOR/ADD chains per lane (64 VALU
-   instructions per loop trip, eight waves on every SIMD) runs four times on
-   `stream` (NULL: the null stream) after a warm-up; returns lane-operations per
-   second in *lane_ops_per_s and the mean launch time in *ms (nullable).  Blocks
-   until done.  Errors: EINVAL, ENOMEM, EDEVICE. */
-int sogrand_measure_valu_rate(double *lane_ops_per_s, double *ms, void *stream);
+/* Measures the device's VALU issue rate for one instruction kind: a kernel of
+   eight independent chains per lane (64 VALU instructions per loop trip, eight
+   waves on every SIMD) runs four times on `stream` (NULL: the null stream) after
+   a warm-up.  kind 0: 32-bit XOR and ADD (VOP2 forms), the denominator of the
+   ALU roofline; 1: binary64 FMA; 2: 32-bit bit-field extract and shift-add (VOP3
+   forms).  Returns lane-operations (one per lane per instruction) per second in
+   *lane_ops_per_s and the mean launch time in *ms (nullable).  Blocks until
+   done.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int sogrand_measure_valu_rate(int kind, double *lane_ops_per_s, double *ms, void *stream);
 
 #ifdef __cplusplus
 }

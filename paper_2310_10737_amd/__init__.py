@@ -142,7 +142,7 @@ def lib():
     L.sogrand_serve_destroy.argtypes = [P]
     L.sogrand_profile_begin.argtypes = [I]
     L.sogrand_profile_end.argtypes = [P, I, P]
-    L.sogrand_measure_valu_rate.argtypes = [P, P, P]
+    L.sogrand_measure_valu_rate.argtypes = [I, P, P, P]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -389,11 +389,12 @@ def _batched(fn, codes, frame_code, frame_offset, llr, list_max, query_cap, max_
     return out
 
 
-def measure_valu_rate(stream=None) -> float:
-    """The device's measured VALU issue rate in lane-operations per second (integer XOR/ADD
-    chains on every SIMD; the denominator of the ALU roofline)."""
+def measure_valu_rate(kind: int = 0, stream=None) -> float:
+    """The device's measured VALU issue rate in lane-operations per second for one instruction
+    kind: 0 integer XOR/ADD (the denominator of the ALU roofline), 1 binary64 FMA, 2 integer
+    bit-field extract and shift-add."""
     rate, ms = ctypes.c_double(), ctypes.c_double()
-    _check(lib().sogrand_measure_valu_rate(ctypes.byref(rate), ctypes.byref(ms), _stream(stream)))
+    _check(lib().sogrand_measure_valu_rate(int(kind), ctypes.byref(rate), ctypes.byref(ms), _stream(stream)))
     return rate.value
 
 
