@@ -116,6 +116,9 @@ def lib():
         return _lib
     if not os.path.exists(_LIBPATH):
         raise SograndError(-3, f"{_LIBPATH} is missing: build it with __graft_entry__.build()")
+    # torch (which supplies device memory and streams) loads its HIP runtime first, so that the
+    # library binds to the same runtime instead of loading a second one into the process
+    import torch  # noqa: F401
     L = ctypes.CDLL(_LIBPATH)
     P, I, U32, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t
     L.sogrand_last_error.restype = ctypes.c_char_p
