@@ -186,7 +186,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
         // largest pattern weight of the round over both words' 64-pattern chunks
         const uint32_t w0 = base < lim0 ? wm0[base >> 6] : 0u;
         const uint32_t w1 = base < lim1 ? wm1[base >> 6] : 0u;
-        const uint32_t wmx = w0 > w1 ? w0 : w1;
+        const uint32_t wmx = __builtin_amdgcn_readfirstlane(w0 > w1 ? w0 : w1);   // the same in every lane
         const bool act = !done && base + (uint32_t)hl < limit;
         uint32_t s = s0;
         double tau = 1.0;

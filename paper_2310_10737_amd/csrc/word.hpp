@@ -692,7 +692,9 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     uint32_t wm_next2 = limit > (uint32_t)kWave ? wm[1] : 0u;
     for (uint32_t base = 0; base < limit; base += kWave) {
         const uint4 e = e_next;
-        const uint32_t wmx = wm_next;
+        // wave-uniform; in the persistent kernels its load is a vector load, so the branches on it
+        // would otherwise be taken per lane under exec masks
+        const uint32_t wmx = __builtin_amdgcn_readfirstlane(wm_next);
         const uint32_t nb = base + kWave;
         e_next = e_next2;
         wm_next = wm_next2;
