@@ -491,6 +491,17 @@ __device__ __forceinline__ void put_rho(LDS &S, int r, double v) {
         tau *= __longlong_as_double((long long)(((uint64_t)q_.y << 32) | q_.x)); \
     } while (0)
 
+// Two ranks of a pattern, both entries read before either is used (the products keep the
+// order of two SG_RANKs).
+#define SG_RANK2(d, SH1, SH2)                                                        \
+    do {                                                                             \
+        const uint4 qa_ = S.ent_r[((d) >> (SH1)) & 0xffu];                           \
+        const uint4 qb_ = S.ent_r[((d) >> (SH2)) & 0xffu];                           \
+        s ^= qa_.z ^ qb_.z;                                                          \
+        tau *= __longlong_as_double((long long)(((uint64_t)qa_.y << 32) | qa_.x));   \
+        tau *= __longlong_as_double((long long)(((uint64_t)qb_.y << 32) | qb_.x));   \
+    } while (0)
+
 // Rank (1-based) of each lane's key among the n keys, |lambda| bit patterns by bit
 // index (non-negative doubles order like their bit patterns), ties by bit index.
 // Returns whether the exact tie-resolving pass ran.
@@ -709,27 +720,19 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         double tau = 1.0;
         // ranks in straight-line pairs (rank 0 pads: hs 0, rho 1), so that both
         // lookups of a pair are in flight together
-        SG_RANK(e.x, 0);
-        SG_RANK(e.x, 8);
+        SG_RANK2(e.x, 0, 8);
         if (wmx > 2) {
-            SG_RANK(e.x, 16);
-            SG_RANK(e.x, 24);
+            SG_RANK2(e.x, 16, 24);
             if (wmx > 4) {
-                SG_RANK(e.y, 0);
-                SG_RANK(e.y, 8);
+                SG_RANK2(e.y, 0, 8);
                 if (wmx > 6) {
-                    SG_RANK(e.y, 16);
-                    SG_RANK(e.y, 24);
+                    SG_RANK2(e.y, 16, 24);
                     if (wmx > 8) {
-                        SG_RANK(e.z, 0);
-                        SG_RANK(e.z, 8);
-                        SG_RANK(e.z, 16);
-                        SG_RANK(e.z, 24);
+                        SG_RANK2(e.z, 0, 8);
+                        SG_RANK2(e.z, 16, 24);
                         if (wmx > 12) {
-                            SG_RANK(e.w, 0);
-                            SG_RANK(e.w, 8);
-                            SG_RANK(e.w, 16);
-                            SG_RANK(e.w, 24);
+                            SG_RANK2(e.w, 0, 8);
+                            SG_RANK2(e.w, 16, 24);
                         }
                     }
                 }
