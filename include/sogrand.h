@@ -342,9 +342,9 @@ int sogrand_profile_end(sogrand_kernel_stat_t *stats, int max_stats, int *n_stat
 /* Measures the device's VALU issue rate for one instruction kind: a kernel of
    eight independent chains per lane (64 VALU instructions per loop trip, eight
    waves on every SIMD) runs four times on `stream` (NULL: the null stream) after
-   a warm-up.  kind 0: 32-bit XOR and ADD (VOP2 forms), the denominator of the
-   ALU roofline; 1: binary64 FMA; 2: 32-bit bit-field extract and shift-add (VOP3
-   forms).  Returns lane-operations (one per lane per instruction) per second in
+   a warm-up.  kind 0: 32-bit XOR and ADD (VOP2 forms), the measured counterpart
+   of the ALU roofline's derived peak; 1: binary64 FMA; 2: 32-bit bit-field
+   extract and shift-add (VOP3 forms).  Returns lane-operations (one per lane per instruction) per second in
    *lane_ops_per_s and the mean launch time in *ms (nullable).  Blocks until
    done.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int sogrand_measure_valu_rate(int kind, double *lane_ops_per_s, double *ms, void *stream);

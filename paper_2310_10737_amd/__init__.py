@@ -394,8 +394,8 @@ def _batched(fn, codes, frame_code, frame_offset, llr, list_max, query_cap, max_
 
 def measure_valu_rate(kind: int = 0, stream=None) -> float:
     """The device's measured VALU issue rate in lane-operations per second for one instruction
-    kind: 0 integer XOR/ADD (the denominator of the ALU roofline), 1 binary64 FMA, 2 integer
-    bit-field extract and shift-add."""
+    kind: 0 integer XOR/ADD (the measured counterpart of the ALU roofline's derived peak), 1 binary64
+    FMA, 2 integer bit-field extract and shift-add."""
     rate, ms = ctypes.c_double(), ctypes.c_double()
     _check(lib().sogrand_measure_valu_rate(int(kind), ctypes.byref(rate), ctypes.byref(ms), _stream(stream)))
     return rate.value
