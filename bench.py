@@ -172,8 +172,14 @@ def mixed_frames_f32(nks, lo, hi, seed, F, np):
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
     step = 1000
     jobs = [(nks, lo, hi, seed, a, min(F, a + step)) for a in range(0, F, step)]
-    with mp.get_context("fork").Pool(workers) as pool:
+    pool = mp.get_context("fork").Pool(workers)
+    try:
         parts = pool.map(_mixed_chunk, jobs)
+    finally:
+        # the workers exit on their own; terminating them would signal them while a
+        # profiler's handlers are installed
+        pool.close()
+        pool.join()
     cidx = np.concatenate([p[0] for p in parts])
     eb = np.concatenate([p[1] for p in parts])
     base, offs = 0, []

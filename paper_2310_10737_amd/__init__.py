@@ -20,8 +20,7 @@ __all__ = [
 SOGRAND_F64 = 0
 SOGRAND_F32 = 1
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# SOGRAND_LIB selects another build of the library (A/B measurements of two builds)
-_LIBPATH = os.environ.get("SOGRAND_LIB") or os.path.join(_HERE, "libsogrand.so")
+_LIBPATH = os.path.join(_HERE, "libsogrand.so")
 _lib = None
 
 EXPORTS = [

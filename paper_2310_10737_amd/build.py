@@ -1,20 +1,26 @@
-"""Builds libsogrand.so (HIP, gfx950) in-tree with hipcc."""
+"""Builds libsogrand.so (HIP, gfx950) in-tree with hipcc.
+
+Each source compiles to its own object (in parallel), and the objects link into
+one shared library.  The sources share no device symbols across files, so no
+relocatable device code is needed.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsogrand.so")
+OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["code.hip", "decode.hip", "batched.hip", "serve.hip", "profile.hip"]
-HOST_SOURCES: list = []
 
-HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIPCC = "/opt/rocm/bin/hipcc"
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
     # packed FP32 VALU forms stay off: the compiler would otherwise emit them from
     # scalar float code
@@ -23,11 +29,23 @@ FLAGS = [
 ]
 
 
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC] + FLAGS + ["-c", "-o", obj, os.path.join(CSRC, src)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source of the library into one shared object."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES + HOST_SOURCES]
+    """Compile every HIP source of the library and link them into one shared object."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    workers = max(1, min(len(SOURCES), len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(workers) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs + ["-lpthread"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -24,7 +24,6 @@ struct ComponentArgs {
     double *p_notfound;
     uint8_t *found_z;
     ProfCounters *prof;
-    int xcd;
 };
 
 
@@ -35,7 +34,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_component(ComponentArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = WPB == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     WaveLds &S = lds[wave];
-    const size_t wid = logical_block(a.xcd) * WPB + wave;
+    const size_t wid = (size_t)blockIdx.x * WPB + wave;
     if (wid >= a.nwords) return;
     const int n = a.code.n;
     const T *in = static_cast<const T *>(a.llr_in) + wid * n;
@@ -117,7 +116,6 @@ struct ProductArgs {
     uint16_t *half_iters;   // [F]
     int early_stop;
     ProfCounters *prof;
-    int xcd;
 };
 
 // Per-frame state at the start (the first row pass needs no a-priori LLRs and
@@ -166,7 +164,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
     WaveLds &S = lds[wave];
     const uint32_t n = (uint32_t)a.code.n;
     // the host keeps nframes * n below 2^31
-    const uint32_t wid = (uint32_t)logical_block(a.xcd) * WPB + (uint32_t)wave;
+    const uint32_t wid = (uint32_t)blockIdx.x * WPB + (uint32_t)wave;
     const uint32_t f = wid / n;
     const uint32_t line = wid - f * n;
     if (f >= a.nframes) return;
@@ -238,7 +236,7 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass_pair(ProductArgs a
     PairLds &S = lds[wave][upper ? 1 : 0];
     const uint32_t n = (uint32_t)a.code.n;
     // the host keeps nframes * n below 2^31
-    const uint32_t pair = (uint32_t)logical_block(a.xcd) * WPB + (uint32_t)wave;
+    const uint32_t pair = (uint32_t)blockIdx.x * WPB + (uint32_t)wave;
     const uint32_t gl = pair * 2u + (upper ? 1u : 0u);
     const uint32_t f = gl / n;
     const uint32_t line = gl - f * n;
@@ -341,30 +339,10 @@ __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, 
 // ----------------------------------------------------------------------------
 static int sort_width(int n) { return n <= 32 ? 32 : (n <= 64 ? 64 : 128); }
 
-// Launch shape of the decode kernels: kWavesPerBlock waves per workgroup (measured
-// best on MI355X against 1 and 2) and the workgroup order; SOGRAND_XCD=1 selects the
-// XCD-aware order (measured slower here: frames of similar SNR then share an XCD).
-struct LaunchShape {
-    int wpb;
-    int xcd;
-};
-
-static LaunchShape launch_shape() {
-    static const LaunchShape shape = [] {
-        LaunchShape s{kWavesPerBlock, 0};
-        if (const char *e = getenv("SOGRAND_XCD")) s.xcd = atoi(e) != 0;
-        return s;
-    }();
-    return shape;
-}
-
-// workgroups covering `words` words, rounded up to a multiple of the XCD count when
-// the XCD-aware order is on
-static size_t word_grid(size_t words, const LaunchShape &ls) {
-    size_t g = (words + ls.wpb - 1) / ls.wpb;
-    if (ls.xcd) g = (g + kXcds - 1) / kXcds * kXcds;
-    return g;
-}
+// Workgroups of kWavesPerBlock waves (measured best on MI355X against 1 and 2), in
+// plain dispatch order.  An XCD-aware order (consecutive lines of a frame on one XCD)
+// measured slower: frames of similar SNR then share an XCD and its load.
+static size_t word_grid(size_t words) { return (words + kWavesPerBlock - 1) / kWavesPerBlock; }
 
 template <typename T, bool STOP>
 static void launch_component_s(const ComponentArgs &a, int ns, dim3 g, hipStream_t st) {
@@ -431,9 +409,7 @@ int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t 
     a.p_notfound = p_notfound;
     a.found_z = found_z;
     a.prof = prof_counters(PK_COMPONENT);
-    const LaunchShape ls = launch_shape();
-    a.xcd = ls.xcd;
-    const size_t blocks = word_grid(nwords, ls);
+    const size_t blocks = word_grid(nwords);
     if (blocks > 0x7fffffffull) return fail(SOGRAND_EINVAL, "nwords too large for one launch");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int ns = sort_width(code->n);
@@ -461,10 +437,9 @@ static int decode_frames(int topo, const sogrand_code_t *code, const sogrand_par
     const size_t words = nframes * (size_t)n;
     if (nframes > ((size_t)1 << 34) / ((size_t)n * n) || words >= ((size_t)1 << 31))
         return fail(SOGRAND_EINVAL, "nframes too large");
-    const LaunchShape ls = launch_shape();
     const int ns = sort_width(n);
     // words of up to 32 bits go two to a wave
-    const size_t blocks = word_grid(ns == 32 ? (words + 1) / 2 : words, ls);
+    const size_t blocks = word_grid(ns == 32 ? (words + 1) / 2 : words);
     if (blocks > 0x7fffffffull) return fail(SOGRAND_EINVAL, "nframes too large for one launch");
     ProductArgs a;
     SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &a.code));
@@ -506,7 +481,6 @@ static int decode_frames(int topo, const sogrand_code_t *code, const sogrand_par
     a.half_iters = half_iters ? half_iters : reinterpret_cast<uint16_t *>(ws + off_hi);
     a.early_stop = params->early_stop ? 1 : 0;
     a.prof = prof_counters(PK_PASS);
-    a.xcd = ls.xcd;
     const bool f64 = params->precision == SOGRAND_F64;
     int rc = SOGRAND_OK;
     {

@@ -28,7 +28,6 @@ namespace sg {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;            // init and check kernels
 constexpr int kBlock = kWave * kWavesPerBlock;
-constexpr int kXcds = 8;                     // MI355X: workgroups are dealt to 8 XCDs in turn
 
 // Per-wave scratch.  A rank's H column and rho share one 16-byte entry, so the
 // query loop reads both with one LDS instruction into an aligned register pair.
@@ -42,15 +41,6 @@ struct WaveLds {
     uint8_t pi_r[SOGRAND_NMAX + 1];      // bit index of each rank
     uint8_t rank_b[SOGRAND_NMAX];        // rank of each bit index
 };
-
-// Logical index of this workgroup.  With xcd set, consecutive logical indices (the
-// lines of one frame) go to the same XCD and share its L2; the grid is then a
-// multiple of 8.
-__device__ __forceinline__ size_t logical_block(bool xcd) {
-    if (!xcd) return blockIdx.x;
-    const size_t per = gridDim.x / kXcds;
-    return (size_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
-}
 
 template <int NS>
 struct Lanes {
