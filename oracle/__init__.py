@@ -52,7 +52,7 @@ def lib():
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_long, P,
                            ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                           ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int]
+                           ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P, ctypes.c_int]
         L.oracle_vnode.restype = ctypes.c_int
         L.oracle_vnode.argtypes = [ctypes.c_int] * 5
         _lib = L
@@ -89,7 +89,9 @@ def decode_component(code, llr, list_max: int = 4, qcap: int = 1000, want_z: boo
     """SISO SOGRAND decode of each row of llr (W, n) float64 (lambda = L_Ch + L_A).
 
     pstop > 0 ends a word's search once the predicted list-BLER of the list found so
-    far is below pstop."""
+    far is below pstop.  diag (want_diag): per word p(0|r), the tested mass, the
+    not-found mass M, the parity-class mass, and 1.0 if the search tested every
+    pattern of the class (M is then exactly 0)."""
     llr = np.ascontiguousarray(llr, dtype=np.float64)
     W, n = llr.shape
     assert n == code.n
@@ -99,7 +101,7 @@ def decode_component(code, llr, list_max: int = 4, qcap: int = 1000, want_z: boo
         found_q=np.zeros((W, list_max), np.uint32), p_found=np.zeros((W, list_max)),
         p_notfound=np.zeros(W),
         found_z=np.zeros((W, list_max, n), np.uint8) if want_z else None,
-        diag=np.zeros((W, 4)) if want_diag else None,
+        diag=np.zeros((W, 5)) if want_diag else None,
     )
     rc = lib().oracle_decode_component(
         code.n, code.k, _p(_hcols(code)), W, _p(llr), list_max, qcap, float(pstop),
@@ -112,7 +114,7 @@ def decode_component(code, llr, list_max: int = 4, qcap: int = 1000, want_z: boo
 
 
 def _two_family(fn, name, code, llr_ch, list_max, qcap, max_iter, alpha, early_stop, store_f32, want_app,
-                nthreads, pstop):
+                nthreads, pstop, want_last_diag=False):
     llr_ch = np.ascontiguousarray(llr_ch, dtype=np.float64)
     F, n, n2 = llr_ch.shape
     assert n == n2 == code.n
@@ -120,10 +122,13 @@ def _two_family(fn, name, code, llr_ch, list_max, qcap, max_iter, alpha, early_s
         hard=np.zeros((F, n, n), np.uint8), llr_app=np.zeros((F, n, n)) if want_app else None,
         success=np.zeros(F, np.uint8), half_iters=np.zeros(F, np.uint16),
         sum_queries=np.zeros(F, np.uint64), sum_max_queries=np.zeros(F, np.uint64),
+        last_diag=np.zeros((F, n, 5)) if want_last_diag else None,
+        kappa_max=np.zeros(F) if want_last_diag else None,
     )
     rc = fn(code.n, code.k, _p(_hcols(code)), F, _p(llr_ch), list_max, qcap, float(pstop), max_iter, alpha,
             int(early_stop), int(store_f32), _p(out["hard"]), _p(out["llr_app"]), _p(out["success"]),
-            _p(out["half_iters"]), _p(out["sum_queries"]), _p(out["sum_max_queries"]), nthreads)
+            _p(out["half_iters"]), _p(out["sum_queries"]), _p(out["sum_max_queries"]), _p(out["last_diag"]),
+            _p(out["kappa_max"]), nthreads)
     if rc:
         raise ValueError(f"{name} rejected its arguments")
     return out
@@ -131,19 +136,24 @@ def _two_family(fn, name, code, llr_ch, list_max, qcap, max_iter, alpha, early_s
 
 def decode_product(code, llr_ch, list_max: int = 4, qcap: int = 1000, max_iter: int = 4,
                    alpha: float = 0.5, early_stop: bool = True, store_f32: bool = False,
-                   want_app: bool = False, nthreads: int = 1, pstop: float = 0.0):
-    """Block-turbo decode of product-code frames llr_ch (F, n, n) float64, row-major."""
+                   want_app: bool = False, nthreads: int = 1, pstop: float = 0.0, want_last_diag: bool = False):
+    """Block-turbo decode of product-code frames llr_ch (F, n, n) float64, row-major.
+
+    want_last_diag: also return last_diag (F, n, 5), decode_component's diag of each word of
+    the frame's last half-iteration (rows after an odd, columns after an even count), and
+    kappa_max (F,), the largest condition number class mass / not-found mass over every word
+    the frame decoded."""
     return _two_family(lib().oracle_decode_product, "oracle_decode_product", code, llr_ch, list_max, qcap,
-                       max_iter, alpha, early_stop, store_f32, want_app, nthreads, pstop)
+                       max_iter, alpha, early_stop, store_f32, want_app, nthreads, pstop, want_last_diag)
 
 
 def decode_gldpc(code, llr_ch, list_max: int = 4, qcap: int = 1000, max_iter: int = 20,
                  alpha: float = 0.6, early_stop: bool = True, store_f32: bool = False,
-                 want_app: bool = False, nthreads: int = 1, pstop: float = 0.0):
+                 want_app: bool = False, nthreads: int = 1, pstop: float = 0.0, want_last_diag: bool = False):
     """The same loop over QC-GLDPC frames llr_ch (F, n, n) float64: element [j, c] is variable
     node j*n + c (column c of block j of the adjacency matrix)."""
     return _two_family(lib().oracle_decode_gldpc, "oracle_decode_gldpc", code, llr_ch, list_max, qcap,
-                       max_iter, alpha, early_stop, store_f32, want_app, nthreads, pstop)
+                       max_iter, alpha, early_stop, store_f32, want_app, nthreads, pstop, want_last_diag)
 
 
 def vnode(topo: int, n: int, fam: int, line: int, j: int) -> int:

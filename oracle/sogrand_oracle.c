@@ -254,7 +254,8 @@ typedef struct {
     double *p_found;             /* [L] */
     double *p_notfound;          /* [1] */
     uint8_t *found_z;            /* [L][n] or NULL */
-    double *diag;                /* [4] p0, queried mass, not-found mass, parity-class mass; or NULL */
+    double *diag;                /* [5] p0, queried mass, not-found mass, parity-class mass, and 1 if
+                                    the class was exhausted (else 0); or NULL */
 } oword_out;
 
 typedef struct {
@@ -323,6 +324,10 @@ static void decode_word(const ocode *c, const oorders *os, const double *lam, in
           list-BLER predicted by Corollary 1 for the list so far, with the mass
           tested up to this codeword, is below pstop; that test is taken in binary64. */
     const oorder *ord = c->even ? &os->ord[ypar] : &os->ord[0];
+    /* size of the queried class: every pattern of the hard decision's parity (even
+       codes) or every pattern; 0 when it exceeds any query cap */
+    const int cbits = c->even ? n - 1 : n;
+    const long class_size = cbits <= 40 ? (1L << cbits) : 0;
     long t = 0;
     int stopped = 0;
     int found = 0;
@@ -349,7 +354,7 @@ static void decode_word(const ocode *c, const oorders *os, const double *lam, in
             found++;
             if (pstop > 0.0 && found < L) {
                 long double Mi = p0 * ((long double)(zero_in_class - zero_tested) + (T_nz - S_nz));
-                if (Mi < 0.0L) Mi = 0.0L;
+                if (Mi < 0.0L || t == class_size) Mi = 0.0L;   /* nothing left untested */
                 long double Di = Mi * phi;
                 for (int l = 0; l < found; l++) Di += sc->pz[l];
                 if ((double)((Mi * phi) / Di) < pstop) stopped = 1;
@@ -358,9 +363,11 @@ static void decode_word(const ocode *c, const oorders *os, const double *lam, in
     }
     const long Q = t;
 
-    /* 7. not-found mass and block soft output (Corollary 1) */
+    /* 7. not-found mass and block soft output (Corollary 1).  Once every pattern of
+          the class has been tested, the untested mass is exactly zero; the
+          subtraction would leave only its rounding residue. */
     long double M = p0 * ((long double)(zero_in_class - zero_tested) + (T_nz - S_nz));
-    if (M < 0.0L) M = 0.0L;
+    if (M < 0.0L || Q == class_size) M = 0.0L;
     long double D = M * phi;
     for (int l = 0; l < found; l++) D += sc->pz[l];
     long double Pnf = (M * phi) / D;
@@ -395,12 +402,13 @@ static void decode_word(const ocode *c, const oorders *os, const double *lam, in
         out->diag[1] = (double)(p0 * ((long double)zero_tested + S_nz));
         out->diag[2] = (double)M;
         out->diag[3] = (double)(p0 * ((long double)zero_in_class + T_nz));
+        out->diag[4] = Q == class_size ? 1.0 : 0.0;
     }
 }
 
 /* Component decode of nwords independent words, row-major [nwords][n].
    found_q/p_found are [nwords][list_max]; entries past n_found are left zero.
-   found_z ([nwords][list_max][n]) and diag ([nwords][4]) may be NULL. */
+   found_z ([nwords][list_max][n]) and diag ([nwords][5]) may be NULL. */
 int oracle_decode_component(int n, int k, const uint64_t *hcols, long nwords, const double *llr,
                             int list_max, long qcap, double pstop,
                             double *llr_app, double *llr_ext, uint8_t *hard,
@@ -424,7 +432,7 @@ int oracle_decode_component(int n, int k, const uint64_t *hcols, long nwords, co
         o.p_found = p_found + wd * list_max;
         o.p_notfound = p_notfound + wd;
         o.found_z = found_z ? found_z + (size_t)wd * list_max * n : NULL;
-        o.diag = diag ? diag + wd * 4 : NULL;
+        o.diag = diag ? diag + wd * 5 : NULL;
         memset(o.found_q, 0, sizeof(uint32_t) * list_max);
         memset(o.p_found, 0, sizeof(double) * list_max);
         if (o.found_z) memset(o.found_z, 0, (size_t)list_max * n);
@@ -453,6 +461,8 @@ typedef struct {
     uint8_t *success;
     uint16_t *half_iters;
     uint64_t *sum_q, *sum_maxq;
+    double *last_diag;   /* [F][n][5] per word of the last half-iteration, or NULL */
+    double *kappa_max;   /* [F] largest condition number of a not-found mass, or NULL */
     long next;   /* shared frame counter */
 } oprod_job;
 
@@ -489,13 +499,16 @@ static int frame_is_codeword(const ocode *c, int topo, const uint8_t *C) {
 
 static void decode_frame(const oprod_job *J, long f, oscratch *sc, double *LA, double *LE,
                          double *LAPP, uint8_t *C, double *lam, double *app, double *ext,
-                         uint8_t *hd, uint32_t *fq, double *pf) {
+                         uint8_t *hd, uint32_t *fq, double *pf, double *dg) {
     const ocode *c = J->c;
     const int n = c->n;
     const double *Lch = J->llr_ch + (size_t)f * n * n;
     for (int i = 0; i < n * n; i++) LA[i] = 0.0;
     uint64_t sq = 0, smq = 0;
     int ok = 0, h;
+    /* condition number of M = class mass - tested mass over every word decoded: the
+       subtraction loses log2 of it in bits (0 when the class was exhausted, M = 0 exactly) */
+    double kmax = 0.0;
     for (h = 1; h <= 2 * J->max_iter; h++) {
         const int fam = (h & 1) ? 0 : 1;   /* rows / first block row on odd h */
         uint32_t qmax = 0;
@@ -505,10 +518,15 @@ static void decode_frame(const oprod_job *J, long f, oscratch *sc, double *LA, d
                 lam[j] = Lch[idx] + LA[idx];
             }
             uint32_t q; int32_t nf; double pnf;
-            oword_out o = { app, ext, hd, &q, &nf, fq, pf, &pnf, NULL, NULL };
+            oword_out o = { app, ext, hd, &q, &nf, fq, pf, &pnf, NULL, dg + (size_t)line * 5 };
             decode_word(c, J->os, lam, J->list_max, J->qcap, J->pstop, sc, &o);
             sq += q;
             if (q > qmax) qmax = q;
+            {
+                const double *d = dg + (size_t)line * 5;
+                double kw = d[4] > 0.0 ? 0.0 : (d[2] > 0.0 ? d[3] / d[2] : INFINITY);
+                if (kw > kmax) kmax = kw;
+            }
             for (int j = 0; j < n; j++) {
                 long idx = vnode(J->topo, n, fam, line, j);
                 LAPP[idx] = app[j];
@@ -528,6 +546,8 @@ static void decode_frame(const oprod_job *J, long f, oscratch *sc, double *LA, d
     if (h > 2 * J->max_iter) h = 2 * J->max_iter;
     memcpy(J->hard + (size_t)f * n * n, C, (size_t)n * n);
     if (J->llr_app) memcpy(J->llr_app + (size_t)f * n * n, LAPP, sizeof(double) * n * n);
+    if (J->last_diag) memcpy(J->last_diag + (size_t)f * n * 5, dg, sizeof(double) * n * 5);
+    if (J->kappa_max) J->kappa_max[f] = kmax;
     J->success[f] = (uint8_t)ok;
     J->half_iters[f] = (uint16_t)h;
     J->sum_q[f] = sq;
@@ -549,31 +569,38 @@ static void *prod_worker(void *arg) {
     uint8_t *hd = (uint8_t *)malloc((size_t)n);
     uint32_t *fq = (uint32_t *)malloc(sizeof(uint32_t) * J->list_max);
     double *pf = (double *)malloc(sizeof(double) * J->list_max);
+    double *dg = (double *)malloc(sizeof(double) * n * 5);
     for (;;) {
         long f = __atomic_fetch_add(&J->next, 1, __ATOMIC_RELAXED);
         if (f >= J->nframes) break;
-        decode_frame(J, f, &sc, LA, LE, LAPP, C, lam, app, ext, hd, fq, pf);
+        decode_frame(J, f, &sc, LA, LE, LAPP, C, lam, app, ext, hd, fq, pf, dg);
     }
     free(LA); free(LE); free(LAPP); free(C); free(lam); free(app); free(ext); free(hd); free(fq); free(pf);
+    free(dg);
     scratch_free(&sc);
     return NULL;
 }
 
 /* Product decode of nframes frames [nframes][n][n] of channel LLRs.
    store_f32 != 0 stores the exchanged a-priori LLRs in binary32 (the caller
-   passes binary32-representable channel LLRs).  llr_app may be NULL. */
+   passes binary32-representable channel LLRs).  llr_app may be NULL.  last_diag, if not
+   NULL, receives [F][n][5]: the diag entries of each word of the frame's last
+   half-iteration (word = row on odd, column on even half-iterations).  kappa_max, if
+   not NULL, receives [F] the largest condition number class mass / not-found mass
+   over every word the frame decoded (0 for an exhausted class, inf where the
+   not-found mass vanished without exhaustion). */
 static int decode_two_families(int topo, int n, int k, const uint64_t *hcols, long nframes,
                                const double *llr_ch, int list_max, long qcap, double pstop, int max_iter,
                                double alpha, int early_stop, int store_f32, uint8_t *hard, double *llr_app,
                                uint8_t *success, uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq,
-                               int nthreads) {
+                               double *last_diag, double *kappa_max, int nthreads) {
     ocode c;
     if (code_init(&c, n, k, hcols)) return -1;
     if (list_max < 1 || qcap < 1 || max_iter < 1 || !(pstop >= 0.0 && pstop <= 1.0)) return -1;
     oorders os;
     orders_build(&os, &c, qcap);
     oprod_job J = { &c, &os, topo, nframes, llr_ch, list_max, max_iter, early_stop, store_f32, qcap, pstop,
-                    alpha, hard, llr_app, success, half_iters, sum_q, sum_maxq, 0 };
+                    alpha, hard, llr_app, success, half_iters, sum_q, sum_maxq, last_diag, kappa_max, 0 };
     if (nthreads < 1) nthreads = 1;
     if (nthreads == 1) {
         prod_worker(&J);
@@ -591,10 +618,11 @@ static int decode_two_families(int topo, int n, int k, const uint64_t *hcols, lo
 int oracle_decode_product(int n, int k, const uint64_t *hcols, long nframes, const double *llr_ch,
                           int list_max, long qcap, double pstop, int max_iter, double alpha, int early_stop,
                           int store_f32, uint8_t *hard, double *llr_app, uint8_t *success,
-                          uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq, int nthreads) {
+                          uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq, double *last_diag, double *kappa_max,
+                          int nthreads) {
     return decode_two_families(0, n, k, hcols, nframes, llr_ch, list_max, qcap, pstop, max_iter, alpha,
                                early_stop, store_f32, hard, llr_app, success, half_iters, sum_q, sum_maxq,
-                               nthreads);
+                               last_diag, kappa_max, nthreads);
 }
 
 /* The same loop over (n^2, n^2 - 2n(n-k)) QC-GLDPC frames, variable node j*n + c
@@ -602,8 +630,9 @@ int oracle_decode_product(int n, int k, const uint64_t *hcols, long nframes, con
 int oracle_decode_gldpc(int n, int k, const uint64_t *hcols, long nframes, const double *llr_ch,
                         int list_max, long qcap, double pstop, int max_iter, double alpha, int early_stop,
                         int store_f32, uint8_t *hard, double *llr_app, uint8_t *success,
-                        uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq, int nthreads) {
+                        uint16_t *half_iters, uint64_t *sum_q, uint64_t *sum_maxq, double *last_diag, double *kappa_max,
+                          int nthreads) {
     return decode_two_families(1, n, k, hcols, nframes, llr_ch, list_max, qcap, pstop, max_iter, alpha,
                                early_stop, store_f32, hard, llr_app, success, half_iters, sum_q, sum_maxq,
-                               nthreads);
+                               last_diag, kappa_max, nthreads);
 }

@@ -261,7 +261,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
                         break;
                     }
                     double Mi = T - (s_before + __longlong_as_double((long long)S.key_b[h]));
-                    if (!(Mi > 0.0)) Mi = 0.0;
+                    if (!(Mi > 0.0) || base + (uint32_t)h + 1u == class_size(c)) Mi = 0.0;
                     double Di = Mi * c.phi;
                     for (int l = 0; l < found; l++) Di += S.tau_l[l];
                     if ((Mi * c.phi) / Di < pstop) {
@@ -294,7 +294,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
     wave_sync();
     const double T = c.even ? (par ? O : E) : (E + O);
     double M = T - Snz;
-    if (!(M > 0.0)) M = 0.0;
+    if (!(M > 0.0) || Q == class_size(c)) M = 0.0;
     double D = M * c.phi;
     for (int l = 0; l < found; l++) D += S.tau_l[l];
     const bool degenerate = !(D > 0.0) || !isfinite(D);

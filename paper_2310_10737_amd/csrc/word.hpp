@@ -444,6 +444,15 @@ __device__ __forceinline__ double log_ratio(double n0, double n1) {
     return la;
 }
 
+// Patterns in the queried class: every pattern of the hard decision's parity for an even
+// code, every pattern otherwise; 0 when the class is larger than any query cap.  A search
+// that has tested this many patterns leaves no mass untested (Corollary 1's not-found mass
+// is then exactly zero, rather than the rounding residue of class mass minus tested mass).
+__device__ __forceinline__ uint32_t class_size(const DevCode &c) {
+    const int bits = c.even ? c.n - 1 : c.n;
+    return bits <= 31 ? (1u << bits) : 0u;
+}
+
 // zmask[bit] |= 1 << l for every bit of found pattern l: lane t handles byte t % 16
 // of pattern t / 16 (+ 4 per round); rank r maps back to its bit through pi_r.
 __device__ __forceinline__ void mark_found(WaveLds &S, int found, int lane) {
@@ -771,7 +780,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
                         break;
                     }
                     double Mi = T - (s_before + readlane_f64(tested, h));
-                    if (!(Mi > 0.0)) Mi = 0.0;
+                    if (!(Mi > 0.0) || base + (uint32_t)h + 1u == class_size(c)) Mi = 0.0;
                     double Di = Mi * c.phi;
                     for (int l = 0; l < found; l++) Di += S.tau_l[l];
                     if ((Mi * c.phi) / Di < pstop) {
@@ -799,7 +808,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     wave_sync();
     const double T = c.even ? (par ? O : E) : (E + O);
     double M = T - Snz;
-    if (!(M > 0.0)) M = 0.0;
+    if (!(M > 0.0) || Q == class_size(c)) M = 0.0;
     double D = M * c.phi;
     for (int l = 0; l < found; l++) D += S.tau_l[l];
     const bool degenerate = !(D > 0.0) || !isfinite(D);

@@ -86,6 +86,50 @@ def test_edge_cases(sg):
         run_pair(sg, c64, llr, 4, 500, label=f"ragged {W}")
 
 
+def small_code(n, k, even, seed):
+    """A systematic [n, k] code with random parity part, no bit that is 0 in every codeword, and
+    rows of even weight when `even`."""
+    rng = np.random.default_rng(seed)
+    while True:
+        P = rng.integers(0, 2, size=(k, n - k)).astype(np.uint8)
+        if even:
+            P[:, -1] = (1 + P[:, :-1].sum(1)) % 2
+        elif np.all((1 + P.sum(1)) % 2 == 0):
+            P[0, -1] ^= 1
+        if np.all(P.any(0)):
+            break
+    G = np.concatenate([np.eye(k, dtype=np.uint8), P], axis=1)
+    return synth.code_from_generator(f"[{n},{k}]{'e' if even else ''}", G, list(range(k)))
+
+
+@pytest.mark.parametrize("n,k,even", [(8, 3, True), (16, 3, True), (12, 3, False)])
+def test_exhausted_class_gives_exact_app(sg, n, k, even):
+    """A list longer than the codebook runs the search through the whole class: every
+    codeword is found, the not-found mass is exactly zero, and eq. (LLRi) is the exact bitwise
+    APP LLR, summed here over the codebook (within 1e-12 relative)."""
+    code = small_code(n, k, even, 100 + n)
+    assert code.is_even == even
+    llr, _, _ = synth.component_words(code, 0.5, 31 + n, np.arange(70))
+    L, cap = (1 << k) + 1, 1 << (n - 1 if even else n)
+    run_pair(sg, code, llr, L, cap, label=f"{code.name} exhausted class")
+    import torch
+    gcode = sg.Code.from_hcols(code.n, code.k, code.hcols)
+    out = sg.sogrand_decode_component(gcode, torch.from_numpy(llr).cuda(), list_max=L, query_cap=cap)
+    torch.cuda.synchronize()
+    assert np.all(out["n_queries"].cpu().numpy() == cap)
+    assert np.all(out["n_found"].cpu().numpy() == 1 << k)
+    assert np.all(out["p_notfound"].cpu().numpy() == 0.0)
+    msgs = ((np.arange(1 << k)[:, None] >> np.arange(k)) & 1).astype(np.int64)
+    cb = ((msgs @ code.G.astype(np.int64)) % 2).astype(np.float64)
+    s = (llr[:, None, :] * (1.0 - 2.0 * cb)).sum(-1) / 2.0
+    w = np.exp(s - s.max(1, keepdims=True))
+    exact = np.log((w[:, :, None] * (cb == 0)).sum(1)) - np.log((w[:, :, None] * (cb == 1)).sum(1))
+    got = out["llr_app"].cpu().numpy()
+    err = np.abs(got - exact) / np.maximum(1.0, np.abs(exact))
+    print(f"[gpu]   worst relative difference from the codebook APP {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-12
+
+
 @pytest.mark.parametrize("nk", [(32, 26), (64, 57), (128, 120)])
 def test_nearly_equal_magnitudes(sg, nk):
     """Magnitudes on a grid of 0.5, some moved by less than binary32 resolution: equal binary32

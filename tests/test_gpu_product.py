@@ -8,6 +8,7 @@ import pytest
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import oracle  # noqa: E402
 import synth  # noqa: E402
+from parity import compare_product  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -33,24 +34,6 @@ def gpu_product(sg, code, llr, L, qcap, iters, f32=False, early_stop=True):
     return {k: v.cpu().numpy() for k, v in out.items() if v is not None}
 
 
-def compare_product(g, r, f32=False, label=""):
-    np.testing.assert_array_equal(g["success"], r["success"], err_msg=label)
-    np.testing.assert_array_equal(g["half_iters"].astype(np.int64), r["half_iters"].astype(np.int64), err_msg=label)
-    np.testing.assert_array_equal(g["sum_queries"].astype(np.int64), r["sum_queries"].astype(np.int64), err_msg=label)
-    np.testing.assert_array_equal(g["sum_max_queries"].astype(np.int64), r["sum_max_queries"].astype(np.int64),
-                                  err_msg=label)
-    np.testing.assert_array_equal(g["hard"], r["hard"], err_msg=label)
-    d = np.abs(g["llr_app"].astype(np.float64) - r["llr_app"])
-    scale = np.maximum(1.0, np.abs(r["llr_app"]))
-    rel = d / scale
-    # same trajectory: final L_APP agree to the binary64 (or binary32 storage) rounding of the last pass,
-    # except where the not-found mass is ill-conditioned
-    lim = 1e-4 if f32 else 1e-9
-    frac = float(np.mean(rel > lim))
-    assert frac < 1e-3, f"{label}: {frac:.2e} of L_APP beyond {lim}, worst {rel.max():.3e}"
-    return float(rel.max())
-
-
 CASES = [
     ((16, 11), 2.0, 40, 4, 1000, 4),
     ((32, 26), 3.0, 100, 4, 1000, 4),     # the small plain configuration: 100 frames, seed 0
@@ -73,10 +56,9 @@ def test_product_parity(sg, nk, ebn0, frames, L, qcap, iters, f32):
     label = f"{code.name}^2 @{ebn0}dB f32={f32}"
     print(f"[gpu] product {label} frames={frames}", flush=True)
     g = gpu_product(sg, code, llr, L, qcap, iters, f32=f32)
-    r = oracle.decode_product(code, llr, L, qcap, iters, store_f32=f32, want_app=True, nthreads=8)
-    worst = compare_product(g, r, f32, label)
-    print(f"[gpu]   ok; BLER {np.mean(np.any(g['hard'] != cw, axis=(1, 2))):.3f}, worst rel dL {worst:.2e}",
-          flush=True)
+    r = oracle.decode_product(code, llr, L, qcap, iters, store_f32=f32, want_app=True, want_last_diag=True, nthreads=8)
+    compare_product(g, r, f32, label)
+    print(f"[gpu]   ok; BLER {np.mean(np.any(g['hard'] != cw, axis=(1, 2))):.3f}", flush=True)
 
 
 def hamming15():
@@ -97,7 +79,7 @@ def test_product_parity_short_and_odd_codes(sg, which, ebn0, frames, qcap, f32):
     label = f"{code.name}^2 @{ebn0}dB f32={f32}"
     print(f"[gpu] product {label} frames={frames}", flush=True)
     g = gpu_product(sg, code, llr, 4, qcap, 4, f32=f32)
-    r = oracle.decode_product(code, llr, 4, qcap, 4, store_f32=f32, want_app=True, nthreads=8)
+    r = oracle.decode_product(code, llr, 4, qcap, 4, store_f32=f32, want_app=True, want_last_diag=True, nthreads=8)
     compare_product(g, r, f32, label)
     assert r["half_iters"].max() > 2
 
@@ -117,7 +99,7 @@ def test_product_parity_with_equal_and_nearly_equal_magnitudes(sg, nk):
     llr[1, 0, :] = -0.0
     nudge = np.random.default_rng(1).integers(0, 3, size=llr.shape) * 2.0 ** -40   # below binary32 resolution
     llr = llr + np.sign(llr) * nudge
-    r = oracle.decode_product(code, llr, 4, 3000, 4, want_app=True, nthreads=8)
+    r = oracle.decode_product(code, llr, 4, 3000, 4, want_app=True, want_last_diag=True, nthreads=8)
     one = np.nonzero(r["half_iters"] == 1)[0]
     assert one.size >= 30
     llr = llr[one]
@@ -131,7 +113,7 @@ def test_product_without_early_stop(sg):
     code = synth.ebch(32, 26)
     llr, _, _ = synth.product_frames(code, 3.0, 9, np.arange(20))
     g = gpu_product(sg, code, llr, 4, 1000, 3, early_stop=False)
-    r = oracle.decode_product(code, llr, 4, 1000, 3, early_stop=False, want_app=True)
+    r = oracle.decode_product(code, llr, 4, 1000, 3, early_stop=False, want_app=True, want_last_diag=True)
     compare_product(g, r, label="no early stop")
     assert np.all(g["half_iters"] == 6)
 
@@ -141,7 +123,7 @@ def test_product_ragged_frame_counts(sg):
     for F in (1, 3, 5):
         llr, _, _ = synth.product_frames(code, 3.0, 77 + F, np.arange(F))
         g = gpu_product(sg, code, llr, 4, 2000, 3)
-        r = oracle.decode_product(code, llr, 4, 2000, 3, want_app=True)
+        r = oracle.decode_product(code, llr, 4, 2000, 3, want_app=True, want_last_diag=True)
         compare_product(g, r, label=f"F={F}")
 
 
@@ -191,7 +173,7 @@ def test_product_parity_rician(sg, f32):
                                     list_bler_stop=1e-4)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
-    r = oracle.decode_product(code, llr, 4, 10000, 20, store_f32=f32, want_app=True, pstop=1e-4, nthreads=8)
+    r = oracle.decode_product(code, llr, 4, 10000, 20, store_f32=f32, want_app=True, pstop=1e-4, want_last_diag=True, nthreads=8)
     compare_product(g, r, f32, label)
     assert r["half_iters"].max() > 2
 

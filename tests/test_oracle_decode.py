@@ -108,7 +108,8 @@ def test_list_and_query_numbers_match_bruteforce(nk, ebn0, seed, L, qcap):
         S = sum(p for m, p in B.p_of_mask.items() if B.q_of_mask[m] <= Q)
         M = sum(p for m, p in B.p_of_mask.items() if B.q_of_mask[m] > Q)
         Ppar = sum(B.p_of_mask.values())
-        p0, Sd, Md, Pd = out["diag"][wd]
+        p0, Sd, Md, Pd, exhausted = out["diag"][wd]
+        assert exhausted == (1.0 if Q == B.count else 0.0)
         assert math.isclose(Sd, S, rel_tol=1e-12)
         assert math.isclose(Pd, Ppar, rel_tol=1e-12)
         assert math.isclose(Md, M, rel_tol=1e-10, abs_tol=1e-300)
@@ -154,15 +155,17 @@ def test_exhaustive_list_gives_exact_bitwise_app(nk, ebn0):
     x = 1.0 - 2.0 * cb
     for wd in range(4):
         assert out["n_found"][wd] == L and out["n_queries"][wd] == 1 << (code.n - 1)
-        assert out["diag"][wd, 2] == pytest.approx(0.0, abs=1e-15 * out["diag"][wd, 3])
+        # every pattern of the class was tested: the untested mass is exactly zero
+        assert out["diag"][wd, 2] == 0.0 and out["diag"][wd, 4] == 1.0
         logf = -((r[wd][None, :] - x) ** 2).sum(1) / (2 * s2)
         logf -= logf.max()
         f = np.exp(logf)
         num = (f[:, None] * (cb == 0)).sum(0)
         den = (f[:, None] * (cb == 1)).sum(0)
         exact = np.log(num) - np.log(den)
-        np.testing.assert_allclose(out["llr_app"][wd], exact, rtol=1e-11, atol=1e-11)
-        assert out["p_notfound"][wd] < 1e-15
+        err = np.abs(out["llr_app"][wd] - exact) / np.maximum(1.0, np.abs(exact))
+        assert err.max() <= 1e-12
+        assert out["p_notfound"][wd] == 0.0
 
 
 @pytest.mark.parametrize("nk,ebn0", [((16, 11), 2.0), ((32, 26), 3.0), ((64, 57), 3.0)])
