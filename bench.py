@@ -1,23 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of SOGRAND product-code decoding on one MI355X.
 
-Default workload (--workload product): the (4096, 3249) = [64,57]^2 eBCH
-product code over BPSK-AWGN at Eb/N0 = 2.5, 3.0 and 3.5 dB, 10^4 frames per
-Eb/N0 (seeds 1, 2, 3), list size L = 4, query cap 10^4, 6 row+column
-iterations, alpha = 0.5.  One step decodes all 3x10^4 frames (every step of
-the hot path: ranking, query loop, soft output, exchange, validity checks)
-with inputs already resident in HBM.
+Default workload (--workload headline): the metric "decoded info bits/s (batched/served vs
+plain) at matched BLER; p99 frame latency", one JSON line combining
+  * the mixed stream (the line's `value`): 3x10^4 frames, codes uniform over the eBCH
+    [32,26]^2, [64,57]^2 and [128,120]^2 product codes, Eb/N0 uniform in [2, 4] dB (seed 4),
+    binary32 LLR storage, L = 4, query cap 10^5, 6 iterations, alpha 0.5: one persistent
+    batched launch per step against per-code plain calls on the same frames, resident in HBM;
+  * the serving form (`served`, `p50_frame_latency_ms`, `p99_frame_latency_ms`): 10^5
+    requests arriving as a Poisson process of rate 2x10^5/s (seed 6), codes uniform over the
+    three, Eb/N0 uniform in [2.5, 4.0] dB, the same decoder settings, continuous batching;
+  * the [64,57]^2 workload's forms (`product_64x57`): 10^4 frames at each of 2.5, 3.0, 3.5 dB
+    (seeds 1-3), L = 4, cap 10^4, 6 iterations; plain and batched, binary64 and binary32.
 
 Other workloads, each printing its own line:
-  mixed      3x10^4 frames, codes uniform over [32,26]^2, [64,57]^2, [128,120]^2,
-             Eb/N0 uniform in [2, 4] dB (seed 4), FP32 storage, L = 4, cap 10^5,
-             6 iterations: one persistent batched launch vs per-code plain calls.
+  product    the [64,57]^2 workload above, with the oracle as CPU baseline.
+  mixed      the mixed stream alone.
   component  2^20 independent [128,120] words at 4.0 dB (seed 5), cap 10^5,
              L = 1 and 4, FP32 and FP64 storage.
-  serve      10^5 requests arriving as a Poisson process of rate 2x10^5/s
-             (seed 6), codes uniform over the three above, Eb/N0 uniform in
-             [2.5, 4.0] dB, FP32, L = 4, cap 10^5, 6 iterations, served by
-             continuous batching; p50/p99 latency from arrival to result.
+  serve      the serving workload alone.
   gldpc      the (1024, 640) QC-GLDPC code with [32,26] eBCH check nodes at
              Eb/N0 = 2.0, 2.25 and 2.5 dB, 10^4 frames each (seeds 11-13),
              L = 4, cap 10^4, alpha = 0.6, 20 iterations, list-BLER stop 10^-5
@@ -28,8 +29,8 @@ Other workloads, each printing its own line:
              frames each (seeds 21-23), L = 4, cap 10^4, alpha = 0.5, 20
              iterations, list-BLER stop 10^-5 (the paper's fading settings).
 
-Prints one JSON line.  `value` is decoded information bits per second of the
-fastest form whose BLER matches the plain binary64 form (product workload).
+Every decode computes in binary64; `dtype` names that arithmetic, and the LLR storage of the
+timed form is given in the config.
 """
 from __future__ import annotations
 
@@ -51,6 +52,7 @@ SNRS = ((2.5, 1), (3.0, 2), (3.5, 3))
 N, K, L, QCAP, ITERS = 64, 57, 4, 10000, 6
 MIX_CODES = ((32, 26), (64, 57), (128, 120))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "product_64x57_hbm_bytes.md")
+MIXED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_mixed_hbm_bytes.md")
 KERNEL_SOURCES = ("word.hpp", "pair.hpp", "decode.hip", "batched.hip", "internal.hpp")
 
 
@@ -89,12 +91,12 @@ def kernel_digest() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(form: str):
+def recorded_traffic(form: str, path: str = None):
     """HBM bytes per launch of the form's dominant kernel (the row/column pass kernel, or the
-    persistent kernel), from the committed counter summary, if it was taken on the current
-    kernel sources (else None)."""
+    persistent kernel), from a committed counter summary (the [64,57]^2 one by default), if it
+    was taken on the current kernel sources (else None)."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path or TRAFFIC_FILE).read()
     except OSError:
         return None
     m = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
@@ -102,6 +104,22 @@ def recorded_traffic(form: str):
         return None
     m = re.search(rf"bytes_per_launch\[{form}\]:\s*([0-9.eE+]+)", text)
     return float(m.group(1)) if m else None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads for the oracle: every core this process may run on, at most 16 (a GPU machine
+    allots 16 host cores to one GPU, whatever the affinity mask shows)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def timed(step, steps, warmup, sg, count=True):
@@ -273,14 +291,22 @@ def oracle_baseline(args, np, llr_all, ngroups, F, decode, info_bits_per_frame):
     """The oracle over the first cpu_frames frames of each Eb/N0 group, on up to 16 threads."""
     if args.no_cpu or args.cpu_frames <= 0:
         return None
-    threads = min(16, len(os.sched_getaffinity(0)))
+    threads = host_threads()
     cf = min(args.cpu_frames, F)
     sample = np.concatenate([llr_all[j * F:j * F + cf] for j in range(ngroups)])
     t0 = time.perf_counter()
     decode(sample, threads)
     dt = time.perf_counter() - t0
+    c1 = max(1, cf // 20)
+    s1 = np.concatenate([llr_all[j * F:j * F + c1] for j in range(ngroups)])
+    t1 = time.perf_counter()
+    decode(s1, 1)
+    dt1 = time.perf_counter() - t1
     return dict(value=sample.shape[0] * info_bits_per_frame / dt, unit="info bits/s", cores=threads, kind="oracle",
-                sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall")
+                sample=f"first {cf} frames of each Eb/N0 ({sample.shape[0]} frames), {dt:.1f} s wall",
+                cpu_model=cpu_model(), affinity_cores=len(os.sched_getaffinity(0)),
+                one_thread=dict(value=s1.shape[0] * info_bits_per_frame / dt1,
+                                sample=f"first {c1} frames of each Eb/N0, {dt1:.1f} s wall"))
 
 
 def load_frames(np, torch, make, snrs, F, dev):
@@ -393,6 +419,8 @@ def bench_product(args, sg, np, torch, synth):
 # mixed: one persistent launch over three codes vs per-code plain calls
 # --------------------------------------------------------------------------------------------
 def bench_mixed(args, sg, np, torch, synth):
+    """The mixed stream: one persistent batched launch per step against per-code plain calls
+    on the same HBM-resident frames; BLER per code for both forms."""
     dev = torch.device("cuda:0")
     F, qcap = (args.frames if args.frames_set else 30000), (args.qcap or 100000)
     codes = [synth.ebch(*nk) for nk in MIX_CODES]
@@ -447,16 +475,21 @@ def bench_mixed(args, sg, np, torch, synth):
     bsucc = bout["success"].cpu().numpy()
     bhalf = bout["half_iters"].double().cpu().numpy()
     bq = bout["sum_queries"].double().cpu().numpy()
-    per_code = {}
+    bmq = bout["sum_max_queries"].double().cpu().numpy()
+    per_code, matched = {}, True
     for (c, sel, idx), po in zip(groups, pouts):
         nn = codes[c].n ** 2
+        phard = po["hard"].cpu().numpy().reshape(-1)
         same &= bool(np.array_equal(bsucc[sel], po["success"].cpu().numpy()))
-        same &= bool(np.array_equal(bhard[idx], po["hard"].cpu().numpy().reshape(-1)))
-        err = np.any(bhard[idx].reshape(-1, nn) != cw[idx].reshape(-1, nn), axis=1)
-        k_err = int(err.sum())
+        same &= bool(np.array_equal(bhard[idx], phard))
+        k_b = int(np.any(bhard[idx].reshape(-1, nn) != cw[idx].reshape(-1, nn), axis=1).sum())
+        k_p = int(np.any(phard.reshape(-1, nn) != cw[idx].reshape(-1, nn), axis=1).sum())
+        ci_p = wilson(k_p, int(sel.size))
+        matched &= ci_p[0] - 1e-12 <= k_b / max(1, sel.size) <= ci_p[1] + 1e-12
         per_code[f"[{codes[c].n},{codes[c].k}]^2"] = dict(
-            frames=int(sel.size), bler=k_err / max(1, sel.size), bler_ci95=wilson(k_err, int(sel.size)),
-            avg_iterations=float(bhalf[sel].mean() / 2), queries_per_bit=float(bq[sel].mean() / nn))
+            frames=int(sel.size), bler_batched=k_b / max(1, sel.size), bler_plain=k_p / max(1, sel.size),
+            bler_plain_ci95=ci_p, avg_iterations=float(bhalf[sel].mean() / 2),
+            queries_per_bit=float(bq[sel].mean() / nn), parallel_queries_per_bit=float(bmq[sel].mean() / nn))
     roof = None
     kp, wk = kern_b.get("batched", {}), work_b.get("batched", {})
     if kp.get("launches") and wk:
@@ -468,38 +501,79 @@ def bench_mixed(args, sg, np, torch, synth):
         avg_ms = kp["total_ms"] / kp["launches"]
         ops_launch = ops / (kp["launches"] / args.steps)
         achieved = ops_launch / (avg_ms / 1e3) / 1e12
+        default_cfg = F == 30000 and qcap == 100000
+        traffic = recorded_traffic("batched_f32", MIXED_TRAFFIC_FILE) if default_cfg else None
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_ALU_TOPS, unit="Top/s", frac=achieved / PEAK_ALU_TOPS,
-                    traffic=None, kernel="k_batched (persistent)", avg_launch_ms=avg_ms, ops_per_launch=ops_launch,
-                    words_per_step=wk["words"], queries_per_step=wk["queries"], ranks_per_step=wk["ranks"])
+                    traffic=traffic, kernel="k_batched<float, 8 waves, n <= 128> (persistent)",
+                    avg_launch_ms=avg_ms, ops_per_launch=ops_launch, words_per_step=wk["words"],
+                    queries_per_step=wk["queries"], ranks_per_step=wk["ranks"],
+                    exact_rank_words_per_step=wk.get("exact_rank"))
     cpu = None
     if not args.no_cpu and args.cpu_frames > 0:
         import oracle
-        threads = min(16, len(os.sched_getaffinity(0)))
+        threads = host_threads()
+
+        def oracle_rate(count, nthreads):
+            t0 = time.perf_counter()
+            bits = 0
+            for c, code in enumerate(codes):
+                sel = np.nonzero(cidx[:count] == c)[0]
+                if sel.size == 0:
+                    continue
+                nn = code.n * code.n
+                fr = np.stack([llr[o:o + nn] for o in offs[sel]]).astype(np.float64)
+                oracle.decode_product(code, fr.reshape(-1, code.n, code.n), L, qcap, ITERS, store_f32=True,
+                                      nthreads=nthreads)
+                bits += sel.size * code.k ** 2
+            dt = time.perf_counter() - t0
+            return bits / dt, dt
+
         cf = min(args.cpu_frames, F)
-        t0 = time.perf_counter()
-        bits = 0
-        for c, code in enumerate(codes):
-            sel = np.nonzero(cidx[:cf] == c)[0]
-            if sel.size == 0:
-                continue
-            nn = code.n * code.n
-            fr = np.stack([llr[o:o + nn] for o in offs[sel]]).astype(np.float64)
-            oracle.decode_product(code, fr.reshape(-1, code.n, code.n), L, qcap, ITERS, store_f32=True,
-                                  nthreads=threads)
-            bits += sel.size * code.k ** 2
-        dt = time.perf_counter() - t0
-        cpu = dict(value=bits / dt, unit="info bits/s", cores=threads, kind="oracle",
-                   sample=f"first {cf} frames of the mixed stream, {dt:.1f} s wall")
-    config = {"workload": "mixed eBCH product frames [32,26]^2/[64,57]^2/[128,120]^2 uniform, Eb/N0 U[2,4] dB, "
-                          f"{F} frames, L=4, query cap {qcap}, 6 iterations, FP32 storage",
-              "form": "batched_f32", "sched": dict(waves_per_group=sc.waves_per_group,
-                                                   frames_per_group=sc.frames_per_group,
-                                                   steal_chunk=sc.steal_chunk, groups_per_cu=sc.groups_per_cu),
+        rate, dt = oracle_rate(cf, threads)
+        c1 = min(max(1, cf // 10), F)
+        rate1, dt1 = oracle_rate(c1, 1)
+        cpu = dict(value=rate, unit="info bits/s", cores=threads, kind="oracle",
+                   sample=f"first {cf} frames of the mixed stream, {dt:.1f} s wall on {threads} threads",
+                   cpu_model=cpu_model(), affinity_cores=len(os.sched_getaffinity(0)),
+                   one_thread=dict(value=rate1, sample=f"first {c1} frames, {dt1:.1f} s wall"))
+    config = {"workload": "mixed eBCH product frames [32,26]^2/[64,57]^2/[128,120]^2 uniform, BPSK-AWGN Eb/N0 "
+                          f"U[2,4] dB (seed 4), {F} frames, L=4, query cap {qcap}, 6 iterations, alpha 0.5",
+              "form": "batched_f32", "llr_storage": "f32", "frames_per_step": F,
+              "sched": dict(waves_per_group=sc.waves_per_group, frames_per_group=sc.frames_per_group,
+                            steal_chunk=sc.steal_chunk, groups_per_cu=sc.groups_per_cu),
               "parallelism": "single GPU"}
-    return base_line(args, "decoded info bits/s (batched vs plain) at matched BLER", info / (ms_b / 1e3),
-                     "info bits/s", ms_b, "f64", config, roof, cpu,
+    line = base_line(args, "decoded info bits/s (batched/served vs plain) at matched BLER; p99 frame latency",
+                     info / (ms_b / 1e3), "info bits/s", ms_b, "f64", config, roof, cpu,
                      plain_f32=dict(ms_per_step=ms_p, info_bits_per_s=info / (ms_p / 1e3)),
-                     speedup_vs_plain=ms_p / ms_b, identical_to_plain=same, per_code=per_code)
+                     speedup_vs_plain=ms_p / ms_b, identical_to_plain=same, bler_matches_plain=bool(matched),
+                     per_code=per_code)
+    del x, fc, fo, plain_in, pouts
+    bout.clear()
+    return line
+
+
+def bench_headline(args, sg, np, torch, synth):
+    """The metric's own line: the mixed stream (value), the served form (latency) and the
+    [64,57]^2 forms, each under its own config."""
+    line = bench_mixed(args, sg, np, torch, synth)
+    torch.cuda.empty_cache()
+    srv = bench_serve(args, sg, np, torch, synth)
+    torch.cuda.empty_cache()
+    line["served"] = {k: srv[k] for k in ("value", "unit", "config", "p50_frame_latency_ms", "p99_frame_latency_ms",
+                                          "offered_info_bits_per_s", "p99_frame_latency_ms_middle_80pct_arrivals",
+                                          "mean_step_ms", "max_step_ms", "admission_retries", "per_code")}
+    line["served"]["vs_plain"] = srv["value"] / line["plain_f32"]["info_bits_per_s"]
+    line["p50_frame_latency_ms"] = srv["p50_frame_latency_ms"]
+    line["p99_frame_latency_ms"] = srv["p99_frame_latency_ms"]
+    pargs = argparse.Namespace(**vars(args))
+    pargs.frames, pargs.no_cpu = 10000, True
+    prod = bench_product(pargs, sg, np, torch, synth)
+    torch.cuda.empty_cache()
+    line["product_64x57"] = dict(
+        config=prod["config"], value=prod["value"], unit=prod["unit"], roofline=prod["roofline"],
+        forms={k: {kk: vv for kk, vv in v.items() if kk not in ("kernels", "per_snr")} | {"per_snr": v["per_snr"]}
+               for k, v in prod["forms"].items()})
+    return line
 
 
 # --------------------------------------------------------------------------------------------
@@ -536,7 +610,7 @@ def bench_component(args, sg, np, torch, synth):
         import oracle
         from concurrent.futures import ThreadPoolExecutor
         m = min(args.cpu_words, W)
-        threads = min(16, len(os.sched_getaffinity(0)))
+        threads = host_threads()
         sample = llr[:m].astype(np.float32).astype(np.float64)
         parts = np.array_split(sample, threads)
         t0 = time.perf_counter()
@@ -717,7 +791,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="product", choices=["product", "mixed", "component", "serve", "gldpc", "rician"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "product", "mixed", "component", "serve", "gldpc", "rician"])
     ap.add_argument("--frames", type=int, default=None, help="frames per Eb/N0 (product) or in total (mixed)")
     ap.add_argument("--words", type=int, default=1 << 20, help="component words")
     ap.add_argument("--requests", type=int, default=100000, help="serving requests")
@@ -746,7 +821,8 @@ def main() -> int:
     if args.frames is None:
         args.frames = 10000
     if args.cpu_frames is None:
-        args.cpu_frames = {"product": 10000, "mixed": 4000, "gldpc": 3000, "rician": 3000}.get(args.workload, 0)
+        args.cpu_frames = {"product": 10000, "mixed": 3000, "headline": 3000, "gldpc": 3000,
+                           "rician": 3000}.get(args.workload, 0)
 
     import numpy as np
     import torch
@@ -754,8 +830,8 @@ def main() -> int:
     import paper_2310_10737_amd as sg
     import synth
 
-    fn = dict(product=bench_product, mixed=bench_mixed, component=bench_component, serve=bench_serve,
-              gldpc=bench_gldpc, rician=bench_rician)[args.workload]
+    fn = dict(headline=bench_headline, product=bench_product, mixed=bench_mixed, component=bench_component,
+              serve=bench_serve, gldpc=bench_gldpc, rician=bench_rician)[args.workload]
     line = fn(args, sg, np, torch, synth)
     roof = line.get("roofline")
     if roof and roof.get("bound") == "alu":

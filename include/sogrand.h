@@ -202,15 +202,17 @@ void sogrand_sched_default(sogrand_sched_t *s);
    codes may differ.  codes: HOST array of ncodes (1..8) code handles.
    frame_code[f] (DEVICE, uint8) indexes codes; frame_offset[f] (DEVICE) is the
    element offset of frame f's n x n row-major block in llr_ch (DEVICE, llr_len
-   elements, precision per params) and in hard (DEVICE, llr_len bytes).  Per-frame
-   outputs (DEVICE) as in sogrand_decode_product; success is required, the others
-   may be NULL.  status (DEVICE, optional) receives 0, or bit 0 if a wave gave up
-   waiting (not expected) and bit 1 if a frame descriptor was out of range (that
-   frame is skipped with success 0 and half_iters 0).  sched NULL = default.
-   Errors: EINVAL, ENOMEM, EDEVICE. */
+   elements, precision per params), in hard (DEVICE, llr_len bytes: the final hard
+   decision, written once when the frame finishes) and in llr_app (DEVICE, llr_len
+   elements in the params precision, optional: the final L_APP).  Per-frame outputs
+   (DEVICE) as in sogrand_decode_product; success is required, the others may be
+   NULL.  status (DEVICE, optional) receives 0, or bit 0 if a wave gave up waiting
+   (not expected) and bit 1 if a frame descriptor was out of range (that frame is
+   skipped with success 0 and half_iters 0, and its hard and llr_app are not
+   written).  sched NULL = default.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
                            size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
-                           uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                           uint64_t llr_len, const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
                            uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
                            uint32_t *status, const sogrand_sched_t *sched, void *stream);
 
@@ -223,7 +225,8 @@ int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const
    for sogrand_decode_batched. */
 int sogrand_decode_batched_gldpc(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
                                  size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
-                                 uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                                 uint64_t llr_len, const void *llr_ch, uint8_t *hard, void *llr_app,
+                                 uint8_t *success,
                                  uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
                                  uint32_t *status, const sogrand_sched_t *sched, void *stream);
 
@@ -262,11 +265,17 @@ typedef struct {
 /* CLOCK_MONOTONIC in nanoseconds: the clock of the result timestamps. */
 uint64_t sogrand_clock_ns(void);
 
+/* Server flag: keep every frame's L_APP of its last half-iteration and return it
+   with the result (sogrand_serve_poll's llr_app_out_host).  A slot then also holds
+   n*n LLRs of the server's precision. */
+#define SOGRAND_SERVE_APP 1u
+
 /* params as for sogrand_decode_product (precision sets the LLR storage of the
    slots and of llr_ch_host).  hbm_budget_bytes: device memory for slots, at
-   least 1 MiB; the same amount of pinned host memory is allocated.
-   Errors: EINVAL, ENOMEM, EDEVICE. */
-int sogrand_serve_create(const sogrand_params_t *params, size_t hbm_budget_bytes, sogrand_server_t **out);
+   least 1 MiB; the same amount of pinned host memory is allocated.  flags: 0 or
+   SOGRAND_SERVE_APP.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int sogrand_serve_create(const sogrand_params_t *params, size_t hbm_budget_bytes, unsigned flags,
+                         sogrand_server_t **out);
 
 /* Admits one frame: llr_ch_host is HOST memory, n*n LLRs row-major in the
    server's precision, copied before the call returns (the caller keeps it).
@@ -279,11 +288,15 @@ int sogrand_serve_submit(sogrand_server_t *server, const sogrand_code_t *code, c
 /* Takes up to max_results finished requests, oldest first, waiting up to
    timeout_ns (0: do not wait; < 0: until one finishes).  If hard_out_host is
    not NULL it receives each result's n*n hard decisions at hard_offset, packed
-   back to back (at most max_results * 16384 bytes).  Returns SOGRAND_OK with
-   *n_results >= 1, SOGRAND_ETIMEDOUT if none finished in time, SOGRAND_ENOTFOUND
-   if nothing is in flight and nothing is waiting to be taken. */
+   back to back (at most max_results * 16384 bytes).  If llr_app_out_host is not
+   NULL and the server was created with SOGRAND_SERVE_APP, it receives each
+   result's n*n final L_APP (row-major, the server's precision) at element offset
+   hard_offset (at most max_results * 16384 elements); HOST memory, caller-owned.
+   Returns SOGRAND_OK with *n_results >= 1, SOGRAND_ETIMEDOUT if none finished in
+   time, SOGRAND_ENOTFOUND if nothing is in flight and nothing is waiting to be
+   taken. */
 int sogrand_serve_poll(sogrand_server_t *server, sogrand_result_t *results, size_t max_results,
-                       size_t *n_results, uint8_t *hard_out_host, int64_t timeout_ns);
+                       size_t *n_results, uint8_t *hard_out_host, void *llr_app_out_host, int64_t timeout_ns);
 
 /* Open-loop load generator for measurement: submits request i (code
    codes[req_code[i]], LLRs at element offset req_offset[i] of llr_host, HOST

@@ -12,8 +12,8 @@ import os
 
 __all__ = [
     "SograndError", "Code", "params", "sched", "lib", "library_path", "profile_begin", "profile_end",
-    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_gldpc", "sogrand_decode_batched",
-    "sogrand_decode_batched_gldpc", "pack_frames",
+    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_gldpc",
+    "sogrand_decode_batched", "sogrand_decode_batched_gldpc", "pack_frames",
     "Server", "sogrand_clock_ns", "measure_valu_rate", "SOGRAND_F64", "SOGRAND_F32",
 ]
 
@@ -33,6 +33,7 @@ EXPORTS = [
     "sogrand_profile_begin", "sogrand_profile_end", "sogrand_measure_valu_rate",
 ]
 
+SOGRAND_SERVE_APP = 1
 SOGRAND_EAGAIN = -4
 SOGRAND_ENOTFOUND = -5
 SOGRAND_ETIMEDOUT = -6
@@ -133,12 +134,12 @@ def lib():
     L.sogrand_decode_gldpc.argtypes = [P, P, SZ] + [P] * 8
     L.sogrand_sched_default.argtypes = [P]
     L.sogrand_sched_default.restype = None
-    L.sogrand_decode_batched.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 9
-    L.sogrand_decode_batched_gldpc.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 9
+    L.sogrand_decode_batched.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 10
+    L.sogrand_decode_batched_gldpc.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 10
     L.sogrand_clock_ns.restype = ctypes.c_uint64
-    L.sogrand_serve_create.argtypes = [P, SZ, P]
+    L.sogrand_serve_create.argtypes = [P, SZ, ctypes.c_uint, P]
     L.sogrand_serve_submit.argtypes = [P, P, P, ctypes.c_uint64, P]
-    L.sogrand_serve_poll.argtypes = [P, P, SZ, P, P, ctypes.c_int64]
+    L.sogrand_serve_poll.argtypes = [P, P, SZ, P, P, P, ctypes.c_int64]
     L.sogrand_serve_stats.argtypes = [P, P]
     L.sogrand_serve_replay.argtypes = [P, P, I, SZ, P, P, P, ctypes.c_uint64, P, ctypes.c_uint64, P]
     L.sogrand_serve_destroy.argtypes = [P]
@@ -340,29 +341,31 @@ def pack_frames(frames):
 
 
 def sogrand_decode_batched(codes, frame_code, frame_offset, llr, list_max=4, query_cap=1000, max_iter=4,
-                           alpha=0.5, early_stop=True, sched_=None, outputs=None, stream=None, list_bler_stop=0.0):
+                           alpha=0.5, early_stop=True, sched_=None, outputs=None, stream=None, list_bler_stop=0.0,
+                           want_app=False):
     """Batched decode of product frames of mixed codes in one persistent launch.
 
     codes: list of Code; frame_code: (F,) uint8 CUDA tensor of indices into codes;
     frame_offset: (F,) int64 CUDA tensor of element offsets into llr (flat CUDA
     tensor, float64 or float32).  Returns a dict with hard (flat uint8 like llr),
-    success, half_iters, sum_queries, sum_max_queries and status.
+    success, half_iters, sum_queries, sum_max_queries and status; with want_app also
+    llr_app (flat, like llr).
     """
     return _batched(lib().sogrand_decode_batched, codes, frame_code, frame_offset, llr, list_max, query_cap,
-                    max_iter, alpha, early_stop, sched_, outputs, stream, list_bler_stop)
+                    max_iter, alpha, early_stop, sched_, outputs, stream, list_bler_stop, want_app)
 
 
 def sogrand_decode_batched_gldpc(codes, frame_code, frame_offset, llr, list_max=4, query_cap=1000, max_iter=20,
                                  alpha=0.6, early_stop=True, sched_=None, outputs=None, stream=None,
-                                 list_bler_stop=0.0):
+                                 list_bler_stop=0.0, want_app=False):
     """sogrand_decode_batched for QC-GLDPC frames (laid out by variable node, as for
     sogrand_decode_gldpc)."""
     return _batched(lib().sogrand_decode_batched_gldpc, codes, frame_code, frame_offset, llr, list_max, query_cap,
-                    max_iter, alpha, early_stop, sched_, outputs, stream, list_bler_stop)
+                    max_iter, alpha, early_stop, sched_, outputs, stream, list_bler_stop, want_app)
 
 
 def _batched(fn, codes, frame_code, frame_offset, llr, list_max, query_cap, max_iter, alpha, early_stop, sched_,
-             outputs, stream, list_bler_stop):
+             outputs, stream, list_bler_stop, want_app=False):
     import torch
     if not (llr.is_cuda and llr.is_contiguous() and llr.dim() == 1):
         raise ValueError("llr must be a contiguous 1-D CUDA tensor")
@@ -372,6 +375,7 @@ def _batched(fn, codes, frame_code, frame_offset, llr, list_max, query_cap, max_
     dev = llr.device
     out = dict(
         hard=torch.empty(llr.shape, dtype=torch.uint8, device=dev),
+        llr_app=torch.empty_like(llr) if want_app else None,
         success=torch.empty(F, dtype=torch.uint8, device=dev),
         half_iters=torch.empty(F, dtype=torch.int16, device=dev),
         sum_queries=torch.empty(F, dtype=torch.int64, device=dev),
@@ -386,7 +390,8 @@ def _batched(fn, codes, frame_code, frame_offset, llr, list_max, query_cap, max_
     sc = sched_ if sched_ is not None else sched()
     _check(fn(
         handles, len(codes), ctypes.byref(p), F, _ptr(frame_code), _ptr(frame_offset), llr.numel(),
-        _ptr(llr), _ptr(out["hard"]), _ptr(out["success"]), _ptr(out["half_iters"]), _ptr(out["sum_queries"]),
+        _ptr(llr), _ptr(out["hard"]), _ptr(out.get("llr_app")), _ptr(out["success"]), _ptr(out["half_iters"]),
+        _ptr(out["sum_queries"]),
         _ptr(out["sum_max_queries"]), _ptr(out["status"]), ctypes.byref(sc), _stream(stream)))
     return out
 
@@ -413,12 +418,14 @@ class Server:
     """
 
     def __init__(self, hbm_budget_bytes, list_max=4, query_cap=1000, max_iter=4, alpha=0.5, early_stop=True,
-                 precision=SOGRAND_F32, list_bler_stop=0.0):
+                 precision=SOGRAND_F32, list_bler_stop=0.0, export_app=False):
         self._h = ctypes.c_void_p()
         self.precision = precision
+        self.export_app = bool(export_app)
         p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
                    early_stop=early_stop, precision=precision, list_bler_stop=list_bler_stop)
-        _check(lib().sogrand_serve_create(ctypes.byref(p), int(hbm_budget_bytes), ctypes.byref(self._h)))
+        _check(lib().sogrand_serve_create(ctypes.byref(p), int(hbm_budget_bytes),
+                                          SOGRAND_SERVE_APP if export_app else 0, ctypes.byref(self._h)))
 
     def submit(self, code: Code, llr_host, tag: int = 0):
         """Submits one frame; returns its request id, or None if no slot is free (retry after poll)."""
@@ -435,13 +442,18 @@ class Server:
         return rid.value
 
     def poll(self, max_results=256, timeout_ns=0, want_hard=True):
-        """Finished requests as a list of dicts (hard: (n, n) uint8 numpy array when want_hard)."""
+        """Finished requests as a list of dicts (hard: (n, n) uint8 numpy array when want_hard;
+        llr_app: (n, n) numpy array of the server's precision when the server exports it)."""
         import numpy as np
         res = (sogrand_result_t * max_results)()
         hard = np.empty(max_results * 128 * 128, dtype=np.uint8) if want_hard else None
+        app = None
+        if self.export_app:
+            app = np.empty(max_results * 128 * 128, dtype=np.float64 if self.precision == SOGRAND_F64 else np.float32)
         nres = ctypes.c_size_t()
         rc = lib().sogrand_serve_poll(self._h, res, max_results, ctypes.byref(nres),
-                                      None if hard is None else ctypes.c_void_p(hard.ctypes.data), int(timeout_ns))
+                                      None if hard is None else ctypes.c_void_p(hard.ctypes.data),
+                                      None if app is None else ctypes.c_void_p(app.ctypes.data), int(timeout_ns))
         if rc in (SOGRAND_ETIMEDOUT, SOGRAND_ENOTFOUND):
             return []
         _check(rc)
@@ -451,9 +463,11 @@ class Server:
             d = dict(request_id=r.request_id, user_tag=r.user_tag, status=r.status, success=r.success,
                      half_iters=r.half_iters, n=r.n, queries=r.queries, t_submit_ns=r.t_submit_ns,
                      t_admit_ns=r.t_admit_ns, t_done_ns=r.t_done_ns)
+            nn = r.n * r.n
             if hard is not None:
-                nn = r.n * r.n
                 d["hard"] = hard[r.hard_offset:r.hard_offset + nn].reshape(r.n, r.n).copy()
+            if app is not None:
+                d["llr_app"] = app[r.hard_offset:r.hard_offset + nn].reshape(r.n, r.n).copy()
             out.append(d)
         return out
 

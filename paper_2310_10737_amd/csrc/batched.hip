@@ -39,6 +39,7 @@ struct BatchArgs {
     uint64_t llr_len;               // elements of llr_ch / hard
     const void *llr_ch;
     uint8_t *hard;
+    void *llr_app;                  // optional, written every half-iteration (the last one stays)
     uint8_t *success;
     uint16_t *half_iters;
     uint64_t *sumq;
@@ -204,7 +205,7 @@ __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl,
         hm[b] = __ballot(neg);
         if (!v) continue;
         la[pos[b]] = (T)(a.alpha * (lapp[b] - lam[b]));
-        a.hard[off + pos[b]] = neg;
+        if (a.llr_app) static_cast<T *>(a.llr_app)[off + pos[b]] = (T)lapp[b];
     }
     if (lane == 0) {
         sl.masks[line][0] = hm[0];
@@ -245,13 +246,37 @@ __device__ __forceinline__ WordStats batch_pair(const BatchArgs &a, SlotLds &sl,
     const uint64_t hm = __ballot(neg);
     if (v) {
         la[pos] = (T)(a.alpha * (lapp - lam));
-        a.hard[off + pos] = neg;
+        if (a.llr_app) static_cast<T *>(a.llr_app)[off + pos] = (T)lapp;
     }
     if (live && hl == 0) {
         sl.masks[ln][0] = upper ? (hm >> 32) : (hm & 0xffffffffull);
         sl.masks[ln][1] = 0ull;
     }
     return st;
+}
+
+// The frame's hard decision, written once when it retires: bit `bit` of line `line`'s
+// mask after half-iteration h is the decision on that word's bit, and element [j][c]
+// (variable node j*n + c) is bit c of row j or bit j of column c of a product frame, bit j
+// of word c of the first block row or of word (c - j) mod n of the second of a QC-GLDPC
+// frame.  Consecutive lanes write consecutive bytes of a row of the frame.
+template <int TOPO>
+__device__ __forceinline__ void write_hard(uint8_t *hard, const SlotLds &sl, int n, int h, int lane) {
+    const bool rows = (h & 1) != 0;
+    for (int j = 0; j < n; j++) {
+        for (int c = lane; c < n; c += kWave) {
+            int line, bit;
+            if constexpr (TOPO == kProduct) {
+                line = rows ? j : c;
+                bit = rows ? c : j;
+            } else {
+                bit = j;
+                line = rows ? c : (c >= j ? c - j : c - j + n);
+            }
+            const uint64_t w = sl.masks[line][bit >> 6];
+            hard[j * n + c] = (uint8_t)((w >> (bit & 63)) & 1ull);
+        }
+    }
 }
 
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l) {
@@ -370,10 +395,12 @@ void k_batched(BatchArgs a) {
         // this wave finished the half-iteration
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         const bool valid = slot_valid<TOPO>(sl, c, lane, h);
+        const bool retire = (valid && a.early_stop) || h == 2 * a.max_iter;
+        if (retire) write_hard<TOPO>(a.hard + load_uniform(a.frame_offset + frame), sl, n, h, lane);
         if (lane == 0) {
             sl.summax += sl.halfmax;
             sl.halfmax = 0;
-            if ((valid && a.early_stop) || h == 2 * a.max_iter) {
+            if (retire) {
                 a.success[frame] = valid;
                 if (a.half_iters) a.half_iters[frame] = (uint16_t)h;
                 if (a.sumq) a.sumq[frame] = sl.sumq;
@@ -443,7 +470,7 @@ static int check_sched(const sogrand_sched_t *s) {
 
 static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
                           size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
-                          uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                          uint64_t llr_len, const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
                           uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
                           uint32_t *status, const sogrand_sched_t *sched, void *stream) {
     SG_TRY(check_params(params));
@@ -492,6 +519,7 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     a.llr_len = llr_len;
     a.llr_ch = llr_ch;
     a.hard = hard;
+    a.llr_app = llr_app;
     a.success = success;
     a.half_iters = half_iters;
     a.sumq = sum_queries;
@@ -532,21 +560,21 @@ void sogrand_sched_default(sogrand_sched_t *s) {
 
 int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
                            size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
-                           uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                           uint64_t llr_len, const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
                            uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
                            uint32_t *status, const sogrand_sched_t *sched, void *stream) {
     return sg::decode_batched(sg::kProduct, codes, ncodes, params, nframes, frame_code, frame_offset, llr_len,
-                              llr_ch, hard, success, half_iters, sum_queries, sum_max_queries, status, sched,
+                              llr_ch, hard, llr_app, success, half_iters, sum_queries, sum_max_queries, status, sched,
                               stream);
 }
 
 int sogrand_decode_batched_gldpc(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
                                  size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
-                                 uint64_t llr_len, const void *llr_ch, uint8_t *hard, uint8_t *success,
+                                 uint64_t llr_len, const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
                                  uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
                                  uint32_t *status, const sogrand_sched_t *sched, void *stream) {
     return sg::decode_batched(sg::kGldpc, codes, ncodes, params, nframes, frame_code, frame_offset, llr_len,
-                              llr_ch, hard, success, half_iters, sum_queries, sum_max_queries, status, sched,
+                              llr_ch, hard, llr_app, success, half_iters, sum_queries, sum_max_queries, status, sched,
                               stream);
 }
 

@@ -106,7 +106,7 @@ struct ProductArgs {
     int first;              // this launch is the first row pass (no a-priori LLRs yet)
     int topo;               // kProduct or kGldpc
     void *llr_app;          // [F][n][n] or NULL
-    uint8_t *hard;          // [F][n][n]
+    uint8_t *hard;          // [F][n][n], written by the check kernel when the frame finishes
     uint64_t *masks;        // [F][n][2] hard decision of each line of the last pass
     uint32_t *done;         // [F]
     uint32_t *halfmax;      // [F] largest query count of the current half-iteration
@@ -212,7 +212,6 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
         const double le = lapp[b] - lam[b];
         la_out[LN::cross(line, i, n)] = (T)(a.alpha * le);
         if (a.llr_app) static_cast<T *>(a.llr_app)[fo + pos[b]] = (T)lapp[b];
-        a.hard[fo + pos[b]] = neg;
     }
     if (lane == 0) {
         a.masks[((size_t)f * n + line) * 2 + 0] = hm[0];
@@ -270,7 +269,6 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass_pair(ProductArgs a
     if (live && hl < n) {
         la_out[LN::cross(line, hl, n)] = (T)(a.alpha * (lapp - lam));
         if (a.llr_app) static_cast<T *>(a.llr_app)[fo + pos] = (T)lapp;
-        a.hard[fo + pos] = neg;
     }
     if (live && hl == 0) {
         a.masks[((size_t)f * n + line) * 2 + 0] = upper ? (hm >> 32) : (hm & 0xffffffffull);
@@ -281,7 +279,10 @@ __global__ __launch_bounds__(kWave * WPB) void k_product_pass_pair(ProductArgs a
 }
 
 // One wave per frame after half-iteration h: every word of the last pass and every
-// word of the other family must have a zero syndrome.
+// word of the other family must have a zero syndrome.  A frame that finishes gets its
+// hard decision from the last pass's line masks: element [j][c] (variable node j*n + c)
+// is bit c of row j or bit j of column c of a product frame, bit j of word c of the
+// first block row or of word (c - j) mod n of the second of a QC-GLDPC frame.
 __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, int last) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -323,10 +324,28 @@ __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, 
         bad |= (s != 0u) || (t != 0u);
     }
     const bool valid = __ballot(bad) == 0ull;
+    const bool finish = (valid && a.early_stop) || last;
+    if (finish) {
+        const bool rows = (h & 1) != 0;
+        uint8_t *hd = a.hard + f * n * n;
+        for (int j = 0; j < n; j++) {
+            for (int c = lane; c < n; c += kWave) {
+                int line, bit;
+                if (a.topo == kProduct) {
+                    line = rows ? j : c;
+                    bit = rows ? c : j;
+                } else {
+                    bit = j;
+                    line = rows ? c : (c >= j ? c - j : c - j + n);
+                }
+                hd[j * n + c] = (uint8_t)((mk[line * 2 + (bit >> 6)] >> (bit & 63)) & 1ull);
+            }
+        }
+    }
     if (lane == 0) {
         a.summax[f] += a.halfmax[f];
         a.halfmax[f] = 0u;
-        if ((valid && a.early_stop) || last) {
+        if (finish) {
             a.done[f] = 1u;
             a.success[f] = valid;
             a.half_iters[f] = (uint16_t)h;
@@ -425,10 +444,32 @@ int sogrand_decode_component(const sogrand_code_t *code, const sogrand_params_t 
 
 namespace sg {
 
-// The block turbo loop over either family layout (see Lines).
-static int decode_frames(int topo, const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
-                         const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
-                         uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries, void *stream) {
+// Byte layout of the plain path's work buffer for nframes frames of length n:
+// ch_t | la_rm | la_cm | [ch_a] | masks | done | halfmax | sumq | summax | half_iters.
+struct WorkLayout {
+    size_t ct, lr, lc, ca, mk, dn, hm, sq, sm, hi, total;
+};
+
+static WorkLayout work_layout(int topo, size_t nframes, int n, size_t esz) {
+    WorkLayout w;
+    const size_t plane = (nframes * n * n * esz + 255) & ~(size_t)255;
+    w.ct = 0;
+    w.lr = plane;
+    w.lc = 2 * plane;
+    w.ca = 3 * plane;
+    w.mk = (topo == kGldpc ? 4 : 3) * plane;
+    w.dn = (w.mk + nframes * n * 2 * sizeof(uint64_t) + 255) & ~(size_t)255;
+    w.hm = (w.dn + nframes * sizeof(uint32_t) + 255) & ~(size_t)255;
+    w.sq = (w.hm + nframes * sizeof(uint32_t) + 255) & ~(size_t)255;
+    w.sm = (w.sq + nframes * sizeof(uint64_t) + 255) & ~(size_t)255;
+    w.hi = (w.sm + nframes * sizeof(uint64_t) + 255) & ~(size_t)255;
+    w.total = w.hi + nframes * sizeof(uint16_t);
+    return w;
+}
+
+// Argument checks shared by the product and QC-GLDPC entry points.
+static int check_frames(const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
+                        const void *llr_ch, const uint8_t *hard, const uint8_t *success) {
     SG_TRY(check_params(params));
     if (!code) return fail(SOGRAND_EINVAL, "code is NULL");
     if (nframes == 0) return SOGRAND_OK;
@@ -437,77 +478,88 @@ static int decode_frames(int topo, const sogrand_code_t *code, const sogrand_par
     const size_t words = nframes * (size_t)n;
     if (nframes > ((size_t)1 << 34) / ((size_t)n * n) || words >= ((size_t)1 << 31))
         return fail(SOGRAND_EINVAL, "nframes too large");
+    return SOGRAND_OK;
+}
+
+// The block turbo loop over either family layout (see Lines), in the work buffer ws
+// laid out by work_layout; `prof` false launches without the measurement hooks.
+static int run_frames(int topo, const DevCode &dc, const sogrand_params_t *params, size_t nframes,
+                      const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success, uint16_t *half_iters,
+                      uint64_t *sum_queries, uint64_t *sum_max_queries, char *ws, hipStream_t st, bool prof) {
+    const int n = dc.n;
+    const size_t words = nframes * (size_t)n;
     const int ns = sort_width(n);
     // words of up to 32 bits go two to a wave
     const size_t blocks = word_grid(ns == 32 ? (words + 1) / 2 : words);
-    if (blocks > 0x7fffffffull) return fail(SOGRAND_EINVAL, "nframes too large for one launch");
-    ProductArgs a;
-    SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &a.code));
-    hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t esz = params->precision == SOGRAND_F64 ? sizeof(double) : sizeof(float);
-    // work buffer layout: ch_t | la_rm | la_cm | [ch_a] | masks | done | halfmax | sumq | summax | half_iters
-    const size_t plane = (nframes * n * n * esz + 255) & ~(size_t)255;
-    const size_t off_ct = 0, off_lr = plane, off_lc = 2 * plane, off_ca = 3 * plane;
-    const size_t off_mk = (topo == kGldpc ? 4 : 3) * plane;
-    const size_t off_dn = (off_mk + nframes * n * 2 * sizeof(uint64_t) + 255) & ~(size_t)255;
-    const size_t off_hm = (off_dn + nframes * sizeof(uint32_t) + 255) & ~(size_t)255;
-    const size_t off_sq = (off_hm + nframes * sizeof(uint32_t) + 255) & ~(size_t)255;
-    const size_t off_sm = (off_sq + nframes * sizeof(uint64_t) + 255) & ~(size_t)255;
-    const size_t off_hi = (off_sm + nframes * sizeof(uint64_t) + 255) & ~(size_t)255;
-    const size_t total = off_hi + nframes * sizeof(uint16_t);
-    char *ws = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
-        return fail(SOGRAND_ENOMEM, "work buffer allocation of %zu bytes failed", total);
+    const WorkLayout w = work_layout(topo, nframes, n, esz);
+    ProductArgs a;
+    a.code = dc;
     a.L = params->list_max;
     a.qcap = params->query_cap;
     a.pstop = params->list_bler_stop;
     a.alpha = params->alpha;
     a.nframes = nframes;
     a.llr_ch = llr_ch;
-    a.ch_t = ws + off_ct;
-    a.la_rm = ws + off_lr;
-    a.la_cm = ws + off_lc;
-    a.ch_a = topo == kGldpc ? ws + off_ca : nullptr;
+    a.ch_t = ws + w.ct;
+    a.la_rm = ws + w.lr;
+    a.la_cm = ws + w.lc;
+    a.ch_a = topo == kGldpc ? ws + w.ca : nullptr;
     a.first = 0;
     a.topo = topo;
     a.llr_app = llr_app;
     a.hard = hard;
-    a.masks = reinterpret_cast<uint64_t *>(ws + off_mk);
-    a.done = reinterpret_cast<uint32_t *>(ws + off_dn);
-    a.halfmax = reinterpret_cast<uint32_t *>(ws + off_hm);
-    a.sumq = sum_queries ? sum_queries : reinterpret_cast<uint64_t *>(ws + off_sq);
-    a.summax = sum_max_queries ? sum_max_queries : reinterpret_cast<uint64_t *>(ws + off_sm);
+    a.masks = reinterpret_cast<uint64_t *>(ws + w.mk);
+    a.done = reinterpret_cast<uint32_t *>(ws + w.dn);
+    a.halfmax = reinterpret_cast<uint32_t *>(ws + w.hm);
+    a.sumq = sum_queries ? sum_queries : reinterpret_cast<uint64_t *>(ws + w.sq);
+    a.summax = sum_max_queries ? sum_max_queries : reinterpret_cast<uint64_t *>(ws + w.sm);
     a.success = success;
-    a.half_iters = half_iters ? half_iters : reinterpret_cast<uint16_t *>(ws + off_hi);
+    a.half_iters = half_iters ? half_iters : reinterpret_cast<uint16_t *>(ws + w.hi);
     a.early_stop = params->early_stop ? 1 : 0;
-    a.prof = prof_counters(PK_PASS);
+    a.prof = prof ? prof_counters(PK_PASS) : nullptr;
     const bool f64 = params->precision == SOGRAND_F64;
-    int rc = SOGRAND_OK;
-    {
-        const size_t ib = (nframes + kBlock - 1) / kBlock;
-        const unsigned ig = (unsigned)(ib < 65536 ? ib : 65536);
-        int tok = prof_start(PK_INIT, st);
-        hipLaunchKernelGGL(k_product_init, dim3(ig), dim3(kBlock), 0, st, a);
-        prof_stop(tok, st);
-        const unsigned cg = (unsigned)((nframes + kWavesPerBlock - 1) / kWavesPerBlock);
-        for (int h = 1; h <= 2 * params->max_iter; h++) {
-            const bool rows = (h & 1) != 0;
-            a.first = h == 1 ? 1 : 0;
-            tok = prof_start(PK_PASS, st);
-            if (f64) {
-                if (rows) launch_pass<double, true>(a, ns, dim3((unsigned)blocks), st);
-                else launch_pass<double, false>(a, ns, dim3((unsigned)blocks), st);
-            } else {
-                if (rows) launch_pass<float, true>(a, ns, dim3((unsigned)blocks), st);
-                else launch_pass<float, false>(a, ns, dim3((unsigned)blocks), st);
-            }
-            prof_stop(tok, st);
-            tok = prof_start(PK_CHECK, st);
-            hipLaunchKernelGGL(k_product_check, dim3(cg), dim3(kBlock), 0, st, a, h, h == 2 * params->max_iter ? 1 : 0);
-            prof_stop(tok, st);
+    const size_t ib = (nframes + kBlock - 1) / kBlock;
+    const unsigned ig = (unsigned)(ib < 65536 ? ib : 65536);
+    int tok = prof ? prof_start(PK_INIT, st) : -1;
+    hipLaunchKernelGGL(k_product_init, dim3(ig), dim3(kBlock), 0, st, a);
+    prof_stop(tok, st);
+    const unsigned cg = (unsigned)((nframes + kWavesPerBlock - 1) / kWavesPerBlock);
+    for (int h = 1; h <= 2 * params->max_iter; h++) {
+        const bool rows = (h & 1) != 0;
+        a.first = h == 1 ? 1 : 0;
+        tok = prof ? prof_start(PK_PASS, st) : -1;
+        if (f64) {
+            if (rows) launch_pass<double, true>(a, ns, dim3((unsigned)blocks), st);
+            else launch_pass<double, false>(a, ns, dim3((unsigned)blocks), st);
+        } else {
+            if (rows) launch_pass<float, true>(a, ns, dim3((unsigned)blocks), st);
+            else launch_pass<float, false>(a, ns, dim3((unsigned)blocks), st);
         }
-        if (hipGetLastError() != hipSuccess) rc = fail(SOGRAND_EDEVICE, "product kernel launch failed");
+        prof_stop(tok, st);
+        tok = prof ? prof_start(PK_CHECK, st) : -1;
+        hipLaunchKernelGGL(k_product_check, dim3(cg), dim3(kBlock), 0, st, a, h, h == 2 * params->max_iter ? 1 : 0);
+        prof_stop(tok, st);
     }
+    if (hipGetLastError() != hipSuccess) return fail(SOGRAND_EDEVICE, "product kernel launch failed");
+    return SOGRAND_OK;
+}
+
+static int decode_frames(int topo, const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
+                         const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
+                         uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries, void *stream) {
+    SG_TRY(check_frames(code, params, nframes, llr_ch, hard, success));
+    if (nframes == 0) return SOGRAND_OK;
+    DevCode dc;
+    SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &dc));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t esz = params->precision == SOGRAND_F64 ? sizeof(double) : sizeof(float);
+    const WorkLayout w = work_layout(topo, nframes, code->n, esz);
+    char *ws = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&ws), w.total, st) != hipSuccess)
+        return fail(SOGRAND_ENOMEM, "work buffer allocation of %zu bytes failed", w.total);
+    const int rc = run_frames(topo, dc, params, nframes, llr_ch, hard, llr_app, success, half_iters, sum_queries,
+                              sum_max_queries, ws, st, true);
     (void)hipFreeAsync(ws, st);
     return rc;
 }

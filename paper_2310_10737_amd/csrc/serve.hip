@@ -54,16 +54,20 @@ struct ServeOut {
     uint64_t queries; // patterns tested in this step
 };
 
-// Byte layout of a frame's slot for code length n and element size esz.
+// Byte layout of a frame's slot for code length n and element size esz, in device
+// memory and in its pinned host copy alike: channel LLRs (carried in by the host copy),
+// a-priori LLRs, the last pass's L_APP when the server exports it, the hard decision
+// (carried out by the host copy) and the line masks.
 struct SlotLayout {
-    size_t la, hard, masks, bytes;
+    size_t la, app, hard, masks, bytes;
 };
 
-__host__ __device__ inline SlotLayout slot_layout(int n, size_t esz) {
+__host__ __device__ inline SlotLayout slot_layout(int n, size_t esz, bool app) {
     SlotLayout s;
     const size_t nn = (size_t)n * n;
     s.la = nn * esz;
-    s.hard = 2 * nn * esz;
+    s.app = 2 * nn * esz;
+    s.hard = s.app + (app ? nn * esz : 0);
     s.masks = (s.hard + nn + 15) & ~(size_t)15;
     s.bytes = (s.masks + (size_t)n * 2 * sizeof(uint64_t) + 255) & ~(size_t)255;
     return s;
@@ -85,6 +89,7 @@ struct ServeArgs {
     double alpha;
     int max_iter;
     int early_stop;
+    int app;                  // keep each frame's L_APP and export it with the result
     ProfCounters *prof;
 };
 
@@ -111,11 +116,11 @@ __global__ __launch_bounds__(kBlock) void k_serve_pass(ServeArgs a) {
     const DevCode c = load_uniform(cdev);
     const int n = d.n;
     const int line = (int)(gl - d.line0);
-    const SlotLayout sl = slot_layout(n, sizeof(T));
+    const SlotLayout sl = slot_layout(n, sizeof(T), a.app != 0);
     char *slot = a.arena + d.slot;
     T *ch = reinterpret_cast<T *>(slot);
     T *la = reinterpret_cast<T *>(slot + sl.la);
-    uint8_t *hard = reinterpret_cast<uint8_t *>(slot + sl.hard);
+    T *app = reinterpret_cast<T *>(slot + sl.app);
     uint64_t *mk = reinterpret_cast<uint64_t *>(slot + sl.masks);
     const bool rows = (d.h & 1u) != 0;
     const T *src = reinterpret_cast<const T *>(a.mirror + d.slot);
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_pass(ServeArgs a) {
         hm[b] = __ballot(neg);
         if (!v) continue;
         la[pos[b]] = (T)(a.alpha * (lapp[b] - lam[b]));
-        hard[pos[b]] = neg;
+        if (a.app) app[pos[b]] = (T)lapp[b];
     }
     if (lane == 0) {
         mk[line * 2 + 0] = hm[0];
@@ -162,7 +167,9 @@ __global__ __launch_bounds__(kBlock) void k_serve_pass(ServeArgs a) {
 
 // One wave per frame of the step: validity of the hard decision (every line of
 // the last pass and every cross line a codeword), the frame's outcome into host
-// memory, and for a finished frame its hard decision into the host copy.
+// memory, and for a finished frame its hard decision (from the last pass's line
+// masks: bit c of row j or bit j of column c is element [j][c]) and, when exported,
+// its L_APP into the host copy.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
     if (i >= a.nact) return;
     const ServeDesc d = load_uniform(a.desc + i);
     const int n = d.n;
-    const SlotLayout sl = slot_layout(n, sizeof(T));
+    const SlotLayout sl = slot_layout(n, sizeof(T), a.app != 0);
     const char *slot = a.arena + d.slot;
     const uint64_t *mk = reinterpret_cast<const uint64_t *>(slot + sl.masks);
     const uint32_t *hcol = load_uniform(&a.codes[d.code].hcol);
@@ -202,15 +209,40 @@ __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
     const bool valid = __ballot(bad) == 0ull;
     const bool finished = (valid && a.early_stop) || d.h == (uint32_t)(2 * a.max_iter);
     if (finished) {
-        // 16-byte copies when n is a multiple of 4 (n*n a multiple of 16), else bytes
-        const size_t nn = (size_t)n * n;
-        const uint8_t *hs = reinterpret_cast<const uint8_t *>(slot + sl.hard);
+        const bool rows = (d.h & 1u) != 0;
         uint8_t *hd = reinterpret_cast<uint8_t *>(a.mirror_w + d.slot + sl.hard);
-        if ((nn & 15) == 0) {
-            for (size_t o = (size_t)lane * 16; o < nn; o += kWave * 16)
-                *reinterpret_cast<uint4 *>(hd + o) = *reinterpret_cast<const uint4 *>(hs + o);
+        // four elements of a row per lane and store when n is a multiple of 4, else one
+        if ((n & 3) == 0) {
+            for (int j = 0; j < n; j++) {
+                for (int c = 4 * lane; c < n; c += 4 * kWave) {
+                    uint32_t v = 0;
+                    for (int e = 0; e < 4; e++) {
+                        const int line = rows ? j : c + e, bit = rows ? c + e : j;
+                        v |= (uint32_t)((mk_s[wave][line * 2 + (bit >> 6)] >> (bit & 63)) & 1ull) << (8 * e);
+                    }
+                    *reinterpret_cast<uint32_t *>(hd + j * n + c) = v;
+                }
+            }
         } else {
-            for (size_t o = lane; o < nn; o += kWave) hd[o] = hs[o];
+            for (int j = 0; j < n; j++) {
+                for (int c = lane; c < n; c += kWave) {
+                    const int line = rows ? j : c, bit = rows ? c : j;
+                    hd[j * n + c] = (uint8_t)((mk_s[wave][line * 2 + (bit >> 6)] >> (bit & 63)) & 1ull);
+                }
+            }
+        }
+        if (a.app) {
+            // 16-byte copies: n*n*sizeof(T) is a multiple of 16 when n is even, else 4-byte words
+            const size_t bytes = (size_t)n * n * sizeof(T);
+            const char *as = slot + sl.app;
+            char *ad = a.mirror_w + d.slot + sl.app;
+            if ((bytes & 15) == 0) {
+                for (size_t o = (size_t)lane * 16; o < bytes; o += kWave * 16)
+                    *reinterpret_cast<uint4 *>(ad + o) = *reinterpret_cast<const uint4 *>(as + o);
+            } else {
+                for (size_t o = (size_t)lane * 4; o < bytes; o += kWave * 4)
+                    *reinterpret_cast<uint32_t *>(ad + o) = *reinterpret_cast<const uint32_t *>(as + o);
+            }
         }
     }
     if (lane == 0) {
@@ -246,6 +278,7 @@ struct sogrand_server {
     struct Done {
         sogrand_result_t r;
         std::vector<uint8_t> hard;
+        std::vector<uint8_t> app;   // n*n LLRs in the server's precision, when exported
     };
 
     // one step loop: its thread, stream and per-step tables
@@ -263,6 +296,7 @@ struct sogrand_server {
     sogrand_params_t params{};
     int device = 0;
     size_t esz = 8;
+    bool app = false;             // SOGRAND_SERVE_APP
     size_t budget = 0;
     char *arena = nullptr;        // device slots
     char *mirror = nullptr;       // pinned host copy (host pointer)
@@ -363,6 +397,7 @@ int sogrand_server::step(Lane &ln, std::vector<Req> &active) {
     a.alpha = params.alpha;
     a.max_iter = params.max_iter;
     a.early_stop = params.early_stop ? 1 : 0;
+    a.app = app ? 1 : 0;
     a.prof = prof_counters(PK_SERVE);
     for (int c = 0; c < 3; c++) {
         const uint32_t cnt = gstart[c + 1] - gstart[c];
@@ -408,9 +443,13 @@ int sogrand_server::step(Lane &ln, std::vector<Req> &active) {
             dn.r.t_submit_ns = r.t_submit;
             dn.r.t_admit_ns = r.t_admit;
             dn.r.t_done_ns = t1;
-            const SlotLayout sl = slot_layout(r.n, esz);
+            const SlotLayout sl = slot_layout(r.n, esz, app);
             const uint8_t *src = reinterpret_cast<const uint8_t *>(mirror + r.slot + sl.hard);
             dn.hard.assign(src, src + (size_t)r.n * r.n);
+            if (app) {
+                const uint8_t *as = reinterpret_cast<const uint8_t *>(mirror + r.slot + sl.app);
+                dn.app.assign(as, as + (size_t)r.n * r.n * esz);
+            }
             fin.push_back(std::move(dn));
             is_done[order[j]] = 1;
         } else {
@@ -515,18 +554,21 @@ extern "C" {
 
 uint64_t sogrand_clock_ns(void) { return sg::clock_ns(); }
 
-int sogrand_serve_create(const sogrand_params_t *params, size_t hbm_budget_bytes, sogrand_server_t **out) {
+int sogrand_serve_create(const sogrand_params_t *params, size_t hbm_budget_bytes, unsigned flags,
+                         sogrand_server_t **out) {
     using namespace sg;
     if (!out) return fail(SOGRAND_EINVAL, "out is NULL");
     *out = nullptr;
     SG_TRY(check_params(params));
     if (hbm_budget_bytes < kServeMinBudget) return fail(SOGRAND_EINVAL, "hbm_budget_bytes below 1 MiB");
+    if (flags & ~(unsigned)SOGRAND_SERVE_APP) return fail(SOGRAND_EINVAL, "unknown flags 0x%x", flags);
     sogrand_server_t *s = new (std::nothrow) sogrand_server_t();
     if (!s) return fail(SOGRAND_ENOMEM, "server allocation failed");
     s->params = *params;
     s->esz = params->precision == SOGRAND_F64 ? 8 : 4;
+    s->app = (flags & SOGRAND_SERVE_APP) != 0;
     s->budget = hbm_budget_bytes & ~(size_t)255;
-    for (int c = 0; c < 3; c++) s->class_bytes[c] = slot_layout(class_width(c), s->esz).bytes;
+    for (int c = 0; c < 3; c++) s->class_bytes[c] = slot_layout(class_width(c), s->esz, s->app).bytes;
     s->max_active = s->budget / s->class_bytes[0] + 1;
     auto cleanup = [s](int rc) {
         s->release();
@@ -643,7 +685,7 @@ int sogrand_serve_submit(sogrand_server_t *s, const sogrand_code_t *code, const 
 }
 
 int sogrand_serve_poll(sogrand_server_t *s, sogrand_result_t *results, size_t max_results, size_t *n_results,
-                       uint8_t *hard_out_host, int64_t timeout_ns) {
+                       uint8_t *hard_out_host, void *llr_app_out_host, int64_t timeout_ns) {
     using namespace sg;
     if (!s || !results || !n_results || max_results == 0)
         return fail(SOGRAND_EINVAL, "server, results, n_results and max_results > 0 are required");
@@ -663,6 +705,8 @@ int sogrand_serve_poll(sogrand_server_t *s, sogrand_result_t *results, size_t ma
         results[k] = d.r;
         results[k].hard_offset = off;
         if (hard_out_host && !d.hard.empty()) std::memcpy(hard_out_host + off, d.hard.data(), d.hard.size());
+        if (llr_app_out_host && !d.app.empty())
+            std::memcpy(static_cast<char *>(llr_app_out_host) + off * s->esz, d.app.data(), d.app.size());
         off += (size_t)d.r.n * d.r.n;
         s->done.pop_front();
         k++;

@@ -100,12 +100,10 @@ def compare_product(g, r, f32=False, label="", topo=0):
     pass's kappa-sized error reaches the last pass's inputs through L_A = alpha L_E.  Returns
     the worst ratio to the bound with the last pass's own kappa in place of kappa_traj, the
     fraction of elements beyond that tighter bound, and the kappa-branch fractions."""
-    np.testing.assert_array_equal(g["success"], r["success"], err_msg=label)
-    np.testing.assert_array_equal(g["half_iters"].astype(np.int64), r["half_iters"].astype(np.int64), err_msg=label)
-    np.testing.assert_array_equal(g["sum_queries"].astype(np.int64), r["sum_queries"].astype(np.int64), err_msg=label)
-    np.testing.assert_array_equal(g["sum_max_queries"].astype(np.int64), r["sum_max_queries"].astype(np.int64),
-                                  err_msg=label)
-    np.testing.assert_array_equal(g["hard"], r["hard"], err_msg=label)
+    for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
+        if g.get(key) is not None:   # the served form reports no per-half maxima
+            np.testing.assert_array_equal(g[key].astype(np.int64), r[key].astype(np.int64), err_msg=f"{label}: {key}")
+    np.testing.assert_array_equal(g["hard"].reshape(r["hard"].shape), r["hard"], err_msg=label)
     stats = dict(frames=int(r["success"].shape[0]))
     if g.get("llr_app") is None or r.get("llr_app") is None:
         return stats

@@ -128,21 +128,21 @@ def test_batched_rejects_bad_arguments_before_device_work(sg):
     one = (ctypes.c_void_p * 1)(code.handle)
     sc = sg.sched()
     args = [one, 1, ctypes.byref(p), 4, ctypes.c_void_p(1), ctypes.c_void_p(1), 4096, ctypes.c_void_p(1),
-            ctypes.c_void_p(1), ctypes.c_void_p(1), None, None, None, None, ctypes.byref(sc), None]
+            ctypes.c_void_p(1), None, ctypes.c_void_p(1), None, None, None, None, ctypes.byref(sc), None]
     bad_ncodes = list(args)
     bad_ncodes[1] = 0
     assert L.sogrand_decode_batched(*bad_ncodes) == -1
     bad_ncodes[1] = 9
     assert L.sogrand_decode_batched(*bad_ncodes) == -1
     no_success = list(args)
-    no_success[9] = None
+    no_success[10] = None
     assert L.sogrand_decode_batched(*no_success) == -1
     for field, value in (("waves_per_group", 5), ("frames_per_group", 0), ("frames_per_group", 9),
                          ("steal_chunk", 0), ("groups_per_cu", 0)):
         bad = sg.sched()
         setattr(bad, field, value)
         a = list(args)
-        a[14] = ctypes.byref(bad)
+        a[15] = ctypes.byref(bad)
         assert L.sogrand_decode_batched(*a) == -1, field
     empty = list(args)
     empty[3] = 0
@@ -153,18 +153,19 @@ def test_serving_rejects_bad_arguments_before_device_work(sg):
     L = sg.lib()
     p = sg.params()
     out = ctypes.c_void_p()
-    assert L.sogrand_serve_create(ctypes.byref(p), 1 << 10, ctypes.byref(out)) == -1   # budget below 1 MiB
-    assert L.sogrand_serve_create(ctypes.byref(p), 1 << 30, None) == -1
+    assert L.sogrand_serve_create(ctypes.byref(p), 1 << 10, 0, ctypes.byref(out)) == -1   # budget below 1 MiB
+    assert L.sogrand_serve_create(ctypes.byref(p), 1 << 30, 0, None) == -1
+    assert L.sogrand_serve_create(ctypes.byref(p), 1 << 30, 2, ctypes.byref(out)) == -1   # unknown flag
     bad = sg.params()
     bad.list_max = 0
-    assert L.sogrand_serve_create(ctypes.byref(bad), 1 << 30, ctypes.byref(out)) == -1
+    assert L.sogrand_serve_create(ctypes.byref(bad), 1 << 30, 0, ctypes.byref(out)) == -1
     assert not out.value
     rid = ctypes.c_uint64()
     code = sg.Code.ebch(32, 26)
     assert L.sogrand_serve_submit(None, code.handle, ctypes.c_void_p(1), 0, ctypes.byref(rid)) == -1
     res = (sg.sogrand_result_t * 2)()
     n = ctypes.c_size_t()
-    assert L.sogrand_serve_poll(None, res, 2, ctypes.byref(n), None, 0) == -1
+    assert L.sogrand_serve_poll(None, res, 2, ctypes.byref(n), None, None, 0) == -1
     assert L.sogrand_serve_stats(None, None) == -1
     assert L.sogrand_serve_destroy(None) == 0
     assert L.sogrand_clock_ns() > 0

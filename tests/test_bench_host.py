@@ -65,5 +65,5 @@ def test_every_workload_is_selectable():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 0
-    for w in ("product", "mixed", "component", "serve", "gldpc", "rician"):
+    for w in ("headline", "product", "mixed", "component", "serve", "gldpc", "rician"):
         assert w in r.stdout

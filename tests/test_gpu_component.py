@@ -8,6 +8,7 @@ import pytest
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import oracle  # noqa: E402
 import synth  # noqa: E402
+from codes import small_code  # noqa: E402
 from parity import compare_component  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -84,22 +85,6 @@ def test_edge_cases(sg):
     for W in (1, 2, 3, 5, 63, 65):
         llr, _, _ = synth.component_words(c64, 2.5, 100 + W, np.arange(W))
         run_pair(sg, c64, llr, 4, 500, label=f"ragged {W}")
-
-
-def small_code(n, k, even, seed):
-    """A systematic [n, k] code with random parity part, no bit that is 0 in every codeword, and
-    rows of even weight when `even`."""
-    rng = np.random.default_rng(seed)
-    while True:
-        P = rng.integers(0, 2, size=(k, n - k)).astype(np.uint8)
-        if even:
-            P[:, -1] = (1 + P[:, :-1].sum(1)) % 2
-        elif np.all((1 + P.sum(1)) % 2 == 0):
-            P[0, -1] ^= 1
-        if np.all(P.any(0)):
-            break
-    G = np.concatenate([np.eye(k, dtype=np.uint8), P], axis=1)
-    return synth.code_from_generator(f"[{n},{k}]{'e' if even else ''}", G, list(range(k)))
 
 
 @pytest.mark.parametrize("n,k,even", [(8, 3, True), (16, 3, True), (12, 3, False)])
