@@ -54,6 +54,7 @@ class sogrand_kernel_stat_t(ctypes.Structure):
         ("queries", ctypes.c_uint64),
         ("ranks", ctypes.c_uint64),
         ("exact_rank", ctypes.c_uint64),
+        ("phase_cycles", ctypes.c_uint64 * 7),
     ]
 
 
@@ -210,7 +211,9 @@ def profile_end():
     _check(lib().sogrand_profile_end(arr, 16, ctypes.byref(n)))
     return {arr[i].kernel.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms, words=arr[i].words,
                                          queries=arr[i].queries, ranks=arr[i].ranks,
-                                         exact_rank=arr[i].exact_rank) for i in range(n.value)}
+                                         exact_rank=arr[i].exact_rank,
+                                         phase_cycles=[int(x) for x in arr[i].phase_cycles])
+            for i in range(n.value)}
 
 
 def params(list_max=4, query_cap=1000, alpha=0.5, max_iter=4, early_stop=True, precision=SOGRAND_F64,

@@ -141,13 +141,13 @@ __device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, 
         uint32_t s = 0;
         for (int i = 0; i < n; i++) {
             const uint64_t bit = i < 64 ? (m0 >> i) & 1ull : (m1 >> (i - 64)) & 1ull;
-            if (bit) s ^= c.hcol[i];
+            if (bit) s ^= gptr(c.hcol)[i];
         }
         uint32_t t = 0;
         if constexpr (TOPO == kProduct) {
             for (int l = 0; l < n; l++) {
                 const uint64_t w = x < 64 ? sl.masks[l][0] : sl.masks[l][1];
-                if ((w >> (x & 63)) & 1ull) t ^= c.hcol[l];
+                if ((w >> (x & 63)) & 1ull) t ^= gptr(c.hcol)[l];
             }
         } else {
             const bool after_first = (h & 1) != 0;
@@ -156,7 +156,7 @@ __device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, 
                 if (src >= n) src -= n;
                 if (src < 0) src += n;
                 const uint64_t w = l < 64 ? sl.masks[src][0] : sl.masks[src][1];
-                if ((w >> (l & 63)) & 1ull) t ^= c.hcol[l];
+                if ((w >> (l & 63)) & 1ull) t ^= gptr(c.hcol)[l];
             }
         }
         bad |= (s != 0u) || (t != 0u);
@@ -308,6 +308,9 @@ void k_batched(BatchArgs a) {
     __syncthreads();
     T *la_base = static_cast<T *>(a.la) + (size_t)blockIdx.x * nslots * a.nmax * a.nmax;
     uint32_t idle = 0;
+#ifdef SG_PHASE_CLOCKS
+    uint64_t t_free = __builtin_amdgcn_s_memtime();   // end of this wave's last line of work
+#endif
     int start = wave % nslots;
     for (;;) {
         // steal a range of lines from any slot with unclaimed lines
@@ -374,8 +377,18 @@ void k_batched(BatchArgs a) {
         } else {
             for (int line = first; line < last; line++) {
                 WordStats st;
+                SG_CLOCK(l0);
                 if (NSMAX == 64 || n <= 64) st = batch_line<T, 64, STOP, TOPO>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
                 else st = batch_line<T, 128, STOP, TOPO>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
+#ifdef SG_PHASE_CLOCKS
+                SG_CLOCK(l1);
+                uint32_t inner = 0;
+                for (int q = 0; q < 5; q++) inner += st.phase[q];
+                st.phase[5] = (uint32_t)(l1 - l0) - inner;
+                // the time since this wave's previous line, less the line itself: finding work
+                st.phase[6] = (uint32_t)(l0 - t_free);
+                t_free = l1;
+#endif
                 if (a.prof && lane == 0) prof_add(a.prof, st);
                 qsum += st.Q;
                 qmax = st.Q > qmax ? st.Q : qmax;

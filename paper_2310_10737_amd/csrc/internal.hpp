@@ -88,8 +88,16 @@ int check_params(const sogrand_params_t *p);
 // ----------------------------------------------------------------------------
 enum ProfKind { PK_COMPONENT = 0, PK_PASS, PK_CHECK, PK_INIT, PK_BATCHED, PK_SERVE, PK_COUNT };
 
+// Phases of a component decode timed by builds with SG_PHASE_CLOCKS (wave clock cycles):
+// hard decision, syndrome and rho; ranking; class masses; query loop; soft output; the
+// rest of the line's work in the kernel (reading the inputs, writing the outputs); and, in
+// the persistent kernel, the time a wave spends finding work (claims, frame hand-over,
+// validity checks and waiting).
+constexpr int kPhases = 7;
+
 struct ProfCounters {
     unsigned long long words, queries, ranks, exact_rank;   // exact_rank: words that needed the exact ranking pass
+    unsigned long long phase[kPhases];                       // SG_PHASE_CLOCKS builds only
 };
 // Each kernel family owns kProfSlots counter slots; a workgroup adds to slot
 // blockIdx.x % kProfSlots so that the atomics do not contend on one address.

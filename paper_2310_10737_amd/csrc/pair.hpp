@@ -105,7 +105,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
     const int ybit = valid && lam < 0.0;
     const uint64_t yb = __ballot(ybit);
     const int par = __popc(upper ? (uint32_t)(yb >> 32) : (uint32_t)yb) & 1;
-    const uint32_t s0 = half_xor(ybit ? c.hcol[hl] : 0u);
+    const uint32_t s0 = half_xor(ybit ? gptr(c.hcol)[hl] : 0u);
     const double a = fabs(lam);
     const uint64_t key = valid ? (uint64_t)__double_as_longlong(a) : ~0ull;
     const double rho = valid ? exp_neg<TABLE>(a) : 0.0;
@@ -130,7 +130,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
     }
     const int myrank = valid ? (int)cnt + 1 : 0;
     if (valid) {
-        S.ent_r[myrank].z = c.hcol[hl];
+        S.ent_r[myrank].z = gptr(c.hcol)[hl];
         put_rho(S, myrank, rho);
         S.pi_r[myrank] = (uint8_t)hl;
     } else {
@@ -161,14 +161,14 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
 
     // 4. query loop: each half tests 32 patterns of its word's class schedule per round
     const int cls = c.even ? par : 0;
-    const uint4 *tab = cls ? c.pat[1] : c.pat[0];
+    const auto *tab = gptr(cls ? c.pat[1] : c.pat[0]);
     const uint32_t len = cls ? c.len[1] : c.len[0];
     const uint32_t limit = skip ? 0u : (qcap < len ? qcap : len);
     const uint32_t lim0 = __builtin_amdgcn_readlane(limit, 0), lim1 = __builtin_amdgcn_readlane(limit, 32);
     const uint32_t lim_max = lim0 > lim1 ? lim0 : lim1;
     const int cls0 = __builtin_amdgcn_readlane(cls, 0), cls1 = __builtin_amdgcn_readlane(cls, 32);
-    const uint32_t *wm0 = cls0 ? c.wmax[1] : c.wmax[0];
-    const uint32_t *wm1 = cls1 ? c.wmax[1] : c.wmax[0];
+    const auto *wm0 = gptr(cls0 ? c.wmax[1] : c.wmax[0]);
+    const auto *wm1 = gptr(cls1 ? c.wmax[1] : c.wmax[0]);
     bool done = limit == 0u;
     bool stopped = false;
     int found = 0;
@@ -176,13 +176,13 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
     double s_lane = 0.0;
     uint32_t w_lane = 0;
     uint4 e_next = make_uint4(0u, 0u, 0u, 0u);
-    if ((uint32_t)hl < limit) e_next = tab[hl];
+    if ((uint32_t)hl < limit) e_next = gload(tab, hl);
     for (uint32_t base = 0; base < lim_max; base += 32) {
         // both words have stopped
         if (__ballot(!done) == 0ull) break;
         const uint4 e = e_next;
         e_next = make_uint4(0u, 0u, 0u, 0u);
-        if (!done && base + 32u + (uint32_t)hl < limit) e_next = tab[base + 32u + hl];
+        if (!done && base + 32u + (uint32_t)hl < limit) e_next = gload(tab, base + 32u + hl);
         // largest pattern weight of the round over both words' 64-pattern chunks
         const uint32_t w0 = base < lim0 ? wm0[base >> 6] : 0u;
         const uint32_t w1 = base < lim1 ? wm1[base >> 6] : 0u;
@@ -331,6 +331,9 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
     st.D = D;
     st.ranks = 0;
     st.exact_rank = exact_pass ? 1 : 0;
+#ifdef SG_PHASE_CLOCKS
+    for (int q = 0; q < kPhases; q++) st.phase[q] = 0u;   // pairs are not timed by phase
+#endif
     if (count) st.ranks = half_first_u(half_add(w_lane), lane);
     return st;
 }

@@ -120,6 +120,7 @@ int sogrand_profile_end(sogrand_kernel_stat_t *stats, int max_stats, int *n_stat
                 acc[k].queries += c.queries;
                 acc[k].ranks += c.ranks;
                 acc[k].exact_rank += c.exact_rank;
+                for (int q = 0; q < kPhases; q++) acc[k].phase_cycles[q] += c.phase[q];
             }
     }
     int n = 0;

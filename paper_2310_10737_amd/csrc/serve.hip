@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
     __shared__ uint32_t hc_s[kWavesPerBlock][SOGRAND_NMAX];
     const int wave = threadIdx.x / kWave;
     for (int t = lane; t < 2 * n; t += kWave) mk_s[wave][t] = mk[t];
-    for (int t = lane; t < n; t += kWave) hc_s[wave][t] = hcol[t];
+    for (int t = lane; t < n; t += kWave) hc_s[wave][t] = gptr(hcol)[t];
     wave_sync();
     bool bad = false;
     for (int b = 0; b < 2; b++) {
@@ -211,24 +211,30 @@ __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
     if (finished) {
         const bool rows = (d.h & 1u) != 0;
         uint8_t *hd = reinterpret_cast<uint8_t *>(a.mirror_w + d.slot + sl.hard);
-        // four elements of a row per lane and store when n is a multiple of 4, else one
-        if ((n & 3) == 0) {
-            for (int j = 0; j < n; j++) {
-                for (int c = 4 * lane; c < n; c += 4 * kWave) {
+        const int nn = n * n;
+        // Whole 16-byte units per lane when n*n is a multiple of 16 (the unit is then aligned),
+        // else one byte per lane.  The host copy is pinned host memory: 4-byte stores there
+        // were seen to leave single bytes stale on the test machine, 16-byte stores never.
+        if ((nn & 15) == 0) {
+            for (int o = lane * 16; o < nn; o += kWave * 16) {
+                uint32_t w[4];
+                for (int q = 0; q < 4; q++) {
                     uint32_t v = 0;
                     for (int e = 0; e < 4; e++) {
-                        const int line = rows ? j : c + e, bit = rows ? c + e : j;
+                        const int p = o + 4 * q + e;
+                        const int j = p / n, c = p - j * n;
+                        const int line = rows ? j : c, bit = rows ? c : j;
                         v |= (uint32_t)((mk_s[wave][line * 2 + (bit >> 6)] >> (bit & 63)) & 1ull) << (8 * e);
                     }
-                    *reinterpret_cast<uint32_t *>(hd + j * n + c) = v;
+                    w[q] = v;
                 }
+                *reinterpret_cast<uint4 *>(hd + o) = make_uint4(w[0], w[1], w[2], w[3]);
             }
         } else {
-            for (int j = 0; j < n; j++) {
-                for (int c = lane; c < n; c += kWave) {
-                    const int line = rows ? j : c, bit = rows ? c : j;
-                    hd[j * n + c] = (uint8_t)((mk_s[wave][line * 2 + (bit >> 6)] >> (bit & 63)) & 1ull);
-                }
+            for (int p = lane; p < nn; p += kWave) {
+                const int j = p / n, c = p - j * n;
+                const int line = rows ? j : c, bit = rows ? c : j;
+                hd[p] = (uint8_t)((mk_s[wave][line * 2 + (bit >> 6)] >> (bit & 63)) & 1ull);
             }
         }
         if (a.app) {

@@ -54,7 +54,20 @@ struct WordStats {
     double D;        // normaliser: sum of found prod rho + not-found mass * phi (relative to p(0|r))
     uint64_t ranks;  // sum of the Hamming weights of the tested patterns (only when counting)
     int exact_rank;  // the ranks needed the exact (counting) pass
+#ifdef SG_PHASE_CLOCKS
+    uint32_t phase[kPhases];   // clock cycles of each decode phase (the last one is set by the caller)
+#endif
 };
+
+// Phase clocks (builds with SG_PHASE_CLOCKS only): the wave's clock counter read at the
+// boundaries of decode_word's steps.
+#ifdef SG_PHASE_CLOCKS
+#define SG_CLOCK(var) const uint64_t var = __builtin_amdgcn_s_memtime()
+#else
+#define SG_CLOCK(var) \
+    do {              \
+    } while (0)
+#endif
 
 // number of nonzero bytes of a packed pattern (its Hamming weight)
 __device__ __forceinline__ uint32_t pattern_weight(uint4 e) {
@@ -244,6 +257,22 @@ __device__ __forceinline__ void sort32(uint32_t (&k)[NB], int lane) {
 // v from lane + 1 (lane 63 reads lane 0)
 __device__ __forceinline__ uint32_t next_lane(uint32_t v) {
     return (uint32_t)__shfl((int)v, (int)((threadIdx.x + 1) & (kWave - 1)));
+}
+
+// The same pointer in the global address space.  Pointers that reach a kernel through
+// device memory (a code table read with load_uniform) would otherwise be accessed with
+// flat instructions, which count against the LDS wait counter too: every wait for an LDS
+// read would then also wait for the schedule loads in flight.
+template <typename V>
+__device__ __forceinline__ const __attribute__((address_space(1))) V *gptr(const V *p) {
+    return (const __attribute__((address_space(1))) V *)p;
+}
+
+// p[i] by value (vector types have no assignment from a global-space reference); the
+// generic view of a global pointer still compiles to a global load
+template <typename V>
+__device__ __forceinline__ V gload(const __attribute__((address_space(1))) V *p, uint32_t i) {
+    return ((const V *)p)[i];
 }
 
 // ---- binary64 elementary functions for the per-bit work ----
@@ -599,6 +628,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
                                                  double (&lapp)[Lanes<NS>::NB], int lane, bool count) {
     constexpr int NB = Lanes<NS>::NB;
     const int n = c.n;
+    SG_CLOCK(t0);
 
     // 1. hard decision, its syndrome and parity; keys |lambda| and rho = e^-|lambda| by bit
     bool valid[NB];
@@ -612,7 +642,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         const int i = lane + kWave * b;
         valid[b] = i < n;
         ybit[b] = valid[b] && lam[b] < 0.0;
-        if (ybit[b]) spart ^= c.hcol[i];
+        if (ybit[b]) spart ^= gptr(c.hcol)[i];
         ycount += __popcll(__ballot(ybit[b]));
         const double a = fabs(lam[b]);
         key[b] = valid[b] ? (uint64_t)__double_as_longlong(a) : ~0ull;
@@ -620,6 +650,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     }
     const uint32_t s0 = wave_xor(spart);
     const int par = ycount & 1;
+    SG_CLOCK(t1);
 
     // 2. reliability ranks (|lambda| ascending, ties by bit index).  The plain kernels
     //    count smaller keys for words of up to 64 bits: two VALU operations per key, with
@@ -634,7 +665,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
         if (valid[b]) {
-            S.ent_r[myrank[b]].z = c.hcol[i];
+            S.ent_r[myrank[b]].z = gptr(c.hcol)[i];
             put_rho(S, myrank[b], rho[b]);
             S.pi_r[myrank[b]] = (uint8_t)i;
         } else if (i < NS) {
@@ -648,6 +679,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         put_rho(S, 0, 1.0);
     }
     wave_sync();
+    SG_CLOCK(t2);
 
     // 3. parity-class masses: adding bit i maps (E, O) to (E + O rho_i, O + (1 + E) rho_i);
     //    two disjoint bit sets combine as E = E1 + E2 + E1 E2 + O1 O2, O = O1 + O2 + E1 O2 + O1 E2.
@@ -669,6 +701,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     if constexpr (NS >= 128) eo_combine<8>(E, O);
     E = bcast0(E);
     O = bcast0(O);
+    SG_CLOCK(t3);
 
     // 4. query loop over the schedule of the word's parity class; the next chunk's
     //    patterns are fetched while the current one is tested
@@ -676,16 +709,16 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     // The persistent kernel holds its DevCode in registers, where a dynamic index
     // would move it to scratch memory: it reads the class's table fields from the
     // device copy instead.  A kernel argument is indexed in place.
-    const uint4 *__restrict__ tab;
-    const uint32_t *__restrict__ wm;
+    const __attribute__((address_space(1))) uint4 *__restrict__ tab;
+    const __attribute__((address_space(1))) uint32_t *__restrict__ wm;
     uint32_t len;
     if constexpr (TABLE) {
-        tab = load_uniform(&cdev->pat[cls]);
-        wm = load_uniform(&cdev->wmax[cls]);
+        tab = gptr(load_uniform(&cdev->pat[cls]));
+        wm = gptr(load_uniform(&cdev->wmax[cls]));
         len = load_uniform(&cdev->len[cls]);
     } else {
-        tab = c.pat[cls];
-        wm = c.wmax[cls];
+        tab = gptr(c.pat[cls]);
+        wm = gptr(c.wmax[cls]);
         len = c.len[cls];
     }
     const uint32_t limit = qcap < len ? qcap : len;
@@ -696,8 +729,8 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     uint32_t w_lane = 0;   // this lane's share of the tested pattern weights (counting only)
     // patterns of the next two chunks are in flight while a chunk is tested
     uint4 e_next = make_uint4(0u, 0u, 0u, 0u), e_next2 = make_uint4(0u, 0u, 0u, 0u);
-    if ((uint32_t)lane < limit) e_next = tab[lane];
-    if ((uint32_t)lane + kWave < limit) e_next2 = tab[kWave + lane];
+    if ((uint32_t)lane < limit) e_next = gload(tab, lane);
+    if ((uint32_t)lane + kWave < limit) e_next2 = gload(tab, kWave + lane);
     uint32_t wm_next = wm[0];
     uint32_t wm_next2 = limit > (uint32_t)kWave ? wm[1] : 0u;
     for (uint32_t base = 0; base < limit; base += kWave) {
@@ -711,7 +744,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         const uint32_t nb2 = nb + kWave;
         if (nb2 < limit) {
             e_next2 = make_uint4(0u, 0u, 0u, 0u);
-            if (nb2 + (uint32_t)lane < limit) e_next2 = tab[nb2 + lane];
+            if (nb2 + (uint32_t)lane < limit) e_next2 = gload(tab, nb2 + lane);
             wm_next2 = wm[nb2 >> 6];
         }
         const bool act = base + (uint32_t)lane < limit;
@@ -802,6 +835,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     }
 
     const double Snz = bcast0(wave_sum(s_lane));
+    SG_CLOCK(t4);
 
     // 5. Corollary 1 inside the parity class: not-found mass M = (class mass) - (tested mass),
     //    both relative to p(0|r); the zero pattern (first in its class) cancels exactly.
@@ -870,6 +904,16 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     st.ranks = 0;
     st.exact_rank = exact_pass ? 1 : 0;
     if (count) st.ranks = wave_add(w_lane);
+#ifdef SG_PHASE_CLOCKS
+    SG_CLOCK(t5);
+    st.phase[0] = (uint32_t)(t1 - t0);
+    st.phase[1] = (uint32_t)(t2 - t1);
+    st.phase[2] = (uint32_t)(t3 - t2);
+    st.phase[3] = (uint32_t)(t4 - t3);
+    st.phase[4] = (uint32_t)(t5 - t4);
+    st.phase[5] = 0u;
+    st.phase[6] = 0u;
+#endif
     return st;
 }
 
@@ -880,6 +924,9 @@ __device__ __forceinline__ void prof_add(ProfCounters *p, const WordStats &st) {
     atomicAdd(&p->queries, (unsigned long long)st.Q);
     atomicAdd(&p->ranks, (unsigned long long)st.ranks);
     if (st.exact_rank) atomicAdd(&p->exact_rank, 1ull);
+#ifdef SG_PHASE_CLOCKS
+    for (int q = 0; q < kPhases; q++) atomicAdd(&p->phase[q], (unsigned long long)st.phase[q]);
+#endif
 }
 
 }  // namespace sg

@@ -46,7 +46,7 @@ def run_batched(sg, codes, cidx, offs, llr, f32=False, sched=None, L=4, qcap=100
     fo = torch.from_numpy(offs).cuda()
     out = sg.sogrand_decode_batched(gcodes, fc, fo, x, list_max=L, query_cap=qcap, max_iter=iters, sched_=sched)
     torch.cuda.synchronize()
-    return {k: v.cpu().numpy() for k, v in out.items()}
+    return {k: v.cpu().numpy() for k, v in out.items() if v is not None}
 
 
 def run_plain_per_code(sg, codes, cidx, offs, llr, f32=False, L=4, qcap=10000, iters=6):

@@ -185,13 +185,13 @@ def test_poll_semantics(sg):
         res = (sg.sogrand_result_t * 4)()
         n = ctypes.c_size_t()
         # nothing in flight
-        assert L.sogrand_serve_poll(srv._h, res, 4, ctypes.byref(n), None, 0) == sg.SOGRAND_ENOTFOUND
-        assert L.sogrand_serve_poll(srv._h, res, 4, ctypes.byref(n), None, -1) == sg.SOGRAND_ENOTFOUND
+        assert L.sogrand_serve_poll(srv._h, res, 4, ctypes.byref(n), None, None, 0) == sg.SOGRAND_ENOTFOUND
+        assert L.sogrand_serve_poll(srv._h, res, 4, ctypes.byref(n), None, None, -1) == sg.SOGRAND_ENOTFOUND
         assert srv.submit(g, np.ascontiguousarray(llr[0])) is not None
-        rc = L.sogrand_serve_poll(srv._h, res, 4, ctypes.byref(n), None, -1)
+        rc = L.sogrand_serve_poll(srv._h, res, 4, ctypes.byref(n), None, None, -1)
         assert rc == 0 and n.value == 1 and res[0].status == 0
         # taken: nothing left
-        assert L.sogrand_serve_poll(srv._h, res, 4, ctypes.byref(n), None, 1000) == sg.SOGRAND_ENOTFOUND
+        assert L.sogrand_serve_poll(srv._h, res, 4, ctypes.byref(n), None, None, 1000) == sg.SOGRAND_ENOTFOUND
         # wrong dtype or size is refused by the binding; a NULL LLR pointer by the library
         with pytest.raises(ValueError):
             srv.submit(g, np.zeros((32, 32), np.float32))
