@@ -156,6 +156,33 @@ int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *p
                            uint8_t *success, uint16_t *half_iters, uint64_t *sum_queries,
                            uint64_t *sum_max_queries, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   decoding as sogrand_decode_product, with identical results, but the work
+   buffer is a static device array of SOGRAND_NOALLOC_WORK_MAX bytes that the
+   library holds on each device it has run this call on, until the process ends.
+   The call allocates nothing (no hipMalloc, hipFree or stream-ordered
+   allocation) and leaves the measurement hooks out.
+   Limits and preconditions:
+     - the work buffer of nframes frames of length n, about
+       nframes * (3 n^2 b + 16 n + 32) bytes with b = 8 (F64) or 4 (F32) LLR
+       storage, must fit in SOGRAND_NOALLOC_WORK_MAX bytes (else EINVAL; for
+       example 1300 [64,57]^2 frames in binary32, 170 [128,120]^2 frames in
+       binary64);
+     - the code's device tables for this device and a query cap at least
+       params->query_cap must exist, built by any earlier allocating decode call
+       (component, product, QC-GLDPC, batched or serving) with this code on this
+       device (else EINVAL);
+     - every call on one device shares that device's array, and nothing is kept
+       from one call to the next: calls whose work overlaps on one device (other
+       streams, or other threads) race and give wrong results; serialise them.
+   Arguments, outputs and the other errors as for sogrand_decode_product. */
+#define SOGRAND_NOALLOC_WORK_MAX (64u << 20)
+int sogrand_decode_product_noalloc(const sogrand_code_t *code, const sogrand_params_t *params,
+                                   size_t nframes, const void *llr_ch, uint8_t *hard, void *llr_app,
+                                   uint8_t *success, uint16_t *half_iters, uint64_t *sum_queries,
+                                   uint64_t *sum_max_queries, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* QC-GLDPC codes (section "Performance evaluation", GLDPC decoding)        */
 /* ------------------------------------------------------------------------ */

@@ -12,13 +12,14 @@ import os
 
 __all__ = [
     "SograndError", "Code", "params", "sched", "lib", "library_path", "profile_begin", "profile_end",
-    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_gldpc",
+    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_product_noalloc", "sogrand_decode_gldpc",
     "sogrand_decode_batched", "sogrand_decode_batched_gldpc", "pack_frames",
     "Server", "sogrand_clock_ns", "measure_valu_rate", "SOGRAND_F64", "SOGRAND_F32",
 ]
 
 SOGRAND_F64 = 0
 SOGRAND_F32 = 1
+SOGRAND_NOALLOC_WORK_MAX = 64 << 20
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libsogrand.so")
 _lib = None
@@ -26,7 +27,7 @@ _lib = None
 EXPORTS = [
     "sogrand_last_error", "sogrand_version", "sogrand_params_default",
     "sogrand_code_create", "sogrand_code_create_ebch", "sogrand_code_info", "sogrand_code_destroy",
-    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_gldpc",
+    "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_product_noalloc", "sogrand_decode_gldpc",
     "sogrand_sched_default", "sogrand_decode_batched", "sogrand_decode_batched_gldpc",
     "sogrand_clock_ns", "sogrand_serve_create", "sogrand_serve_submit", "sogrand_serve_poll",
     "sogrand_serve_stats", "sogrand_serve_replay", "sogrand_serve_destroy",
@@ -132,6 +133,7 @@ def lib():
     L.sogrand_code_destroy.restype = None
     L.sogrand_decode_component.argtypes = [P, P, SZ] + [P] * 11
     L.sogrand_decode_product.argtypes = [P, P, SZ] + [P] * 8
+    L.sogrand_decode_product_noalloc.argtypes = [P, P, SZ] + [P] * 8
     L.sogrand_decode_gldpc.argtypes = [P, P, SZ] + [P] * 8
     L.sogrand_sched_default.argtypes = [P]
     L.sogrand_sched_default.restype = None
@@ -283,6 +285,14 @@ def sogrand_decode_product(code: Code, llr_ch, list_max=4, query_cap=1000, max_i
                            early_stop=True, want_app=False, outputs=None, stream=None, list_bler_stop=0.0):
     """Block-turbo decode of product-code frames llr_ch (F, n, n); returns a dict of tensors."""
     return _decode_frames(lib().sogrand_decode_product, code, llr_ch, list_max, query_cap, max_iter, alpha,
+                          early_stop, want_app, outputs, stream, list_bler_stop)
+
+
+def sogrand_decode_product_noalloc(code: Code, llr_ch, list_max=4, query_cap=1000, max_iter=4, alpha=0.5,
+                                   early_stop=True, want_app=False, outputs=None, stream=None, list_bler_stop=0.0):
+    """sogrand_decode_product with the library's static work buffer (no device allocation by the
+    library; the output tensors are allocated here unless supplied in ``outputs``)."""
+    return _decode_frames(lib().sogrand_decode_product_noalloc, code, llr_ch, list_max, query_cap, max_iter, alpha,
                           early_stop, want_app, outputs, stream, list_bler_stop)
 
 

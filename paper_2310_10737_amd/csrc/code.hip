@@ -340,11 +340,20 @@ void free_schedule(Schedule *s) {
     delete s;
 }
 
-int prepare_code(sogrand_code_t *code, uint32_t query_cap, DevCode *dc) {
+int prepare_code(sogrand_code_t *code, uint32_t query_cap, DevCode *dc, bool may_allocate) {
     if (!code) return fail(SOGRAND_EINVAL, "code is NULL");
     int dev = 0;
     SG_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(code->mu);
+    if (!may_allocate) {
+        auto h = code->d_hcol.find(dev);
+        auto t = code->sched.find(dev);
+        if (h == code->d_hcol.end() || !h->second || t == code->sched.end() || !t->second ||
+            t->second->cap < query_cap)
+            return fail(SOGRAND_EINVAL,
+                        "the code's tables for device %d and query cap %u are not built: decode once with this "
+                        "code on this device with a cap at least this large first", dev, query_cap);
+    }
     uint32_t *&hc = code->d_hcol[dev];
     if (!hc) {
         if (hipMalloc(&hc, sizeof(uint32_t) * SOGRAND_NMAX) != hipSuccess) {

@@ -564,6 +564,35 @@ static int decode_frames(int topo, const sogrand_code_t *code, const sogrand_par
     return rc;
 }
 
+// ----------------------------------------------------------------------------
+// the product path without allocation: the work buffer is a static device array
+// ----------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)SOGRAND_NOALLOC_WORK_MAX;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kMaxDevices];   // the array's device address on each device, once looked up
+
+// The address of this device's copy of `scratch`.  In host code the array's name is
+// only a stand-in for the symbol, so the address is looked up once per device and
+// used from then on.
+static int scratch_address(void **out) {
+    int dev = 0;
+    SG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SOGRAND_EDEVICE, "device %d outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SOGRAND_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return SOGRAND_OK;
+}
+
 }  // namespace sg
 
 extern "C" {
@@ -582,6 +611,26 @@ int sogrand_decode_gldpc(const sogrand_code_t *code, const sogrand_params_t *par
                          void *stream) {
     return sg::decode_frames(sg::kGldpc, code, params, nframes, llr_ch, hard, llr_app, success, half_iters,
                              sum_queries, sum_max_queries, stream);
+}
+
+int sogrand_decode_product_noalloc(const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
+                                   const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
+                                   uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
+                                   void *stream) {
+    using namespace sg;
+    SG_TRY(check_frames(code, params, nframes, llr_ch, hard, success));
+    if (nframes == 0) return SOGRAND_OK;
+    const size_t esz = params->precision == SOGRAND_F64 ? sizeof(double) : sizeof(float);
+    const WorkLayout w = work_layout(kProduct, nframes, code->n, esz);
+    if (w.total > kScratchBytes)
+        return fail(SOGRAND_EINVAL, "%zu frames need %zu bytes of work buffer, above the %zu of the static buffer",
+                    nframes, w.total, kScratchBytes);
+    DevCode dc;
+    SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &dc, false));
+    void *ws = nullptr;
+    SG_TRY(scratch_address(&ws));
+    return run_frames(kProduct, dc, params, nframes, llr_ch, hard, llr_app, success, half_iters, sum_queries,
+                      sum_max_queries, static_cast<char *>(ws), static_cast<hipStream_t>(stream), false);
 }
 
 }  // extern "C"

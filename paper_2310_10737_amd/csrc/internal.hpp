@@ -78,8 +78,9 @@ namespace sg {
 
 // Ensures the device copy of H and a schedule covering query_cap on the current
 // device, then fills *dc.  The first call for a (code, device, larger cap) builds
-// the schedule and waits for it.
-int prepare_code(sogrand_code_t *code, uint32_t query_cap, DevCode *dc);
+// the schedule and waits for it.  With may_allocate false nothing is built: a
+// missing table is an EINVAL.
+int prepare_code(sogrand_code_t *code, uint32_t query_cap, DevCode *dc, bool may_allocate = true);
 
 int check_params(const sogrand_params_t *p);
 
