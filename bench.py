@@ -389,14 +389,6 @@ def bench_product(args, sg, np, torch, synth):
     default_cfg = iters == ITERS and stop == 0.0 and F == 10000
     roof = dominant_roofline(args, best_name, best, N, traffic=recorded_traffic(best_name) if default_cfg else None)
 
-    if args.copy_mib > 0:
-        src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
     def oracle_decode(sample, threads):
         import oracle
         oracle.decode_product(code, sample, L, QCAP, iters, nthreads=threads, pstop=stop)
@@ -452,23 +444,26 @@ def bench_mixed(args, sg, np, torch, synth):
         bout.update(sg.sogrand_decode_batched(gcodes, fc, fo, x, list_max=L, query_cap=qcap, max_iter=ITERS,
                                               sched_=sc))
 
-    # launch shape: the fastest of a few candidates on the first 2000 frames
-    m = min(2000, F)
-    end = int(offs[m - 1] + codes[cidx[m - 1]].n ** 2)
-    best = None
-    for w, f, ch, g in [(8, 2, 4, 3), (8, 2, 4, 2), (8, 2, 2, 3), (4, 2, 4, 5), (8, 2, 1, 3)]:
-        sc = sg.sched(w, f, ch, g)
-        t0 = time.perf_counter()
-        sg.sogrand_decode_batched(gcodes, fc[:m], fo[:m], x[:end], L, qcap, ITERS, sched_=sc)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        if best is None or dt < best[0]:
-            best = (dt, sc)
-    sc = best[1]
+    # launch shape: the fastest of a few candidates on the first 2000 frames (--no-tune: the
+    # library default, for profiler runs that should see only full-size launches)
+    sc = sg.sched()
+    if not args.no_tune:
+        m = min(2000, F)
+        end = int(offs[m - 1] + codes[cidx[m - 1]].n ** 2)
+        best = None
+        for w, f, ch, g in [(8, 2, 4, 3), (8, 2, 4, 2), (8, 2, 2, 3), (4, 2, 4, 5), (8, 2, 1, 3)]:
+            sc = sg.sched(w, f, ch, g)
+            t0 = time.perf_counter()
+            sg.sogrand_decode_batched(gcodes, fc[:m], fo[:m], x[:end], L, qcap, ITERS, sched_=sc)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, sc)
+        sc = best[1]
     ms_b, kern_b, work_b = timed(lambda: batched_step(sc), args.steps, args.warmup, sg, count=not args.no_count)
     if int(bout["status"].item()) != 0:
         raise SystemExit(f"batched kernel reported status {int(bout['status'].item())}")
-    ms_p, _, _ = timed(plain_step, args.steps, args.warmup, sg, count=False)
+    ms_p, _, _ = (None, None, None) if args.no_plain else timed(plain_step, args.steps, args.warmup, sg, count=False)
     torch.cuda.synchronize()
     same = True
     bhard = bout["hard"].cpu().numpy()
@@ -477,8 +472,10 @@ def bench_mixed(args, sg, np, torch, synth):
     bq = bout["sum_queries"].double().cpu().numpy()
     bmq = bout["sum_max_queries"].double().cpu().numpy()
     per_code, matched = {}, True
-    for (c, sel, idx), po in zip(groups, pouts):
+    for (c, sel, idx), po in zip(groups, pouts or [None] * len(groups)):
         nn = codes[c].n ** 2
+        if po is None:   # --no-plain: the batched form's own statistics only
+            po = dict(hard=bout["hard"][torch.from_numpy(idx).to(dev)], success=bout["success"][torch.from_numpy(sel).to(dev)])
         phard = po["hard"].cpu().numpy().reshape(-1)
         same &= bool(np.array_equal(bsucc[sel], po["success"].cpu().numpy()))
         same &= bool(np.array_equal(bhard[idx], phard))
@@ -544,8 +541,10 @@ def bench_mixed(args, sg, np, torch, synth):
               "parallelism": "single GPU"}
     line = base_line(args, "decoded info bits/s (batched/served vs plain) at matched BLER; p99 frame latency",
                      info / (ms_b / 1e3), "info bits/s", ms_b, "f64", config, roof, cpu,
-                     plain_f32=dict(ms_per_step=ms_p, info_bits_per_s=info / (ms_p / 1e3)),
-                     speedup_vs_plain=ms_p / ms_b, identical_to_plain=same, bler_matches_plain=bool(matched),
+                     plain_f32=None if ms_p is None else dict(ms_per_step=ms_p, info_bits_per_s=info / (ms_p / 1e3)),
+                     speedup_vs_plain=None if ms_p is None else ms_p / ms_b,
+                     identical_to_plain=None if ms_p is None else same,
+                     bler_matches_plain=None if ms_p is None else bool(matched),
                      per_code=per_code)
     del x, fc, fo, plain_in, pouts
     bout.clear()
@@ -812,6 +811,10 @@ def main() -> int:
                     help="skip the work-counting run (for profiler runs that average kernel durations)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (HBM byte-counter calibration)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="mixed workload: the library's default launch shape, no candidate sweep")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="mixed workload: time the batched form only (profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -833,6 +836,14 @@ def main() -> int:
     fn = dict(headline=bench_headline, product=bench_product, mixed=bench_mixed, component=bench_component,
               serve=bench_serve, gldpc=bench_gldpc, rician=bench_rician)[args.workload]
     line = fn(args, sg, np, torch, synth)
+    if args.copy_mib > 0:
+        # a plain device copy of known size: calibrates the HBM byte counters of profiler runs
+        src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     roof = line.get("roofline")
     if roof and roof.get("bound") == "alu":
         # the derived peak stays the reference; the measured issue rate is reported beside it

@@ -367,12 +367,12 @@ typedef struct {
     uint64_t queries;    /* patterns tested (count_work only)                         */
     uint64_t ranks;      /* sum of the Hamming weights of the tested patterns (count_work only) */
     uint64_t exact_rank; /* words whose ranks needed the exact tie-resolving pass (count_work only) */
-    uint64_t phase_cycles[7]; /* count_work in a build with SG_PHASE_CLOCKS defined, else 0: wave clock
+    uint64_t phase_cycles[8]; /* count_work in a build with SG_PHASE_CLOCKS defined, else 0: wave clock
                                  cycles spent per decode phase, summed over words: hard decision,
                                  syndrome and rho; ranking; class masses; query loop; soft output; the
                                  rest of the word's work in the kernel (inputs, outputs); in the
-                                 persistent kernel, cycles spent finding work (claims, hand-over,
-                                 validity checks, waiting) */
+                                 persistent kernel, cycles spent finding work (claims, waiting) and on
+                                 half-iteration hand-overs (validity check, retire, refill) */
 } sogrand_kernel_stat_t;
 
 /* Starts recording: every decode kernel launched afterwards is bracketed by a

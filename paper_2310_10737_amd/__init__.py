@@ -55,7 +55,7 @@ class sogrand_kernel_stat_t(ctypes.Structure):
         ("queries", ctypes.c_uint64),
         ("ranks", ctypes.c_uint64),
         ("exact_rank", ctypes.c_uint64),
-        ("phase_cycles", ctypes.c_uint64 * 7),
+        ("phase_cycles", ctypes.c_uint64 * 8),
     ]
 
 

@@ -309,6 +309,9 @@ void k_batched(BatchArgs a) {
     T *la_base = static_cast<T *>(a.la) + (size_t)blockIdx.x * nslots * a.nmax * a.nmax;
     uint32_t idle = 0;
 #ifdef SG_PHASE_CLOCKS
+    ProfAcc acc;   // the clocked build adds its counters up once, when the wave ends
+#endif
+#ifdef SG_PHASE_CLOCKS
     uint64_t t_free = __builtin_amdgcn_s_memtime();   // end of this wave's last line of work
 #endif
     int start = wave % nslots;
@@ -389,7 +392,11 @@ void k_batched(BatchArgs a) {
                 st.phase[6] = (uint32_t)(l0 - t_free);
                 t_free = l1;
 #endif
+#ifdef SG_PHASE_CLOCKS
+                if (a.prof) acc.add(st);
+#else
                 if (a.prof && lane == 0) prof_add(a.prof, st);
+#endif
                 qsum += st.Q;
                 qmax = st.Q > qmax ? st.Q : qmax;
             }
@@ -406,6 +413,7 @@ void k_batched(BatchArgs a) {
         if (d != n) continue;
 
         // this wave finished the half-iteration
+        SG_CLOCK(v0);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         const bool valid = slot_valid<TOPO>(sl, c, lane, h);
         const bool retire = (valid && a.early_stop) || h == 2 * a.max_iter;
@@ -425,7 +433,16 @@ void k_batched(BatchArgs a) {
             }
             slot_publish(sl);
         }
+#ifdef SG_PHASE_CLOCKS
+        // the hand-over is not time spent finding work
+        SG_CLOCK(v1);
+        acc.phase[7] += v1 - v0;
+        t_free += v1 - v0;
+#endif
     }
+#ifdef SG_PHASE_CLOCKS
+    if (a.prof && lane == 0) acc.flush(a.prof);
+#endif
 }
 
 // Zeroes the frame counter and error bits and stores the code table where the

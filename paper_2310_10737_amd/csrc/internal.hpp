@@ -92,9 +92,9 @@ enum ProfKind { PK_COMPONENT = 0, PK_PASS, PK_CHECK, PK_INIT, PK_BATCHED, PK_SER
 // Phases of a component decode timed by builds with SG_PHASE_CLOCKS (wave clock cycles):
 // hard decision, syndrome and rho; ranking; class masses; query loop; soft output; the
 // rest of the line's work in the kernel (reading the inputs, writing the outputs); and, in
-// the persistent kernel, the time a wave spends finding work (claims, frame hand-over,
-// validity checks and waiting).
-constexpr int kPhases = 7;
+// the persistent kernel, the time a wave spends finding work (claims and waiting) and the
+// time spent on half-iteration hand-overs (validity check, retiring and refilling a slot).
+constexpr int kPhases = 8;
 
 struct ProfCounters {
     unsigned long long words, queries, ranks, exact_rank;   // exact_rank: words that needed the exact ranking pass

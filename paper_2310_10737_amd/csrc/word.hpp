@@ -913,10 +913,10 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     st.phase[4] = (uint32_t)(t5 - t4);
     st.phase[5] = 0u;
     st.phase[6] = 0u;
+    st.phase[7] = 0u;
 #endif
     return st;
 }
-
 
 __device__ __forceinline__ void prof_add(ProfCounters *p, const WordStats &st) {
     p += blockIdx.x % kProfSlots;
@@ -928,5 +928,34 @@ __device__ __forceinline__ void prof_add(ProfCounters *p, const WordStats &st) {
     for (int q = 0; q < kPhases; q++) atomicAdd(&p->phase[q], (unsigned long long)st.phase[q]);
 #endif
 }
+
+// A persistent wave's running totals of the same counters, added to the device
+// counters once when the wave ends (flush), so that the measurement's atomics do not
+// sit between the words that it times.
+struct ProfAcc {
+    unsigned long long words = 0, queries = 0, ranks = 0, exact_rank = 0;
+#ifdef SG_PHASE_CLOCKS
+    unsigned long long phase[kPhases] = {};
+#endif
+    __device__ __forceinline__ void add(const WordStats &st) {
+        words += 1;
+        queries += st.Q;
+        ranks += st.ranks;
+        exact_rank += st.exact_rank ? 1 : 0;
+#ifdef SG_PHASE_CLOCKS
+        for (int q = 0; q < kPhases; q++) phase[q] += st.phase[q];
+#endif
+    }
+    __device__ __forceinline__ void flush(ProfCounters *p) const {
+        p += blockIdx.x % kProfSlots;
+        atomicAdd(&p->words, words);
+        atomicAdd(&p->queries, queries);
+        atomicAdd(&p->ranks, ranks);
+        atomicAdd(&p->exact_rank, exact_rank);
+#ifdef SG_PHASE_CLOCKS
+        for (int q = 0; q < kPhases; q++) atomicAdd(&p->phase[q], phase[q]);
+#endif
+    }
+};
 
 }  // namespace sg
