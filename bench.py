@@ -365,21 +365,11 @@ def bench_product(args, sg, np, torch, synth):
     iters, stop = args.iters, args.list_bler_stop
 
     def tune(x):
-        """Times candidate launch shapes on the first 3000 frames; returns the fastest."""
-        m = min(3000, total)
-        xs = x[:m].contiguous().view(-1)
-        best = None
-        for w, f, ch, g in [(8, 2, 4, 3), (8, 2, 2, 3), (8, 3, 4, 3), (8, 2, 4, 2), (4, 2, 4, 6), (8, 2, 1, 3)]:
-            sc = sg.sched(w, f, ch, g)
-            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, iters, sched_=sc, list_bler_stop=stop)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            sg.sogrand_decode_batched([gcode], fcode[:m], foff[:m], xs, L, QCAP, iters, sched_=sc, list_bler_stop=stop)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            if best is None or dt < best[0]:
-                best = (dt, sc)
-        return best[1]
+        """The library's launch-shape tuner on every tenth frame (all three Eb/N0)."""
+        idx = torch.arange(0, total, 10, device=dev)
+        best, _ = sg.sched_tune([gcode], fcode[idx], foff[idx], x.contiguous().view(-1), L, QCAP, iters,
+                                list_bler_stop=stop)
+        return best
 
     out_of, make_step, fcode, foff = plain_or_batched(sg, torch, gcode, total, N, dev, x64, x32, iters, stop,
                                                       sched_of=tune if args.tune else None)
@@ -444,22 +434,12 @@ def bench_mixed(args, sg, np, torch, synth):
         bout.update(sg.sogrand_decode_batched(gcodes, fc, fo, x, list_max=L, query_cap=qcap, max_iter=ITERS,
                                               sched_=sc))
 
-    # launch shape: the fastest of a few candidates on the first 2000 frames (--no-tune: the
+    # launch shape: the library's tuner on every tenth frame of the stream (--no-tune: the
     # library default, for profiler runs that should see only full-size launches)
     sc = sg.sched()
     if not args.no_tune:
-        m = min(2000, F)
-        end = int(offs[m - 1] + codes[cidx[m - 1]].n ** 2)
-        best = None
-        for w, f, ch, g in [(8, 2, 4, 3), (8, 2, 4, 2), (8, 2, 2, 3), (4, 2, 4, 5), (8, 2, 1, 3)]:
-            sc = sg.sched(w, f, ch, g)
-            t0 = time.perf_counter()
-            sg.sogrand_decode_batched(gcodes, fc[:m], fo[:m], x[:end], L, qcap, ITERS, sched_=sc)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            if best is None or dt < best[0]:
-                best = (dt, sc)
-        sc = best[1]
+        idx = torch.arange(0, F, 10, device=dev)
+        sc, _ = sg.sched_tune(gcodes, fc[idx], fo[idx], x, list_max=L, query_cap=qcap, max_iter=ITERS)
     ms_b, kern_b, work_b = timed(lambda: batched_step(sc), args.steps, args.warmup, sg, count=not args.no_count)
     if int(bout["status"].item()) != 0:
         raise SystemExit(f"batched kernel reported status {int(bout['status'].item())}")
@@ -806,7 +786,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="plain_f64,plain_f32,batched_f64,batched_f32")
     ap.add_argument("--tune", action="store_true",
-                    help="pick the batched launch shape by timing a few candidates on a sample first")
+                    help="product workload: pick the batched launch shape with the library's tuner first")
     ap.add_argument("--no-count", action="store_true",
                     help="skip the work-counting run (for profiler runs that average kernel durations)")
     ap.add_argument("--copy-mib", type=int, default=0,

@@ -212,9 +212,9 @@ int sogrand_decode_gldpc(const sogrand_code_t *code, const sogrand_params_t *par
 /* Launch shape of the persistent kernel.  Each workgroup (waves_per_group
    waves) keeps frames_per_group frames in flight and its waves take
    steal_chunk rows or columns at a time from whichever of them has lines left
-   in its current half-iteration; groups_per_cu workgroups run per compute unit.
-   Every frame is decoded exactly as by sogrand_decode_product, so results do not
-   depend on the shape. */
+   in its current half-iteration; at most groups_per_cu workgroups run per compute
+   unit, and no more than fit on it at once.  Every frame is decoded exactly as by
+   sogrand_decode_product, so results do not depend on the shape. */
 typedef struct {
     int waves_per_group;   /* 4, 8 or 16 */
     int frames_per_group;  /* 1..8 */
@@ -222,7 +222,7 @@ typedef struct {
     int groups_per_cu;     /* 1..64 */
 } sogrand_sched_t;
 
-/* A measured default (8 waves, 2 frames, 4 lines, 3 groups per CU). */
+/* A measured default (8 waves, 2 frames, 4 lines, as many groups per CU as fit). */
 void sogrand_sched_default(sogrand_sched_t *s);
 
 /* Block turbo decoding (section "Iterative decoding") of nframes frames whose
@@ -236,7 +236,9 @@ void sogrand_sched_default(sogrand_sched_t *s);
    NULL.  status (DEVICE, optional) receives 0, or bit 0 if a wave gave up waiting
    (not expected) and bit 1 if a frame descriptor was out of range (that frame is
    skipped with success 0 and half_iters 0, and its hard and llr_app are not
-   written).  sched NULL = default.  Errors: EINVAL, ENOMEM, EDEVICE. */
+   written).  sched NULL = the shape recorded for this kind of batch by
+   sogrand_sched_tune or sogrand_sched_table_load, else the default.  Errors:
+   EINVAL, ENOMEM, EDEVICE. */
 int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
                            size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,
                            uint64_t llr_len, const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,
@@ -256,6 +258,35 @@ int sogrand_decode_batched_gldpc(const sogrand_code_t *const *codes, int ncodes,
                                  uint8_t *success,
                                  uint16_t *half_iters, uint64_t *sum_queries, uint64_t *sum_max_queries,
                                  uint32_t *status, const sogrand_sched_t *sched, void *stream);
+
+/* Launch-shape tuner for the persistent kernel.  Decodes the sample described by
+   the arguments (as for sogrand_decode_batched, or sogrand_decode_batched_gldpc
+   when gldpc is nonzero; the outputs go to buffers of the tuner's own) once per
+   candidate shape and times each with HIP events on `stream`.  The candidates
+   come from a coordinate search that starts at the default and varies
+   waves_per_group over {4, 8, 16}, frames_per_group over {1, 2, 3, 4} and
+   steal_chunk over {1, 2, 4, 8} in turn, keeping a change when it is faster;
+   groups_per_cu stays at the default (as many as fit).  The fastest shape goes
+   to *best, its time in milliseconds to *best_ms (optional), and the library's
+   table of tuned shapes, under the batch's kind: topology, precision, whether
+   the list-BLER stop is on, and the (n, k) of its codes.  A later batched call
+   with sched NULL on a batch of that kind uses it.  The sample should be a few
+   thousand frames that look like the workload.  Blocks until done; results of a
+   decode never depend on the shape.  Errors: EINVAL (also for an empty sample),
+   ENOMEM, EDEVICE. */
+int sogrand_sched_tune(int gldpc, const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                       size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset, uint64_t llr_len,
+                       const void *llr_ch, sogrand_sched_t *best, float *best_ms, void *stream);
+
+/* The table of tuned shapes as a text file: one line per batch kind, the kind's
+   name, '|', then waves_per_group frames_per_group steal_chunk groups_per_cu.
+   save writes every entry (EINVAL if the file cannot be written); load adds the
+   file's entries, replacing those of the same kind, and returns how many it read
+   (EINVAL for an unreadable file or a malformed or out-of-range line, in which
+   case nothing is added); clear empties the table. */
+int sogrand_sched_table_save(const char *path);
+int sogrand_sched_table_load(const char *path);
+void sogrand_sched_table_clear(void);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of product-frame decode requests            */

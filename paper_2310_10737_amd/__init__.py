@@ -29,6 +29,7 @@ EXPORTS = [
     "sogrand_code_create", "sogrand_code_create_ebch", "sogrand_code_info", "sogrand_code_destroy",
     "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_product_noalloc", "sogrand_decode_gldpc",
     "sogrand_sched_default", "sogrand_decode_batched", "sogrand_decode_batched_gldpc",
+    "sogrand_sched_tune", "sogrand_sched_table_save", "sogrand_sched_table_load", "sogrand_sched_table_clear",
     "sogrand_clock_ns", "sogrand_serve_create", "sogrand_serve_submit", "sogrand_serve_poll",
     "sogrand_serve_stats", "sogrand_serve_replay", "sogrand_serve_destroy",
     "sogrand_profile_begin", "sogrand_profile_end", "sogrand_measure_valu_rate",
@@ -139,6 +140,10 @@ def lib():
     L.sogrand_sched_default.restype = None
     L.sogrand_decode_batched.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 10
     L.sogrand_decode_batched_gldpc.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 10
+    L.sogrand_sched_tune.argtypes = [I, P, I, P, SZ, P, P, ctypes.c_uint64, P, P, P, P]
+    L.sogrand_sched_table_save.argtypes = [ctypes.c_char_p]
+    L.sogrand_sched_table_load.argtypes = [ctypes.c_char_p]
+    L.sogrand_sched_table_clear.restype = None
     L.sogrand_clock_ns.restype = ctypes.c_uint64
     L.sogrand_serve_create.argtypes = [P, SZ, ctypes.c_uint, P]
     L.sogrand_serve_submit.argtypes = [P, P, P, ctypes.c_uint64, P]
@@ -400,13 +405,46 @@ def _batched(fn, codes, frame_code, frame_offset, llr, list_max, query_cap, max_
     handles = (ctypes.c_void_p * len(codes))(*[c.handle for c in codes])
     p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
                early_stop=early_stop, precision=_precision_of(llr), list_bler_stop=list_bler_stop)
-    sc = sched_ if sched_ is not None else sched()
+    # no shape: the library's tuned shape for this kind of batch, else its default
     _check(fn(
         handles, len(codes), ctypes.byref(p), F, _ptr(frame_code), _ptr(frame_offset), llr.numel(),
         _ptr(llr), _ptr(out["hard"]), _ptr(out.get("llr_app")), _ptr(out["success"]), _ptr(out["half_iters"]),
         _ptr(out["sum_queries"]),
-        _ptr(out["sum_max_queries"]), _ptr(out["status"]), ctypes.byref(sc), _stream(stream)))
+        _ptr(out["sum_max_queries"]), _ptr(out["status"]), None if sched_ is None else ctypes.byref(sched_),
+        _stream(stream)))
     return out
+
+
+def sched_tune(codes, frame_code, frame_offset, llr, list_max=4, query_cap=1000, max_iter=4, alpha=0.5,
+               early_stop=True, list_bler_stop=0.0, gldpc=False, stream=None):
+    """The library's launch-shape tuner on a sample batch (arguments as for sogrand_decode_batched);
+    returns (shape, milliseconds).  The shape is also recorded for later calls without one."""
+    if not (llr.is_cuda and llr.is_contiguous() and llr.dim() == 1):
+        raise ValueError("llr must be a contiguous 1-D CUDA tensor")
+    handles = (ctypes.c_void_p * len(codes))(*[c.handle for c in codes])
+    p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
+               early_stop=early_stop, precision=_precision_of(llr), list_bler_stop=list_bler_stop)
+    best, ms = sogrand_sched_t(), ctypes.c_float()
+    _check(lib().sogrand_sched_tune(1 if gldpc else 0, handles, len(codes), ctypes.byref(p), frame_code.shape[0],
+                                    _ptr(frame_code), _ptr(frame_offset), llr.numel(), _ptr(llr),
+                                    ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
+    return best, ms.value
+
+
+def sched_table_save(path: str):
+    _check(lib().sogrand_sched_table_save(os.fsencode(path)))
+
+
+def sched_table_load(path: str) -> int:
+    """Adds a saved table of tuned shapes; returns the number of entries read."""
+    rc = lib().sogrand_sched_table_load(os.fsencode(path))
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def sched_table_clear():
+    lib().sogrand_sched_table_clear()
 
 
 def measure_valu_rate(kind: int = 0, stream=None) -> float:

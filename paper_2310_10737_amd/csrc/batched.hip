@@ -11,6 +11,15 @@
 // coordination is workgroup-local, so no cache maintenance across XCDs is
 // needed; frames are independent, so the result of a frame does not depend on
 // the schedule.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
 #include "pair.hpp"
 
 namespace sg {
@@ -285,12 +294,20 @@ __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v,
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// Waves per SIMD that the register allocation of each instantiation aims at: eight for
+// product frames of up to 64 bits without the list-BLER stop (64 registers, no spills),
+// six otherwise (the 128-bit instantiations spill a few registers there and still beat
+// four waves with none; the stop and QC-GLDPC forms of the 64-bit one would spill more
+// at eight).
+template <int NSMAX, bool STOP, int TOPO>
+constexpr int batched_waves() {
+    return NSMAX == 64 && !STOP && TOPO == kProduct ? 8 : 6;
+}
+
 // NSMAX: 32 when every code of the batch has n <= 32 (two words per wave), 64 when
-// n <= 64, else 128; the narrower instantiations compile without the wider paths
-// and keep more waves resident (six per SIMD, 80 registers, no spills; measured
-// faster than five or seven).
+// n <= 64, else 128; the narrower instantiations compile without the wider paths.
 template <typename T, int WPB, int NSMAX, bool STOP, int TOPO>
-__global__ __launch_bounds__(kWave * WPB) __attribute__((amdgpu_waves_per_eu(NSMAX > 64 ? 4 : 6)))
+__global__ __launch_bounds__(kWave * WPB) __attribute__((amdgpu_waves_per_eu(batched_waves<NSMAX, STOP, TOPO>())))
 void k_batched(BatchArgs a) {
     __shared__ WaveLds wl[WPB];
     extern __shared__ SlotLds slot_dyn[];
@@ -456,36 +473,28 @@ __global__ void k_batched_status(const uint32_t *error, uint32_t *status) {
     if (threadIdx.x == 0) *status = *error;
 }
 
+using BatchedKernel = void (*)(BatchArgs);
+
 template <typename T, int WPB, int NSMAX, bool STOP>
-static void launch_batched_w(const BatchArgs &a, int grid, hipStream_t st) {
-    const size_t dyn = sizeof(SlotLds) * a.slots;
-    if (a.topo == kProduct)
-        hipLaunchKernelGGL((k_batched<T, WPB, NSMAX, STOP, kProduct>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
-    else
-        hipLaunchKernelGGL((k_batched<T, WPB, NSMAX, STOP, kGldpc>), dim3(grid), dim3(kWave * WPB), dyn, st, a);
+static BatchedKernel batched_kernel_w(int topo) {
+    if (topo == kProduct) return k_batched<T, WPB, NSMAX, STOP, kProduct>;
+    return k_batched<T, WPB, NSMAX, STOP, kGldpc>;
 }
 
 template <typename T, int NSMAX, bool STOP>
-static void launch_batched_n(const BatchArgs &a, int wpb, int grid, hipStream_t st) {
-    if (wpb == 4) launch_batched_w<T, 4, NSMAX, STOP>(a, grid, st);
-    else if (wpb == 8) launch_batched_w<T, 8, NSMAX, STOP>(a, grid, st);
-    else launch_batched_w<T, 16, NSMAX, STOP>(a, grid, st);
+static BatchedKernel batched_kernel_n(int wpb, int topo) {
+    if (wpb == 4) return batched_kernel_w<T, 4, NSMAX, STOP>(topo);
+    if (wpb == 8) return batched_kernel_w<T, 8, NSMAX, STOP>(topo);
+    return batched_kernel_w<T, 16, NSMAX, STOP>(topo);
 }
 
-// the list-BLER stop is a separate instantiation, so that batches without it pay nothing
+// The instantiation for the batch: word width, the list-BLER stop (a separate
+// instantiation, so that batches without it pay nothing), waves per group and topology.
 template <typename T>
-static void launch_batched(const BatchArgs &a, int wpb, int grid, hipStream_t st) {
-    const bool stop = a.pstop > 0.0;
-    if (a.nmax <= 32) {
-        if (stop) launch_batched_n<T, 32, true>(a, wpb, grid, st);
-        else launch_batched_n<T, 32, false>(a, wpb, grid, st);
-    } else if (a.nmax <= 64) {
-        if (stop) launch_batched_n<T, 64, true>(a, wpb, grid, st);
-        else launch_batched_n<T, 64, false>(a, wpb, grid, st);
-    } else {
-        if (stop) launch_batched_n<T, 128, true>(a, wpb, grid, st);
-        else launch_batched_n<T, 128, false>(a, wpb, grid, st);
-    }
+static BatchedKernel batched_kernel(int nmax, bool stop, int wpb, int topo) {
+    if (nmax <= 32) return stop ? batched_kernel_n<T, 32, true>(wpb, topo) : batched_kernel_n<T, 32, false>(wpb, topo);
+    if (nmax <= 64) return stop ? batched_kernel_n<T, 64, true>(wpb, topo) : batched_kernel_n<T, 64, false>(wpb, topo);
+    return stop ? batched_kernel_n<T, 128, true>(wpb, topo) : batched_kernel_n<T, 128, false>(wpb, topo);
 }
 
 static int check_sched(const sogrand_sched_t *s) {
@@ -496,6 +505,23 @@ static int check_sched(const sogrand_sched_t *s) {
     if (s->steal_chunk < 1 || s->steal_chunk > SOGRAND_NMAX) return fail(SOGRAND_EINVAL, "steal_chunk outside 1..128");
     if (s->groups_per_cu < 1 || s->groups_per_cu > 64) return fail(SOGRAND_EINVAL, "groups_per_cu outside 1..64");
     return SOGRAND_OK;
+}
+
+// Tuned launch shapes by kind of batch: topology, precision, list-BLER stop on or off,
+// and the (n, k) of its codes.
+static std::mutex g_tuned_mu;
+static std::map<std::string, sogrand_sched_t> g_tuned;
+
+static std::string batch_kind(int topo, const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *p) {
+    std::vector<std::pair<int, int>> nk;
+    for (int i = 0; i < ncodes; i++) nk.emplace_back(codes[i]->n, codes[i]->k);
+    std::sort(nk.begin(), nk.end());
+    nk.erase(std::unique(nk.begin(), nk.end()), nk.end());
+    std::string kind = topo == kProduct ? "product" : "gldpc";
+    kind += p->precision == SOGRAND_F64 ? " f64" : " f32";
+    kind += p->list_bler_stop > 0.0 ? " stop" : " nostop";
+    for (const auto &c : nk) kind += " " + std::to_string(c.first) + ":" + std::to_string(c.second);
+    return kind;
 }
 
 static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
@@ -509,26 +535,44 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     if (nframes >= (1ull << 31)) return fail(SOGRAND_EINVAL, "nframes too large");
     if (!frame_code || !frame_offset || !llr_ch || !hard || !success)
         return fail(SOGRAND_EINVAL, "frame_code, frame_offset, llr_ch, hard and success are required");
+    for (int i = 0; i < ncodes; i++)
+        if (!codes[i]) return fail(SOGRAND_EINVAL, "codes[%d] is NULL", i);
     sogrand_sched_t sc;
     sogrand_sched_default(&sc);
-    if (sched) sc = *sched;
+    if (sched) {
+        sc = *sched;
+    } else {
+        std::lock_guard<std::mutex> g(g_tuned_mu);
+        const auto it = g_tuned.find(batch_kind(topo, codes, ncodes, params));
+        if (it != g_tuned.end()) sc = it->second;
+    }
     SG_TRY(check_sched(&sc));
     BatchArgs a{};
     CodeTable table{};
     int nmax = 0;
     for (int i = 0; i < ncodes; i++) {
-        if (!codes[i]) return fail(SOGRAND_EINVAL, "codes[%d] is NULL", i);
         SG_TRY(prepare_code(const_cast<sogrand_code_t *>(codes[i]), params->query_cap, &table.codes[i]));
         nmax = codes[i]->n > nmax ? codes[i]->n : nmax;
     }
     int dev = 0, cus = 0;
     SG_HIP(hipGetDevice(&dev));
     SG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const bool f64 = params->precision == SOGRAND_F64;
+    const BatchedKernel kern = f64 ? batched_kernel<double>(nmax, params->list_bler_stop > 0.0, sc.waves_per_group, topo)
+                                   : batched_kernel<float>(nmax, params->list_bler_stop > 0.0, sc.waves_per_group, topo);
+    const size_t dyn = sizeof(SlotLds) * sc.frames_per_group;
+    // no more groups than fit on the compute units at once: a group that could not start
+    // would find the frames taken when it did
+    int resident = 0;
+    SG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, reinterpret_cast<const void *>(kern),
+                                                        kWave * sc.waves_per_group, dyn));
+    if (resident < 1) return fail(SOGRAND_EINVAL, "launch shape does not fit a compute unit");
+    const size_t per_cu = (size_t)(sc.groups_per_cu < resident ? sc.groups_per_cu : resident);
     const size_t want = (nframes + sc.frames_per_group - 1) / sc.frames_per_group;
-    const size_t cap = (size_t)cus * sc.groups_per_cu;
+    const size_t cap = (size_t)cus * per_cu;
     const int grid = (int)(want < cap ? want : cap);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t esz = params->precision == SOGRAND_F64 ? sizeof(double) : sizeof(float);
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
     const size_t la_bytes = (size_t)grid * sc.frames_per_group * nmax * nmax * esz;
     char *ws = nullptr;
     const size_t head = 256 + ((sizeof(DevCode) * kMaxCodes + 255) & ~(size_t)255);
@@ -565,8 +609,7 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     hipLaunchKernelGGL(k_batched_init, dim3(1), dim3(64), 0, st, a.next_frame, table,
                        reinterpret_cast<DevCode *>(ws + 256), ncodes);
     const int tok = prof_start(PK_BATCHED, st);
-    if (params->precision == SOGRAND_F64) launch_batched<double>(a, sc.waves_per_group, grid, st);
-    else launch_batched<float>(a, sc.waves_per_group, grid, st);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * sc.waves_per_group), dyn, st, a);
     prof_stop(tok, st);
     a.status = status;
     if (status) hipLaunchKernelGGL(k_batched_status, dim3(1), dim3(64), 0, st, a.error, status);
@@ -576,16 +619,147 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     return rc;
 }
 
+// Times one batched decode of the sample with shape s on st (the stream's work before
+// it included).
+static int time_shape(int topo, const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                      size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset, uint64_t llr_len,
+                      const void *llr_ch, uint8_t *hard, uint8_t *success, const sogrand_sched_t &s,
+                      hipEvent_t e0, hipEvent_t e1, hipStream_t st, float &ms) {
+    SG_HIP(hipEventRecord(e0, st));
+    SG_TRY(decode_batched(topo, codes, ncodes, params, nframes, frame_code, frame_offset, llr_len, llr_ch, hard,
+                          nullptr, success, nullptr, nullptr, nullptr, nullptr, &s, st));
+    SG_HIP(hipEventRecord(e1, st));
+    SG_HIP(hipEventSynchronize(e1));
+    SG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return SOGRAND_OK;
+}
+
+static int tune(int topo, const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset, uint64_t llr_len,
+                const void *llr_ch, sogrand_sched_t *best, float *best_ms, hipStream_t st) {
+    if (!best) return fail(SOGRAND_EINVAL, "best is required");
+    if (nframes == 0) return fail(SOGRAND_EINVAL, "the tuning sample is empty");
+    SG_TRY(check_params(params));
+    if (!codes || ncodes < 1 || ncodes > kMaxCodes) return fail(SOGRAND_EINVAL, "ncodes outside 1..%d", kMaxCodes);
+    for (int i = 0; i < ncodes; i++)
+        if (!codes[i]) return fail(SOGRAND_EINVAL, "codes[%d] is NULL", i);
+    uint8_t *hard = nullptr, *success = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = SOGRAND_OK;
+    if (hipMalloc(reinterpret_cast<void **>(&hard), llr_len) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&success), nframes) != hipSuccess) {
+        rc = fail(SOGRAND_ENOMEM, "tuning output buffers");
+    } else if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = fail(SOGRAND_EDEVICE, "hipEventCreate failed");
+    }
+    sogrand_sched_t cur;
+    sogrand_sched_default(&cur);
+    float cur_ms = 0.f;
+    // a shape's time: the better of two runs (the first run of all also builds the tables)
+    auto measure = [&](const sogrand_sched_t &s, float &out) -> int {
+        float t0 = 0.f, t1 = 0.f;
+        SG_TRY(time_shape(topo, codes, ncodes, params, nframes, frame_code, frame_offset, llr_len, llr_ch, hard,
+                          success, s, e0, e1, st, t0));
+        SG_TRY(time_shape(topo, codes, ncodes, params, nframes, frame_code, frame_offset, llr_len, llr_ch, hard,
+                          success, s, e0, e1, st, t1));
+        out = t0 < t1 ? t0 : t1;
+        return SOGRAND_OK;
+    };
+    if (rc == SOGRAND_OK) rc = measure(cur, cur_ms);
+    static const int kWaves[] = {4, 8, 16}, kFrames[] = {1, 2, 3, 4}, kChunks[] = {1, 2, 4, 8};
+    for (int field = 0; field < 3 && rc == SOGRAND_OK; field++) {
+        const int *vals = field == 0 ? kWaves : field == 1 ? kFrames : kChunks;
+        const int nv = field == 0 ? 3 : 4;
+        const sogrand_sched_t base = cur;
+        for (int j = 0; j < nv && rc == SOGRAND_OK; j++) {
+            sogrand_sched_t cand = base;
+            int &f = field == 0 ? cand.waves_per_group : field == 1 ? cand.frames_per_group : cand.steal_chunk;
+            if (f == vals[j]) continue;
+            f = vals[j];
+            float t = 0.f;
+            rc = measure(cand, t);
+            if (rc == SOGRAND_OK && t < cur_ms) {
+                cur = cand;
+                cur_ms = t;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (hard) (void)hipFree(hard);
+    if (success) (void)hipFree(success);
+    if (rc != SOGRAND_OK) return rc;
+    {
+        std::lock_guard<std::mutex> g(g_tuned_mu);
+        g_tuned[batch_kind(topo, codes, ncodes, params)] = cur;
+    }
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return SOGRAND_OK;
+}
+
 }  // namespace sg
 
 extern "C" {
+
+int sogrand_sched_tune(int gldpc, const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
+                       size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset, uint64_t llr_len,
+                       const void *llr_ch, sogrand_sched_t *best, float *best_ms, void *stream) {
+    return sg::tune(gldpc ? sg::kGldpc : sg::kProduct, codes, ncodes, params, nframes, frame_code, frame_offset,
+                    llr_len, llr_ch, best, best_ms, static_cast<hipStream_t>(stream));
+}
+
+int sogrand_sched_table_save(const char *path) {
+    if (!path) return sg::fail(SOGRAND_EINVAL, "path is NULL");
+    std::lock_guard<std::mutex> g(sg::g_tuned_mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f) return sg::fail(SOGRAND_EINVAL, "cannot write %s", path);
+    for (const auto &e : sg::g_tuned)
+        std::fprintf(f, "%s|%d %d %d %d\n", e.first.c_str(), e.second.waves_per_group, e.second.frames_per_group,
+                     e.second.steal_chunk, e.second.groups_per_cu);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? SOGRAND_OK : sg::fail(SOGRAND_EINVAL, "cannot write %s", path);
+}
+
+int sogrand_sched_table_load(const char *path) {
+    if (!path) return sg::fail(SOGRAND_EINVAL, "path is NULL");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return sg::fail(SOGRAND_EINVAL, "cannot read %s", path);
+    std::map<std::string, sogrand_sched_t> got;
+    char line[512];
+    int lineno = 0, rc = SOGRAND_OK;
+    while (rc == SOGRAND_OK && std::fgets(line, sizeof line, f)) {
+        lineno++;
+        char *bar = std::strchr(line, '|');
+        sogrand_sched_t s{};
+        char tail = 0;
+        if (!bar || bar == line ||
+            std::sscanf(bar + 1, "%d %d %d %d %c", &s.waves_per_group, &s.frames_per_group, &s.steal_chunk,
+                        &s.groups_per_cu, &tail) != 4 ||
+            sg::check_sched(&s) != SOGRAND_OK) {
+            rc = sg::fail(SOGRAND_EINVAL, "%s line %d: not a tuned shape", path, lineno);
+            break;
+        }
+        got[std::string(line, bar)] = s;
+    }
+    std::fclose(f);
+    if (rc != SOGRAND_OK) return rc;
+    std::lock_guard<std::mutex> g(sg::g_tuned_mu);
+    for (const auto &e : got) sg::g_tuned[e.first] = e.second;
+    return (int)got.size();
+}
+
+void sogrand_sched_table_clear(void) {
+    std::lock_guard<std::mutex> g(sg::g_tuned_mu);
+    sg::g_tuned.clear();
+}
 
 void sogrand_sched_default(sogrand_sched_t *s) {
     if (!s) return;
     s->waves_per_group = 8;
     s->frames_per_group = 2;
     s->steal_chunk = 4;
-    s->groups_per_cu = 3;
+    s->groups_per_cu = 8;
 }
 
 int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,

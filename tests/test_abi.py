@@ -170,3 +170,32 @@ def test_serving_rejects_bad_arguments_before_device_work(sg):
     assert L.sogrand_serve_destroy(None) == 0
     assert L.sogrand_clock_ns() > 0
     assert ctypes.sizeof(sg.sogrand_result_t) == 72   # the C layout (natural alignment)
+
+
+def test_tuned_shape_table_round_trip(sg, tmp_path):
+    """The table of tuned launch shapes is host state: a saved file loads back entry for entry,
+    and a malformed or out-of-range line is refused without adding anything."""
+    sg.sched_table_clear()
+    good = tmp_path / "tuned.txt"
+    good.write_text("product f32 nostop 32:26 64:57 128:120|8 2 4 8\n"
+                    "gldpc f64 stop 32:26|16 3 1 2\n")
+    assert sg.sched_table_load(str(good)) == 2
+    saved = tmp_path / "saved.txt"
+    sg.sched_table_save(str(saved))
+    assert sorted(saved.read_text().splitlines()) == sorted(good.read_text().splitlines())
+    for bad in ("product f32 nostop 64:57|8 2 4\n",          # a field missing
+                "product f32 nostop 64:57|5 2 4 8\n",        # waves_per_group not 4, 8 or 16
+                "product f32 nostop 64:57|8 2 4 8 9\n",      # a field too many
+                "|8 2 4 8\n",                                # no kind
+                "product f32 nostop 64:57 8 2 4 8\n"):       # no separator
+        p = tmp_path / "bad.txt"
+        p.write_text("product f64 nostop 8:4|4 1 1 1\n" + bad)
+        with pytest.raises(sg.SograndError):
+            sg.sched_table_load(str(p))
+    sg.sched_table_save(str(saved))
+    assert len(saved.read_text().splitlines()) == 2     # nothing from the refused files
+    with pytest.raises(sg.SograndError):
+        sg.sched_table_load(str(tmp_path / "missing.txt"))
+    sg.sched_table_clear()
+    sg.sched_table_save(str(saved))
+    assert saved.read_text() == ""

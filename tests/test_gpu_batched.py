@@ -133,7 +133,10 @@ def test_batched_matches_oracle_on_sample(sg):
 def test_batched_result_independent_of_launch_shape(sg):
     codes, cidx, eb, offs, llr, cw = mixed(300, seed=9)
     ref = None
-    for w, fpg, ch, gpc in [(8, 4, 1, 2), (4, 1, 1, 1), (16, 8, 3, 1), (4, 2, 64, 4), (8, 3, 2, 3)]:
+    # hand-picked shapes, then every value the library's tuner tries (waves 4/8/16, frames 1-4,
+    # chunks 1/2/4/8) at as many groups per compute unit as fit
+    for w, fpg, ch, gpc in [(8, 4, 1, 2), (4, 1, 1, 1), (16, 8, 3, 1), (4, 2, 64, 4), (8, 3, 2, 3),
+                            (4, 1, 8, 8), (16, 2, 2, 8), (8, 3, 1, 8), (8, 4, 4, 8)]:
         print(f"[gpu] batched shape w={w} f={fpg} chunk={ch} gpc={gpc}", flush=True)
         out = run_batched(sg, codes, cidx, offs, llr, f32=True, sched=sg.sched(w, fpg, ch, gpc))
         assert int(out["status"][0]) == 0
@@ -165,3 +168,27 @@ def test_batched_single_frame_and_empty(sg):
     b = run_batched(sg, codes, cidx, offs, llr)
     p = run_plain_per_code(sg, codes, cidx, offs, llr)
     np.testing.assert_array_equal(b["hard"], p["hard"])
+
+
+def test_tuned_shape_gives_identical_results(sg):
+    """The library's tuner picks a shape on a sample and records it; decoding with that shape, and
+    with no shape (the recorded one), gives the default shape's per-frame results."""
+    import torch
+    codes, cidx, eb, offs, llr, cw = mixed(200, seed=21)
+    gcodes = [handle(sg, c) for c in codes]
+    x = torch.from_numpy(llr.astype(np.float32)).cuda()
+    fc, fo = torch.from_numpy(cidx).cuda(), torch.from_numpy(offs).cuda()
+    sg.sched_table_clear()
+    print("[gpu] tuner on 200 mixed frames", flush=True)
+    best, ms = sg.sched_tune(gcodes, fc, fo, x, list_max=4, query_cap=3000, max_iter=4)
+    assert ms > 0.0
+    assert best.waves_per_group in (4, 8, 16) and 1 <= best.frames_per_group <= 4
+    assert best.steal_chunk in (1, 2, 4, 8) and best.groups_per_cu == sg.sched().groups_per_cu
+    ref = run_batched(sg, codes, cidx, offs, llr, f32=True, sched=sg.sched(), qcap=3000, iters=4)
+    tuned = run_batched(sg, codes, cidx, offs, llr, f32=True, sched=best, qcap=3000, iters=4)
+    recorded = run_batched(sg, codes, cidx, offs, llr, f32=True, sched=None, qcap=3000, iters=4)
+    sg.sched_table_clear()
+    for out in (tuned, recorded):
+        assert int(out["status"][0]) == 0
+        for key in ("success", "half_iters", "sum_queries", "sum_max_queries", "hard"):
+            np.testing.assert_array_equal(out[key], ref[key], err_msg=key)
