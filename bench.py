@@ -552,7 +552,43 @@ def bench_headline(args, sg, np, torch, synth):
         config=prod["config"], value=prod["value"], unit=prod["unit"], roofline=prod["roofline"],
         forms={k: {kk: vv for kk, vv in v.items() if kk not in ("kernels", "per_snr")} | {"per_snr": v["per_snr"]}
                for k, v in prod["forms"].items()})
+    line["plan_small_batches"] = bench_plan(sg, np, torch, synth)
     return line
+
+
+def bench_plan(sg, np, torch, synth):
+    """Small batches, where launches cost: the plain path's decode of 100 [32,26]^2 frames (3 dB,
+    L=4, cap 1e3, FP64) called eagerly and replayed from its recorded graph (sogrand_plan_*),
+    each timed call to completion, at I_max 4 and 20."""
+    code = synth.ebch(32, 26)
+    g = sg.Code.ebch(32, 26)
+    llr = synth.product_frames(code, 3.0, 0, np.arange(100))[0]
+    x = torch.from_numpy(llr).to("cuda:0").contiguous()
+    res = {}
+    for iters in (4, 20):
+        out = sg.sogrand_decode_product(g, x, list_max=4, query_cap=1000, max_iter=iters)
+        plan = sg.Plan(g, x, list_max=4, query_cap=1000, max_iter=iters)
+        torch.cuda.synchronize()
+
+        def median_ms(fn, reps=50):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            return 1e3 * float(np.median(ts))
+        eager = median_ms(lambda: sg.sogrand_decode_product(g, x, list_max=4, query_cap=1000, max_iter=iters,
+                                                            outputs=out))
+        graph = median_ms(plan.launch)
+        same = all(bool(torch.equal(plan.outputs[k], out[k])) for k in ("hard", "success", "half_iters"))
+        plan.close()
+        res[f"I_max_{iters}"] = dict(launches=4 * iters + 1, eager_ms=eager, plan_ms=graph,
+                                     speedup=eager / graph, identical=same)
+    return dict(config={"workload": "100 eBCH [32,26]^2 frames, BPSK-AWGN 3 dB (seed 0), L=4, query cap 1e3, "
+                                    "FP64, alpha 0.5", "form": "plain path, eager vs recorded graph"}, **res)
 
 
 # --------------------------------------------------------------------------------------------

@@ -207,6 +207,32 @@ int sogrand_decode_gldpc(const sogrand_code_t *code, const sogrand_params_t *par
                          uint64_t *sum_max_queries, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Plans: a decode's launches captured once in a HIP graph                  */
+/* ------------------------------------------------------------------------ */
+/* The block turbo decoding of sogrand_decode_product (section "Iterative
+   decoding"), or of sogrand_decode_gldpc when gldpc is nonzero, over nframes
+   frames whose buffers are fixed when the plan is made.  create records the
+   decode's kernel launches (the initialisation, then a pass and a validity check
+   per half-iteration: 4 max_iter + 1 launches) into a HIP graph once, and
+   allocates the plan's own work buffer (the only allocation); it builds the
+   code's tables if needed and returns when done.  Arguments are those of
+   sogrand_decode_product (DEVICE buffers, same shapes, layouts and optional
+   outputs); they must stay valid while the plan exists.  launch enqueues one
+   replay of the graph on `stream`, on the device current at create: the frames
+   that llr_ch holds when it runs are decoded into the plan's outputs exactly as
+   sogrand_decode_product would decode them.  It saves the per-launch cost of the
+   separate launches, which counts when frames are few.  Launches of one plan
+   share its work buffer and outputs, so they must not overlap (use one stream,
+   or order them).  destroy frees the plan after waiting for the device; it
+   accepts NULL.  Errors: EINVAL (also for nframes 0), ENOMEM, EDEVICE. */
+typedef struct sogrand_plan sogrand_plan_t;
+int sogrand_plan_create(const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes, int gldpc,
+                        const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success, uint16_t *half_iters,
+                        uint64_t *sum_queries, uint64_t *sum_max_queries, sogrand_plan_t **out);
+int sogrand_plan_launch(sogrand_plan_t *plan, void *stream);
+void sogrand_plan_destroy(sogrand_plan_t *plan);
+
+/* ------------------------------------------------------------------------ */
 /* Batched decoding: mixed codes, one persistent launch                     */
 /* ------------------------------------------------------------------------ */
 /* Launch shape of the persistent kernel.  Each workgroup (waves_per_group

@@ -30,6 +30,7 @@ EXPORTS = [
     "sogrand_decode_component", "sogrand_decode_product", "sogrand_decode_product_noalloc", "sogrand_decode_gldpc",
     "sogrand_sched_default", "sogrand_decode_batched", "sogrand_decode_batched_gldpc",
     "sogrand_sched_tune", "sogrand_sched_table_save", "sogrand_sched_table_load", "sogrand_sched_table_clear",
+    "sogrand_plan_create", "sogrand_plan_launch", "sogrand_plan_destroy",
     "sogrand_clock_ns", "sogrand_serve_create", "sogrand_serve_submit", "sogrand_serve_poll",
     "sogrand_serve_stats", "sogrand_serve_replay", "sogrand_serve_destroy",
     "sogrand_profile_begin", "sogrand_profile_end", "sogrand_measure_valu_rate",
@@ -140,6 +141,10 @@ def lib():
     L.sogrand_sched_default.restype = None
     L.sogrand_decode_batched.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 10
     L.sogrand_decode_batched_gldpc.argtypes = [P, I, P, SZ, P, P, ctypes.c_uint64] + [P] * 10
+    L.sogrand_plan_create.argtypes = [P, P, SZ, I] + [P] * 8
+    L.sogrand_plan_launch.argtypes = [P, P]
+    L.sogrand_plan_destroy.argtypes = [P]
+    L.sogrand_plan_destroy.restype = None
     L.sogrand_sched_tune.argtypes = [I, P, I, P, SZ, P, P, ctypes.c_uint64, P, P, P, P]
     L.sogrand_sched_table_save.argtypes = [ctypes.c_char_p]
     L.sogrand_sched_table_load.argtypes = [ctypes.c_char_p]
@@ -299,6 +304,51 @@ def sogrand_decode_product_noalloc(code: Code, llr_ch, list_max=4, query_cap=100
     library; the output tensors are allocated here unless supplied in ``outputs``)."""
     return _decode_frames(lib().sogrand_decode_product_noalloc, code, llr_ch, list_max, query_cap, max_iter, alpha,
                           early_stop, want_app, outputs, stream, list_bler_stop)
+
+
+class Plan:
+    """sogrand_plan_create/launch/destroy: a product (or QC-GLDPC) decode of the frames in llr_ch
+    (F, n, n), recorded once as a HIP graph; launch() decodes what llr_ch holds then into the
+    plan's output tensors (``outputs``, the same dict as sogrand_decode_product returns)."""
+
+    def __init__(self, code: Code, llr_ch, list_max=4, query_cap=1000, max_iter=4, alpha=0.5, early_stop=True,
+                 want_app=False, gldpc=False, list_bler_stop=0.0):
+        import torch
+        if not llr_ch.is_cuda or not llr_ch.is_contiguous() or llr_ch.dim() != 3 or \
+                llr_ch.shape[1] != code.n or llr_ch.shape[2] != code.n:
+            raise ValueError("llr_ch must be a contiguous CUDA tensor of shape (F, n, n)")
+        F, n = llr_ch.shape[0], code.n
+        dev, dt = llr_ch.device, llr_ch.dtype
+        self.llr_ch, self.code = llr_ch, code
+        self.outputs = dict(
+            hard=torch.empty((F, n, n), dtype=torch.uint8, device=dev),
+            llr_app=torch.empty((F, n, n), dtype=dt, device=dev) if want_app else None,
+            success=torch.empty(F, dtype=torch.uint8, device=dev),
+            half_iters=torch.empty(F, dtype=torch.int16, device=dev),
+            sum_queries=torch.empty(F, dtype=torch.int64, device=dev),
+            sum_max_queries=torch.empty(F, dtype=torch.int64, device=dev),
+        )
+        p = params(list_max=list_max, query_cap=query_cap, alpha=alpha, max_iter=max_iter,
+                   early_stop=early_stop, precision=_precision_of(llr_ch), list_bler_stop=list_bler_stop)
+        o = self.outputs
+        h = ctypes.c_void_p()
+        _check(lib().sogrand_plan_create(code.handle, ctypes.byref(p), F, 1 if gldpc else 0, _ptr(llr_ch),
+                                         _ptr(o["hard"]), _ptr(o["llr_app"]), _ptr(o["success"]),
+                                         _ptr(o["half_iters"]), _ptr(o["sum_queries"]), _ptr(o["sum_max_queries"]),
+                                         ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().sogrand_plan_launch(self.handle, _stream(stream)))
+        return self.outputs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sogrand_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 def sogrand_decode_gldpc(code: Code, llr_ch, list_max=4, query_cap=1000, max_iter=20, alpha=0.6,

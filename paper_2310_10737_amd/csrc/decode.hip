@@ -1,5 +1,7 @@
 // SOGRAND component decoding and plain block-turbo product decoding on gfx950:
 // one launch per half-iteration plus a per-frame validity check.
+#include <new>
+
 #include "pair.hpp"
 
 namespace sg {
@@ -595,7 +597,108 @@ static int scratch_address(void **out) {
 
 }  // namespace sg
 
+// A decode's launches recorded once (see sogrand_plan_create): the graph and the work
+// buffer that its kernels address.
+struct sogrand_plan {
+    int device = 0;
+    char *ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace sg {
+
+static void plan_free(sogrand_plan *p) {
+    if (!p) return;
+    if (p->exec) {
+        // replays still running use the work buffer: wait for the plan's device first
+        int cur = 0;
+        const bool have = hipGetDevice(&cur) == hipSuccess;
+        if (have && cur != p->device) (void)hipSetDevice(p->device);
+        (void)hipDeviceSynchronize();
+        if (have && cur != p->device) (void)hipSetDevice(cur);
+        (void)hipGraphExecDestroy(p->exec);
+    }
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ws) (void)hipFree(p->ws);
+    delete p;
+}
+
+// Records run_frames on a capture stream of its own: the initialisation and, per
+// half-iteration, the pass and the validity check, all kernels (no memory set or copy
+// nodes), addressing a work buffer that the plan owns.
+static int plan_create(int topo, const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
+                       const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success, uint16_t *half_iters,
+                       uint64_t *sum_queries, uint64_t *sum_max_queries, sogrand_plan **out) {
+    if (!out) return fail(SOGRAND_EINVAL, "out is NULL");
+    *out = nullptr;
+    SG_TRY(check_frames(code, params, nframes, llr_ch, hard, success));
+    if (nframes == 0) return fail(SOGRAND_EINVAL, "a plan needs at least one frame");
+    DevCode dc;
+    SG_TRY(prepare_code(const_cast<sogrand_code_t *>(code), params->query_cap, &dc));
+    sogrand_plan *p = new (std::nothrow) sogrand_plan;
+    if (!p) return fail(SOGRAND_ENOMEM, "plan");
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        plan_free(p);
+        return fail(SOGRAND_EDEVICE, "hipGetDevice failed");
+    }
+    const size_t esz = params->precision == SOGRAND_F64 ? sizeof(double) : sizeof(float);
+    const WorkLayout w = work_layout(topo, nframes, code->n, esz);
+    if (hipMalloc(reinterpret_cast<void **>(&p->ws), w.total) != hipSuccess) {
+        plan_free(p);
+        return fail(SOGRAND_ENOMEM, "work buffer allocation of %zu bytes failed", w.total);
+    }
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        plan_free(p);
+        return fail(SOGRAND_EDEVICE, "capture stream creation failed");
+    }
+    int rc = SOGRAND_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = fail(SOGRAND_EDEVICE, "hipStreamBeginCapture failed");
+    } else {
+        rc = run_frames(topo, dc, params, nframes, llr_ch, hard, llr_app, success, half_iters, sum_queries,
+                        sum_max_queries, p->ws, cs, false);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        p->graph = g;
+        if (rc == SOGRAND_OK && (e != hipSuccess || !g)) rc = fail(SOGRAND_EDEVICE, "graph capture failed");
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc == SOGRAND_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(SOGRAND_EDEVICE, "hipGraphInstantiate failed");
+    if (rc != SOGRAND_OK) {
+        plan_free(p);
+        return rc;
+    }
+    *out = p;
+    return SOGRAND_OK;
+}
+
+}  // namespace sg
+
 extern "C" {
+
+int sogrand_plan_create(const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes, int gldpc,
+                        const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success, uint16_t *half_iters,
+                        uint64_t *sum_queries, uint64_t *sum_max_queries, sogrand_plan_t **out) {
+    return sg::plan_create(gldpc ? sg::kGldpc : sg::kProduct, code, params, nframes, llr_ch, hard, llr_app, success,
+                           half_iters, sum_queries, sum_max_queries, out);
+}
+
+int sogrand_plan_launch(sogrand_plan_t *plan, void *stream) {
+    using namespace sg;
+    if (!plan) return fail(SOGRAND_EINVAL, "plan is NULL");
+    int dev = 0;
+    SG_HIP(hipGetDevice(&dev));
+    if (dev != plan->device) return fail(SOGRAND_EINVAL, "the plan was made on device %d, not %d", plan->device, dev);
+    SG_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+    return SOGRAND_OK;
+}
+
+void sogrand_plan_destroy(sogrand_plan_t *plan) {
+    sg::plan_free(plan);
+}
 
 int sogrand_decode_product(const sogrand_code_t *code, const sogrand_params_t *params, size_t nframes,
                            const void *llr_ch, uint8_t *hard, void *llr_app, uint8_t *success,

@@ -199,3 +199,18 @@ def test_tuned_shape_table_round_trip(sg, tmp_path):
     sg.sched_table_clear()
     sg.sched_table_save(str(saved))
     assert saved.read_text() == ""
+
+
+def test_plan_rejects_bad_arguments_before_device_work(sg):
+    L = sg.lib()
+    p = sg.params()
+    one = ctypes.c_void_p(1)
+    out = ctypes.c_void_p()
+    code = sg.Code.ebch(8, 4)
+    ok = [code.handle, ctypes.byref(p), 4, 0, one, one, None, one, None, None, None, ctypes.byref(out)]
+    for i, value in ((0, None), (2, 0), (4, None), (5, None), (7, None), (11, None)):
+        a = list(ok)
+        a[i] = value
+        assert L.sogrand_plan_create(*a) == -1, i
+    assert L.sogrand_plan_launch(None, None) == -1
+    L.sogrand_plan_destroy(None)
