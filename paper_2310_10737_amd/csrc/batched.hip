@@ -138,34 +138,42 @@ __device__ void slot_refill(const BatchArgs &a, SlotLds &sl) {
 // masks hold the last pass's lines.  Bit l of the other family's word x is, for a
 // product code, bit x of line l; for a QC-GLDPC code, bit l of line (x + l) mod n
 // after a first-family pass and of line (x - l) mod n after a second-family pass
-// (both families take bit l from block l).
+// (both families take bit l from block l).  The H columns are staged in the wave's
+// own LDS scratch (its list-membership words, which the next decode clears), so the
+// loops below read LDS, without a dependent global load per bit.
 template <int TOPO>
-__device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, int lane, int h) {
+__device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, WaveLds &S, int lane, int h) {
     const int n = sl.n;
+    uint32_t *hc = S.zmask;
+    for (int t = lane; t < n; t += kWave) hc[t] = gptr(c.hcol)[t];
+    wave_sync();
     bool bad = false;
     for (int b = 0; b < 2; b++) {
         const int x = lane + kWave * b;
         if (x >= n) continue;
         const uint64_t m0 = sl.masks[x][0], m1 = sl.masks[x][1];
-        uint32_t s = 0;
-        for (int i = 0; i < n; i++) {
-            const uint64_t bit = i < 64 ? (m0 >> i) & 1ull : (m1 >> (i - 64)) & 1ull;
-            if (bit) s ^= gptr(c.hcol)[i];
-        }
-        uint32_t t = 0;
+        const int half = x >> 6, xb = x & 63;
+        uint32_t s = 0, t = 0;
         if constexpr (TOPO == kProduct) {
+#pragma unroll 1
             for (int l = 0; l < n; l++) {
-                const uint64_t w = x < 64 ? sl.masks[l][0] : sl.masks[l][1];
-                if ((w >> (x & 63)) & 1ull) t ^= gptr(c.hcol)[l];
+                const uint32_t col = hc[l];
+                const uint64_t own = l < 64 ? m0 >> l : m1 >> (l - 64);
+                s ^= col & (0u - (uint32_t)(own & 1ull));
+                t ^= col & (0u - (uint32_t)((sl.masks[l][half] >> xb) & 1ull));
             }
         } else {
             const bool after_first = (h & 1) != 0;
+#pragma unroll 1
             for (int l = 0; l < n; l++) {
+                const uint32_t col = hc[l];
+                const uint64_t own = l < 64 ? m0 >> l : m1 >> (l - 64);
+                s ^= col & (0u - (uint32_t)(own & 1ull));
                 int src = after_first ? x + l : x - l;
                 if (src >= n) src -= n;
                 if (src < 0) src += n;
                 const uint64_t w = l < 64 ? sl.masks[src][0] : sl.masks[src][1];
-                if ((w >> (l & 63)) & 1ull) t ^= gptr(c.hcol)[l];
+                t ^= col & (0u - (uint32_t)((w >> (l & 63)) & 1ull));
             }
         }
         bad |= (s != 0u) || (t != 0u);
@@ -432,7 +440,7 @@ void k_batched(BatchArgs a) {
         // this wave finished the half-iteration
         SG_CLOCK(v0);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const bool valid = slot_valid<TOPO>(sl, c, lane, h);
+        const bool valid = slot_valid<TOPO>(sl, c, S, lane, h);
         const bool retire = (valid && a.early_stop) || h == 2 * a.max_iter;
         if (retire) write_hard<TOPO>(a.hard + load_uniform(a.frame_offset + frame), sl, n, h, lane);
         if (lane == 0) {
