@@ -365,10 +365,9 @@ def bench_product(args, sg, np, torch, synth):
     iters, stop = args.iters, args.list_bler_stop
 
     def tune(x):
-        """The library's launch-shape tuner on every tenth frame (all three Eb/N0)."""
-        idx = torch.arange(0, total, 10, device=dev)
-        best, _ = sg.sched_tune([gcode], fcode[idx], foff[idx], x.contiguous().view(-1), L, QCAP, iters,
-                                list_bler_stop=stop)
+        """The library's launch-shape tuner on the step's own frames (a smaller sample weighs the
+        end of a launch, where the last frames drain, more than the full step does)."""
+        best, _ = sg.sched_tune([gcode], fcode, foff, x.contiguous().view(-1), L, QCAP, iters, list_bler_stop=stop)
         return best
 
     out_of, make_step, fcode, foff = plain_or_batched(sg, torch, gcode, total, N, dev, x64, x32, iters, stop,
@@ -434,12 +433,12 @@ def bench_mixed(args, sg, np, torch, synth):
         bout.update(sg.sogrand_decode_batched(gcodes, fc, fo, x, list_max=L, query_cap=qcap, max_iter=ITERS,
                                               sched_=sc))
 
-    # launch shape: the library's tuner on every tenth frame of the stream (--no-tune: the
-    # library default, for profiler runs that should see only full-size launches)
+    # launch shape: the library's tuner on the step's own frames, since a smaller sample weighs the
+    # end of a launch more than the full step does (--no-tune: the library default, for profiler
+    # runs that should see only full-size launches)
     sc = sg.sched()
     if not args.no_tune:
-        idx = torch.arange(0, F, 10, device=dev)
-        sc, _ = sg.sched_tune(gcodes, fc[idx], fo[idx], x, list_max=L, query_cap=qcap, max_iter=ITERS)
+        sc, _ = sg.sched_tune(gcodes, fc, fo, x, list_max=L, query_cap=qcap, max_iter=ITERS)
     ms_b, kern_b, work_b = timed(lambda: batched_step(sc), args.steps, args.warmup, sg, count=not args.no_count)
     if int(bout["status"].item()) != 0:
         raise SystemExit(f"batched kernel reported status {int(bout['status'].item())}")

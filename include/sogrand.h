@@ -296,9 +296,10 @@ int sogrand_decode_batched_gldpc(const sogrand_code_t *const *codes, int ncodes,
    to *best, its time in milliseconds to *best_ms (optional), and the library's
    table of tuned shapes, under the batch's kind: topology, precision, whether
    the list-BLER stop is on, and the (n, k) of its codes.  A later batched call
-   with sched NULL on a batch of that kind uses it.  The sample should be a few
-   thousand frames that look like the workload.  Blocks until done; results of a
-   decode never depend on the shape.  Errors: EINVAL (also for an empty sample),
+   with sched NULL on a batch of that kind uses it.  The sample should look like
+   the batches the shape will serve, in size too: the end of a launch, where the
+   last frames drain, weighs more in a small sample.  Blocks until done; results
+   of a decode never depend on the shape.  Errors: EINVAL (also for an empty sample),
    ENOMEM, EDEVICE. */
 int sogrand_sched_tune(int gldpc, const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
                        size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset, uint64_t llr_len,
