@@ -58,6 +58,7 @@ struct BatchArgs {
     int slots;
     int chunk;
     uint32_t *next_frame;           // global frame counter
+    const uint32_t *order;          // [F] frame taken at each count (longest codes first), or NULL: in order
     uint32_t *error;                // bit 0: a wave stopped waiting; bit 1: a frame descriptor was invalid
     uint32_t *status;               // caller's copy of the error bits, or NULL
     ProfCounters *prof;
@@ -105,11 +106,12 @@ __device__ __forceinline__ void slot_publish(SlotLds &sl) {
 // reported and the frame is skipped with success 0 and zero half-iterations.
 __device__ void slot_refill(const BatchArgs &a, SlotLds &sl) {
     for (;;) {
-        const uint32_t f = atomicAdd(a.next_frame, 1u);
-        if (f >= a.nframes) {
+        const uint32_t k = atomicAdd(a.next_frame, 1u);
+        if (k >= a.nframes) {
             sl.frame = -1;
             return;
         }
+        const uint32_t f = a.order ? a.order[k] : k;
         const int code = a.frame_code[f];
         const int n = code < a.ncodes ? a.codes[code].n : 0;
         const uint64_t off = a.frame_offset[f];
@@ -477,6 +479,77 @@ __global__ void k_batched_init(uint32_t *counters, CodeTable table, DevCode *dst
     if (threadIdx.x < (unsigned)ncodes) dst[threadIdx.x] = table.codes[threadIdx.x];
 }
 
+// The order in which the persistent kernel takes frames: by code length, longest
+// first, by a stable counting sort on the rank of each frame's code (descriptors that
+// name no code go last).  The frames of the longest codes then start early, and the
+// end of the launch, when waves run out of frames, is left to the shortest ones.
+// Results do not depend on the order.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = kMaxCodes + 1;
+
+struct CodeRanks {
+    uint8_t rank[kMaxCodes];   // bucket of each code index
+    int ncodes;                // bucket of an invalid code index
+};
+
+__global__ __launch_bounds__(kOrderThreads) void k_batched_order(const uint8_t *frame_code, uint32_t nframes,
+                                                                 CodeRanks rk, uint32_t *order) {
+    __shared__ uint32_t cnt[kOrderBuckets][kOrderThreads];   // frames per bucket and thread, then offsets
+    __shared__ uint32_t wsum[kOrderBuckets][kOrderThreads / kWave];
+    __shared__ uint32_t base[kOrderBuckets];
+    const uint32_t t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+    const uint32_t per = (nframes + kOrderThreads - 1) / kOrderThreads;
+    const uint32_t lo = t * per < nframes ? t * per : nframes;
+    const uint32_t hi = lo + per < nframes ? lo + per : nframes;
+    auto bucket = [&](uint32_t f) -> uint32_t {
+        const uint32_t c = frame_code[f];
+        return c < (uint32_t)rk.ncodes ? rk.rank[c] : (uint32_t)rk.ncodes;
+    };
+    for (int b = 0; b < kOrderBuckets; b++) cnt[b][t] = 0u;
+    for (uint32_t f = lo; f < hi; f++) cnt[bucket(f)][t]++;
+    // exclusive prefix of each bucket's counts over the threads: within each wave by
+    // shuffles, then over the waves' totals
+    for (int b = 0; b < kOrderBuckets; b++) {
+        const uint32_t v = cnt[b][t];
+        uint32_t incl = v;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t u = (uint32_t)__shfl_up((int)incl, d);
+            if (lane >= (uint32_t)d) incl += u;
+        }
+        cnt[b][t] = incl - v;
+        if (lane == kWave - 1) wsum[b][wave] = incl;
+    }
+    __syncthreads();
+    if (t < (uint32_t)kOrderBuckets) {
+        uint32_t acc = 0;
+        for (int w = 0; w < kOrderThreads / kWave; w++) {
+            const uint32_t x = wsum[t][w];
+            wsum[t][w] = acc;
+            acc += x;
+        }
+        base[t] = acc;   // the bucket's total, made a base below
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < kOrderBuckets; b++) {
+            const uint32_t x = base[b];
+            base[b] = acc;
+            acc += x;
+        }
+    }
+    __syncthreads();
+    uint32_t pos[kOrderBuckets];
+    for (int b = 0; b < kOrderBuckets; b++) pos[b] = base[b] + wsum[b][wave] + cnt[b][t];
+    for (uint32_t f = lo; f < hi; f++) {
+        const uint32_t b = bucket(f);
+        uint32_t p = 0;
+        for (int j = 0; j < kOrderBuckets; j++)
+            if ((uint32_t)j == b) p = pos[j]++;
+        order[p] = f;
+    }
+}
+
 __global__ void k_batched_status(const uint32_t *error, uint32_t *status) {
     if (threadIdx.x == 0) *status = *error;
 }
@@ -583,7 +656,11 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     const size_t esz = f64 ? sizeof(double) : sizeof(float);
     const size_t la_bytes = (size_t)grid * sc.frames_per_group * nmax * nmax * esz;
     char *ws = nullptr;
-    const size_t head = 256 + ((sizeof(DevCode) * kMaxCodes + 255) & ~(size_t)255);
+    // frames of codes of different lengths are taken longest first
+    bool mixed = false;
+    for (int i = 1; i < ncodes; i++) mixed |= codes[i]->n != codes[0]->n;
+    const size_t order_bytes = mixed ? (nframes * sizeof(uint32_t) + 255) & ~(size_t)255 : 0;
+    const size_t head = 256 + ((sizeof(DevCode) * kMaxCodes + 255) & ~(size_t)255) + order_bytes;
     const size_t total = head + la_bytes;
     if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
         return fail(SOGRAND_ENOMEM, "work buffer allocation of %zu bytes failed", total);
@@ -614,8 +691,21 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     a.next_frame = reinterpret_cast<uint32_t *>(ws);
     a.error = reinterpret_cast<uint32_t *>(ws) + 1;
     a.prof = prof_counters(PK_BATCHED);
+    a.order = nullptr;
     hipLaunchKernelGGL(k_batched_init, dim3(1), dim3(64), 0, st, a.next_frame, table,
                        reinterpret_cast<DevCode *>(ws + 256), ncodes);
+    if (mixed) {
+        CodeRanks rk{};
+        rk.ncodes = ncodes;
+        int idx[kMaxCodes];
+        for (int i = 0; i < ncodes; i++) idx[i] = i;
+        std::stable_sort(idx, idx + ncodes, [&](int x, int y) { return codes[x]->n > codes[y]->n; });
+        for (int r = 0; r < ncodes; r++) rk.rank[idx[r]] = (uint8_t)r;
+        uint32_t *order = reinterpret_cast<uint32_t *>(ws + head - order_bytes);
+        hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(kOrderThreads), 0, st, frame_code, (uint32_t)nframes, rk,
+                           order);
+        a.order = order;
+    }
     const int tok = prof_start(PK_BATCHED, st);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * sc.waves_per_group), dyn, st, a);
     prof_stop(tok, st);
