@@ -85,7 +85,7 @@ static void order_emit(oorder *o, const uint8_t *cur, int w) {
         o->ranks = (uint8_t *)realloc(o->ranks, (size_t)o->rcap);
     }
     o->off[o->count] = o->nranks;
-    memcpy(o->ranks + o->nranks, cur, (size_t)w);
+    if (w > 0) memcpy(o->ranks + o->nranks, cur, (size_t)w);   /* the zero pattern stores nothing */
     o->nranks += w;
     o->count++;
     o->off[o->count] = o->nranks;
