@@ -800,13 +800,54 @@ def bench_serve(args, sg, np, torch, synth):
                      host_ms_between_steps=st1["host_ms"] - st0["host_ms"], per_code=per_code)
 
 
+PHASES = ["hard decision, syndrome, rho", "ranking", "class masses", "query loop", "soft output",
+          "rest of the line (loads, writes, masks)", "finding work (between lines)",
+          "half hand-over (validity, retire or reopen)"]
+
+
+def bench_phases(args, sg, np, torch, synth):
+    """Wave clock cycles per word, by decode phase, of the persistent kernel in the clocked
+    measurement build (`build.py --phase-clocks`): on the mixed stream and on [64,57]^2 frames at
+    Eb/N0 uniform in [2.5, 3.5] dB, one decode each at the default launch shape."""
+    res = {}
+    for tag, nks, lo, hi, seed, qcap in [("mixed", [(32, 26), (64, 57), (128, 120)], 2.0, 4.0, 4, 100000),
+                                         ("product_64x57", [(64, 57)], 2.5, 3.5, 1, 10000)]:
+        F = args.frames if args.frames_set else 30000
+        codes = [synth.ebch(*nk) for nk in nks]
+        cidx, eb, offs, llr, cw = synth.mixed_product_frames(codes, lo, hi, seed, np.arange(F))
+        g = [sg.Code.ebch(*nk) for nk in nks]
+        x = torch.from_numpy(llr.astype(np.float32)).to("cuda:0")
+        fc, fo = torch.from_numpy(cidx).to("cuda:0"), torch.from_numpy(offs).to("cuda:0")
+
+        def run():
+            return sg.sogrand_decode_batched(g, fc, fo, x, list_max=L, query_cap=qcap, max_iter=ITERS)
+        run()
+        torch.cuda.synchronize()
+        sg.profile_begin(count_work=True)
+        run()
+        torch.cuda.synchronize()
+        k = sg.profile_end()["batched"]
+        tot, words = float(sum(k["phase_cycles"])), float(k["words"])
+        res[tag] = dict(
+            config={"workload": f"{F} frames of {'/'.join(f'[{n},{kk}]^2' for n, kk in nks)} eBCH, BPSK-AWGN "
+                                f"Eb/N0 U[{lo},{hi}] dB (seed {seed}), L={L}, query cap {qcap}, {ITERS} iterations, "
+                                f"FP32 storage, default launch shape"},
+            words=int(k["words"]), queries=int(k["queries"]), cycles_per_word=tot / words,
+            phases={nm: dict(cycles_per_word=c / words, share=c / tot) for nm, c in zip(PHASES, k["phase_cycles"])})
+        del x, fc, fo
+    return {"metric": "wave clock cycles per word by decode phase (clocked measurement build)",
+            "value": res["mixed"]["cycles_per_word"], "unit": "cycles/word", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "higher_is_better": False, "data": "synthetic", "dtype": "f64",
+            "config": res["mixed"]["config"], "mixed": res["mixed"], "product_64x57": res["product_64x57"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "product", "mixed", "component", "serve", "gldpc", "rician"])
+                    choices=["headline", "product", "mixed", "component", "serve", "gldpc", "rician", "phases"])
     ap.add_argument("--frames", type=int, default=None, help="frames per Eb/N0 (product) or in total (mixed)")
     ap.add_argument("--words", type=int, default=1 << 20, help="component words")
     ap.add_argument("--requests", type=int, default=100000, help="serving requests")
@@ -848,8 +889,16 @@ def main() -> int:
     import paper_2310_10737_amd as sg
     import synth
 
+    if args.workload == "phases":
+        # the clocked measurement build, loaded in place of the product library
+        from paper_2310_10737_amd import build as sgbuild
+        if not os.path.exists(sgbuild.CLOCKED_LIB):
+            print(f"{sgbuild.CLOCKED_LIB} is missing: build it with "
+                  "python3 paper_2310_10737_amd/build.py --phase-clocks", file=sys.stderr)
+            return 2
+        sg._LIBPATH = sgbuild.CLOCKED_LIB
     fn = dict(headline=bench_headline, product=bench_product, mixed=bench_mixed, component=bench_component,
-              serve=bench_serve, gldpc=bench_gldpc, rician=bench_rician)[args.workload]
+              serve=bench_serve, gldpc=bench_gldpc, rician=bench_rician, phases=bench_phases)[args.workload]
     line = fn(args, sg, np, torch, synth)
     if args.copy_mib > 0:
         # a plain device copy of known size: calibrates the HBM byte counters of profiler runs

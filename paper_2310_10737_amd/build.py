@@ -14,6 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsogrand.so")
+# the same library with per-phase wave clocks in the decode (SG_PHASE_CLOCKS), a measurement
+# build that `bench.py --workload phases` loads instead of the product library
+CLOCKED_LIB = os.path.join(HERE, "libsogrand_clocked.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["code.hip", "decode.hip", "batched.hip", "serve.hip", "profile.hip"]
@@ -35,29 +38,34 @@ FLAGS = [
 SOURCE_FLAGS = {"batched.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + SOURCE_FLAGS.get(src, []) + ["-c", "-o", obj, os.path.join(CSRC, src)]
+def _compile(src: str, verbose: bool, clocked: bool = False) -> str:
+    objdir = os.path.join(OBJDIR, "clocked") if clocked else OBJDIR
+    obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+    extra = ["-DSG_PHASE_CLOCKS"] if clocked else []
+    cmd = [HIPCC] + FLAGS + SOURCE_FLAGS.get(src, []) + extra + ["-c", "-o", obj, os.path.join(CSRC, src)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source of the library and link them into one shared object."""
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(verbose: bool = False, clocked: bool = False) -> str:
+    """Compile every HIP source of the library and link them into one shared object (with
+    clocked, the measurement build with per-phase wave clocks)."""
+    os.makedirs(os.path.join(OBJDIR, "clocked") if clocked else OBJDIR, exist_ok=True)
     workers = max(1, min(len(SOURCES), len(os.sched_getaffinity(0))))
     with ThreadPoolExecutor(workers) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, clocked), SOURCES))
+    lib = CLOCKED_LIB if clocked else LIB
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, clocked="--phase-clocks" in sys.argv[1:]))
