@@ -288,7 +288,9 @@ static int build_schedule(const sogrand_code_t *c, int dev, uint32_t cap, Schedu
     int rc = SOGRAND_OK;
     ClassDesc *d_desc = nullptr;
     for (int cl = 0; cl < ncls && rc == SOGRAND_OK; cl++) {
-        size_t npat = s->len[cl] ? s->len[cl] : 1;
+        // the patterns, then two chunks of zero patterns: the decode loads whole 64-pattern
+        // chunks up to two past the one it tests, without per-lane bounds
+        const size_t npat = s->len[cl] + kSchedPad;
         if (hipMalloc(&s->pat[cl], npat * sizeof(uint4)) != hipSuccess ||
             hipMalloc(&s->wmax[cl], wmax[cl].size() * sizeof(uint32_t)) != hipSuccess) {
             rc = fail(SOGRAND_ENOMEM, "device allocation of the query schedule failed");
@@ -306,6 +308,10 @@ static int build_schedule(const sogrand_code_t *c, int dev, uint32_t cap, Schedu
         }
         if (hipMemcpyAsync(d_desc, descs[cl].data(), nd * sizeof(ClassDesc), hipMemcpyHostToDevice, st) != hipSuccess) {
             rc = fail(SOGRAND_EDEVICE, "copy of the schedule classes failed");
+            break;
+        }
+        if (hipMemsetAsync(s->pat[cl] + s->len[cl], 0, kSchedPad * sizeof(uint4), st) != hipSuccess) {
+            rc = fail(SOGRAND_EDEVICE, "clearing the schedule's padding failed");
             break;
         }
         hipLaunchKernelGGL(k_schedule, dim3((unsigned)((nd + 63) / 64)), dim3(64), 0, st, d_desc, (int)nd, n, s->pat[cl]);

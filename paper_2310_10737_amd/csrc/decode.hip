@@ -30,7 +30,7 @@ struct ComponentArgs {
 
 
 template <typename T, int NS, int WPB, bool STOP>
-__global__ __launch_bounds__(kWave * WPB) void k_component(ComponentArgs a) {
+__global__ __launch_bounds__(kWave * WPB) __attribute__((amdgpu_waves_per_eu(8))) void k_component(ComponentArgs a) {
     constexpr int NB = Lanes<NS>::NB;
     __shared__ WaveLds lds[WPB];
     const int lane = threadIdx.x & (kWave - 1);
@@ -157,7 +157,7 @@ struct Lines {
 // One wave per word: ROWS decodes word `line` of the first family (the rows of a
 // product code) of L_Ch + L_A, otherwise of the second.
 template <typename T, int NS, bool ROWS, int WPB, bool STOP, int TOPO>
-__global__ __launch_bounds__(kWave * WPB) void k_product_pass(ProductArgs a) {
+__global__ __launch_bounds__(kWave * WPB) __attribute__((amdgpu_waves_per_eu(8))) void k_product_pass(ProductArgs a) {
     using LN = Lines<TOPO, ROWS>;
     constexpr int NB = Lanes<NS>::NB;
     __shared__ WaveLds lds[WPB];

@@ -50,6 +50,8 @@ struct Schedule {
 // rows of circulants); which variable nodes form each component word is described
 // where the kernels map words to frame positions.
 constexpr int kProduct = 0, kGldpc = 1;
+// zero patterns after the end of each query schedule: two 64-pattern chunks
+constexpr size_t kSchedPad = 128;
 
 // Device-side view of a code and its schedule, passed by value to kernels.
 struct DevCode {

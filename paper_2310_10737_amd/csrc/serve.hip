@@ -96,7 +96,7 @@ struct ServeArgs {
 // One wave per line of one word width.  Every frame of the launch runs the
 // half-iteration its descriptor names (rows for odd h).
 template <typename T, int NS, bool STOP>
-__global__ __launch_bounds__(kBlock) void k_serve_pass(ServeArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_serve_pass(ServeArgs a) {
     constexpr int NB = Lanes<NS>::NB;
     __shared__ WaveLds lds[kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);

@@ -727,10 +727,10 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     uint32_t Q = 0;
     double s_lane = 0.0;   // this lane's share of the tested nonzero-pattern mass (relative to p(0|r))
     uint32_t w_lane = 0;   // this lane's share of the tested pattern weights (counting only)
-    // patterns of the next two chunks are in flight while a chunk is tested
-    uint4 e_next = make_uint4(0u, 0u, 0u, 0u), e_next2 = make_uint4(0u, 0u, 0u, 0u);
-    if ((uint32_t)lane < limit) e_next = gload(tab, lane);
-    if ((uint32_t)lane + kWave < limit) e_next2 = gload(tab, kWave + lane);
+    // patterns of the next two chunks are in flight while a chunk is tested; the schedule
+    // ends in two chunks of zero patterns, so whole chunks load without per-lane bounds
+    // (a lane at or past `limit` tests whatever it loaded but never counts)
+    uint4 e_next = gload(tab, lane), e_next2 = gload(tab, kWave + lane);
     uint32_t wm_next = wm[0];
     uint32_t wm_next2 = limit > (uint32_t)kWave ? wm[1] : 0u;
     for (uint32_t base = 0; base < limit; base += kWave) {
@@ -743,8 +743,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         wm_next = wm_next2;
         const uint32_t nb2 = nb + kWave;
         if (nb2 < limit) {
-            e_next2 = make_uint4(0u, 0u, 0u, 0u);
-            if (nb2 + (uint32_t)lane < limit) e_next2 = gload(tab, nb2 + lane);
+            e_next2 = gload(tab, nb2 + lane);
             wm_next2 = wm[nb2 >> 6];
         }
         const bool act = base + (uint32_t)lane < limit;
