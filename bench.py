@@ -736,6 +736,20 @@ def bench_serve(args, sg, np, torch, synth):
         srv.submit(gcodes[c], np.ascontiguousarray(x[offs[f]:offs[f] + n * n]), tag=0)
     while srv.poll(max_results=8, timeout_ns=-1, want_hard=False):
         pass
+    # an untimed warm-up replay of the first requests at the same rate, so that every lane
+    # has run steps (its first ones carry one-time costs) before the timed replay starts
+    W = min(8192, R)
+    tw = sg.sogrand_clock_ns() + 5_000_000
+    warm = {}
+    wth = threading.Thread(target=lambda: warm.update(r=srv.replay(gcodes, cidx[:W], offs[:W], x, arrival_ns[:W], tw)))
+    wth.start()
+    got = 0
+    while got < W:
+        batch = srv.poll(max_results=1024, timeout_ns=50_000_000, want_hard=False)
+        got += len(batch)
+        if not batch and not wth.is_alive() and "r" not in warm:
+            raise SystemExit("the warm-up replay failed")
+    wth.join()
     st0 = srv.stats()
     results = []
     t0 = sg.sogrand_clock_ns() + 20_000_000
@@ -785,7 +799,8 @@ def bench_serve(args, sg, np, torch, synth):
     gaps_ms = np.diff(ends) / 1e6 if ends.size > 1 else np.zeros(1)
     mid = (arrival_ns[tags] >= np.percentile(arrival_ns, 10)) & (arrival_ns[tags] <= np.percentile(arrival_ns, 90))
     config = {"workload": f"{R} requests, Poisson arrivals {rate:.0f}/s, eBCH [32,26]^2/[64,57]^2/[128,120]^2 "
-                          f"uniform, Eb/N0 U[2.5,4.0] dB, L=4, query cap {qcap}, 6 iterations, FP32 storage",
+                          f"uniform, Eb/N0 U[2.5,4.0] dB, L=4, query cap {qcap}, 6 iterations, FP32 storage "
+                          f"(timed after an untimed replay of the first {W} requests)",
               "hbm_budget_bytes": budget, "form": "served (continuous batching)", "parallelism": "single GPU"}
     return base_line(args, "decoded info bits/s (served) and p99 frame latency", info / span_s, "info bits/s",
                      span_s * 1e3, "f64", config, None, None,

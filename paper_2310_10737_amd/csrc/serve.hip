@@ -212,19 +212,51 @@ __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
         const bool rows = (d.h & 1u) != 0;
         uint8_t *hd = reinterpret_cast<uint8_t *>(a.mirror_w + d.slot + sl.hard);
         const int nn = n * n;
-        // Whole 16-byte units per lane when n*n is a multiple of 16 (the unit is then aligned),
-        // else one byte per lane.  The host copy is pinned host memory: 4-byte stores there
+        // Whole 16-byte units per lane when a row of the frame is (n a multiple of 16): the
+        // unit's 16 elements are 16 bits of one row of the hard decision, which the last pass's
+        // masks give directly when its lines were rows, and their transpose (one ballot per row
+        // and half) when they were columns.  Each 4 bits spread to 4 bytes with one multiply.
+        // Otherwise 16-byte units that may straddle rows when n*n is a multiple of 16, else one
+        // byte per lane.  The host copy is pinned host memory: 4-byte stores there
         // were seen to leave single bytes stale on the test machine, 16-byte stores never.
-        if ((nn & 15) == 0) {
+        if ((n & 15) == 0) {
+            __shared__ uint64_t rm_s[kWavesPerBlock][2 * SOGRAND_NMAX];
+            const uint64_t *rm = mk_s[wave];
+            if (!rows) {
+                for (int j = 0; j < n; j++) {
+                    const int h = j >> 6, sh = j & 63;
+                    const uint64_t lo = __ballot(lane < n && ((mk_s[wave][lane * 2 + h] >> sh) & 1ull));
+                    const uint64_t hi = __ballot(lane + kWave < n && ((mk_s[wave][(lane + kWave) * 2 + h] >> sh) & 1ull));
+                    if (lane == 0) {
+                        rm_s[wave][j * 2] = lo;
+                        rm_s[wave][j * 2 + 1] = hi;
+                    }
+                }
+                wave_sync();
+                rm = rm_s[wave];
+            }
+            const int upr = n >> 4;   // 16-element units per row
+            for (int u = lane; u < nn / 16; u += kWave) {
+                const int j = u / upr, k = u - j * upr;
+                const uint32_t b = (uint32_t)(rm[j * 2 + (k >> 2)] >> (16 * (k & 3))) & 0xffffu;
+                uint32_t w[4];
+                for (int q = 0; q < 4; q++) w[q] = (((b >> (4 * q)) & 0xfu) * 0x204081u) & 0x01010101u;
+                *reinterpret_cast<uint4 *>(hd + 16 * u) = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+        } else if ((nn & 15) == 0) {
+            // 16-byte units that may straddle rows (n*n a multiple of 16: the unit is aligned)
             for (int o = lane * 16; o < nn; o += kWave * 16) {
+                int j = o / n, c = o - j * n;
                 uint32_t w[4];
                 for (int q = 0; q < 4; q++) {
                     uint32_t v = 0;
                     for (int e = 0; e < 4; e++) {
-                        const int p = o + 4 * q + e;
-                        const int j = p / n, c = p - j * n;
                         const int line = rows ? j : c, bit = rows ? c : j;
                         v |= (uint32_t)((mk_s[wave][line * 2 + (bit >> 6)] >> (bit & 63)) & 1ull) << (8 * e);
+                        if (++c == n) {
+                            c = 0;
+                            ++j;
+                        }
                     }
                     w[q] = v;
                 }
