@@ -262,9 +262,10 @@ void sogrand_sched_default(sogrand_sched_t *s);
    NULL.  status (DEVICE, optional) receives 0, or bit 0 if a wave gave up waiting
    (not expected) and bit 1 if a frame descriptor was out of range (that frame is
    skipped with success 0 and half_iters 0, and its hard and llr_app are not
-   written).  Frames are taken longest code first (a stable sort by code length
-   on the device), so that the end of the launch is left to the shortest ones;
-   the order changes no result.  sched NULL = the shape recorded for this kind of batch by
+   written).  Frames are taken longest code first and, among the frames of the
+   shortest code, those with the smallest mean |L_Ch| over their first 1024
+   elements first (a sort on the device), so that the end of the launch is left
+   to short, easy frames; the order changes no result.  sched NULL = the shape recorded for this kind of batch by
    sogrand_sched_tune or sogrand_sched_table_load, else the default.  Errors:
    EINVAL, ENOMEM, EDEVICE. */
 int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,

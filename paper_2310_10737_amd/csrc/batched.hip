@@ -58,7 +58,7 @@ struct BatchArgs {
     int slots;
     int chunk;
     uint32_t *next_frame;           // global frame counter
-    const uint32_t *order;          // [F] frame taken at each count (longest codes first), or NULL: in order
+    const uint32_t *order;          // [F] frame taken at each count (longest codes, then hardest frames, first)
     uint32_t *error;                // bit 0: a wave stopped waiting; bit 1: a frame descriptor was invalid
     uint32_t *status;               // caller's copy of the error bits, or NULL
     ProfCounters *prof;
@@ -479,37 +479,123 @@ __global__ void k_batched_init(uint32_t *counters, CodeTable table, DevCode *dst
     if (threadIdx.x < (unsigned)ncodes) dst[threadIdx.x] = table.codes[threadIdx.x];
 }
 
-// The order in which the persistent kernel takes frames: by code length, longest
-// first, by a stable counting sort on the rank of each frame's code (descriptors that
-// name no code go last).  The frames of the longest codes then start early, and the
-// end of the launch, when waves run out of frames, is left to the shortest ones.
-// Results do not depend on the order.
-constexpr int kOrderThreads = 1024;
-constexpr int kOrderBuckets = kMaxCodes + 1;
+// The order in which the persistent kernel takes frames: those of the longest codes
+// first, so that the end of the launch, when waves run out of frames, is left to the
+// shortest code; and the frames of that last code hardest first, judged by their mean
+// channel reliability |L| (small means many unreliable bits, and so more queries and
+// half-iterations), so that the launch ends on short, easy frames.  The frames of the
+// other codes keep their input order: taking the hardest of them together, early on,
+// gave slower launches, since the waves of a workgroup then more often wait on the
+// long words of all of its frames at once.  Results do not depend on the order.
+//
+// k_frame_ease writes each frame's mean |L| over a sample of its first elements (one
+// wave per frame; frames of other codes get 0, invalid descriptors -1); k_batched_order
+// then sorts the frames by (rank of the code's length, ease level), the level being the
+// frame's place between the smallest and largest ease among the last code's frames, cut
+// into `levels` equal steps.  Descriptors that name no code or a block outside llr_ch,
+// and frames whose sample holds a NaN, go last.
+constexpr int kEaseSample = 1024;
+constexpr int kOrderThreads = 256;
+constexpr int kOrderBins = 48;   // one per code, plus the last code's extra levels and the invalid frames
 
-struct CodeRanks {
-    uint8_t rank[kMaxCodes];   // bucket of each code index
-    int ncodes;                // bucket of an invalid code index
+struct OrderKeys {
+    uint8_t rank[kMaxCodes];   // rank of each code index by length, longest first
+    int n[kMaxCodes];          // length of each code index
+    int ncodes;
+    int last;                  // index of the code of rank ncodes - 1, whose frames are ordered by ease
+    int levels;                // ease levels: ncodes + levels <= kOrderBins
 };
 
-__global__ __launch_bounds__(kOrderThreads) void k_batched_order(const uint8_t *frame_code, uint32_t nframes,
-                                                                 CodeRanks rk, uint32_t *order) {
-    __shared__ uint32_t cnt[kOrderBuckets][kOrderThreads];   // frames per bucket and thread, then offsets
-    __shared__ uint32_t wsum[kOrderBuckets][kOrderThreads / kWave];
-    __shared__ uint32_t base[kOrderBuckets];
+template <typename T>
+__global__ __launch_bounds__(256) void k_frame_ease(const uint8_t *frame_code, const uint64_t *frame_offset,
+                                                    uint32_t nframes, uint64_t llr_len, const T *llr,
+                                                    OrderKeys ok, float *ease) {
+    const uint32_t f = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    if (f >= nframes) return;
+    const uint32_t c = frame_code[f];
+    const uint64_t off = frame_offset[f];
+    float s = 0.f;
+    uint32_t m = 0;
+    bool valid = false;
+    if (c < (uint32_t)ok.ncodes) {
+        const uint64_t len = (uint64_t)ok.n[c] * ok.n[c];
+        valid = off <= llr_len && llr_len - off >= len;
+        if (valid && c == (uint32_t)ok.last) {
+            m = len < (uint64_t)kEaseSample ? (uint32_t)len : (uint32_t)kEaseSample;
+            for (uint32_t i = lane; i < m; i += kWave) s += fabsf((float)llr[off + i]);
+        }
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d);
+    if (lane == 0) ease[f] = !valid ? -1.f : m ? s / (float)m : 0.f;
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_batched_order(const uint8_t *frame_code, const float *ease,
+                                                                 uint32_t nframes, OrderKeys ok, uint32_t *order) {
+    constexpr int kWaves = kOrderThreads / kWave;
+    constexpr int kBatch = 8;   // frames whose loads a thread has in flight together
+    __shared__ uint32_t cnt[kOrderBins][kOrderThreads];   // frames per bin and thread, then positions
+    __shared__ uint32_t wsum[kOrderBins][kWaves];
+    __shared__ uint32_t base[kOrderBins];
+    __shared__ float wlo[kWaves], whi[kWaves];
+    __shared__ float lo_s, step_s;
+    __shared__ uint32_t rank_s[kMaxCodes];
     const uint32_t t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
-    const uint32_t per = (nframes + kOrderThreads - 1) / kOrderThreads;
-    const uint32_t lo = t * per < nframes ? t * per : nframes;
-    const uint32_t hi = lo + per < nframes ? lo + per : nframes;
-    auto bucket = [&](uint32_t f) -> uint32_t {
-        const uint32_t c = frame_code[f];
-        return c < (uint32_t)rk.ncodes ? rk.rank[c] : (uint32_t)rk.ncodes;
+    const int nc = ok.ncodes, levels = ok.levels, nbins = nc + levels;
+    const uint32_t last = (uint32_t)ok.last;
+    // each thread takes frames t, t + kOrderThreads, ... in every pass below, and issues
+    // the loads of kBatch of them before it uses them
+    auto load = [&](uint32_t f0, uint32_t (&c)[kBatch], float (&e)[kBatch]) {
+#pragma unroll
+        for (int u = 0; u < kBatch; u++) {
+            const uint32_t f = f0 + u * kOrderThreads + t;
+            c[u] = f < nframes ? frame_code[f] : 0xffu;
+            e[u] = f < nframes ? ease[f] : -1.f;
+        }
     };
-    for (int b = 0; b < kOrderBuckets; b++) cnt[b][t] = 0u;
-    for (uint32_t f = lo; f < hi; f++) cnt[bucket(f)][t]++;
-    // exclusive prefix of each bucket's counts over the threads: within each wave by
-    // shuffles, then over the waves' totals
-    for (int b = 0; b < kOrderBuckets; b++) {
+    // the range of ease over the last code's frames
+    float lo = INFINITY, hi = -INFINITY;
+    for (uint32_t f0 = 0; f0 < nframes; f0 += kBatch * kOrderThreads) {
+        uint32_t c[kBatch];
+        float e[kBatch];
+        load(f0, c, e);
+#pragma unroll
+        for (int u = 0; u < kBatch; u++)
+            if (c[u] == last && e[u] >= 0.f) lo = fminf(lo, e[u]), hi = fmaxf(hi, e[u]);
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, d));
+        hi = fmaxf(hi, __shfl_xor(hi, d));
+    }
+    if (lane == 0) wlo[wave] = lo, whi[wave] = hi;
+    for (int b = 0; b < nbins; b++) cnt[b][t] = 0u;
+    if (t < (uint32_t)nc) rank_s[t] = ok.rank[t];
+    __syncthreads();
+    if (t == 0) {
+        float l = INFINITY, h = -INFINITY;
+        for (int w = 0; w < kWaves; w++) l = fminf(l, wlo[w]), h = fmaxf(h, whi[w]);
+        lo_s = l;
+        step_s = h > l ? (float)levels / (h - l) : 0.f;
+    }
+    __syncthreads();
+    auto bin = [&](uint32_t c, float e) -> uint32_t {
+        if (c >= (uint32_t)nc || !(e >= 0.f)) return (uint32_t)(nbins - 1);
+        if (c != last) return rank_s[c];
+        const float r = (e - lo_s) * step_s;
+        const int lv = r < (float)levels ? (int)fmaxf(r, 0.f) : levels - 1;   // NaN lands on the last level
+        return (uint32_t)(nc - 1 + lv);
+    };
+    for (uint32_t f0 = 0; f0 < nframes; f0 += kBatch * kOrderThreads) {
+        uint32_t c[kBatch];
+        float e[kBatch];
+        load(f0, c, e);
+#pragma unroll
+        for (int u = 0; u < kBatch; u++)
+            if (f0 + u * kOrderThreads + t < nframes) cnt[bin(c[u], e[u])][t]++;
+    }
+    // exclusive prefix of each bin's counts over the threads: within each wave by
+    // shuffles, then over the waves' totals, then over the bins
+    for (int b = 0; b < nbins; b++) {
         const uint32_t v = cnt[b][t];
         uint32_t incl = v;
         for (int d = 1; d < kWave; d <<= 1) {
@@ -520,33 +606,35 @@ __global__ __launch_bounds__(kOrderThreads) void k_batched_order(const uint8_t *
         if (lane == kWave - 1) wsum[b][wave] = incl;
     }
     __syncthreads();
-    if (t < (uint32_t)kOrderBuckets) {
+    if (t < (uint32_t)nbins) {
         uint32_t acc = 0;
-        for (int w = 0; w < kOrderThreads / kWave; w++) {
+        for (int w = 0; w < kWaves; w++) {
             const uint32_t x = wsum[t][w];
             wsum[t][w] = acc;
             acc += x;
         }
-        base[t] = acc;   // the bucket's total, made a base below
+        base[t] = acc;   // the bin's total, made a base below
     }
     __syncthreads();
     if (t == 0) {
         uint32_t acc = 0;
-        for (int b = 0; b < kOrderBuckets; b++) {
+        for (int b = 0; b < nbins; b++) {
             const uint32_t x = base[b];
             base[b] = acc;
             acc += x;
         }
     }
     __syncthreads();
-    uint32_t pos[kOrderBuckets];
-    for (int b = 0; b < kOrderBuckets; b++) pos[b] = base[b] + wsum[b][wave] + cnt[b][t];
-    for (uint32_t f = lo; f < hi; f++) {
-        const uint32_t b = bucket(f);
-        uint32_t p = 0;
-        for (int j = 0; j < kOrderBuckets; j++)
-            if ((uint32_t)j == b) p = pos[j]++;
-        order[p] = f;
+    for (int b = 0; b < nbins; b++) cnt[b][t] += base[b] + wsum[b][wave];
+    for (uint32_t f0 = 0; f0 < nframes; f0 += kBatch * kOrderThreads) {
+        uint32_t c[kBatch];
+        float e[kBatch];
+        load(f0, c, e);
+#pragma unroll
+        for (int u = 0; u < kBatch; u++) {
+            const uint32_t f = f0 + u * kOrderThreads + t;
+            if (f < nframes) order[cnt[bin(c[u], e[u])][t]++] = f;
+        }
     }
 }
 
@@ -656,10 +744,8 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     const size_t esz = f64 ? sizeof(double) : sizeof(float);
     const size_t la_bytes = (size_t)grid * sc.frames_per_group * nmax * nmax * esz;
     char *ws = nullptr;
-    // frames of codes of different lengths are taken longest first
-    bool mixed = false;
-    for (int i = 1; i < ncodes; i++) mixed |= codes[i]->n != codes[0]->n;
-    const size_t order_bytes = mixed ? (nframes * sizeof(uint32_t) + 255) & ~(size_t)255 : 0;
+    // the frame order and each frame's ease, ahead of the code table
+    const size_t order_bytes = (nframes * (sizeof(uint32_t) + sizeof(float)) + 511) & ~(size_t)255;
     const size_t head = 256 + ((sizeof(DevCode) * kMaxCodes + 255) & ~(size_t)255) + order_bytes;
     const size_t total = head + la_bytes;
     if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
@@ -694,16 +780,27 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     a.order = nullptr;
     hipLaunchKernelGGL(k_batched_init, dim3(1), dim3(64), 0, st, a.next_frame, table,
                        reinterpret_cast<DevCode *>(ws + 256), ncodes);
-    if (mixed) {
-        CodeRanks rk{};
-        rk.ncodes = ncodes;
+    {
+        OrderKeys ok{};
+        ok.ncodes = ncodes;
+        ok.levels = kOrderBins - ncodes < 32 ? kOrderBins - ncodes : 32;
         int idx[kMaxCodes];
-        for (int i = 0; i < ncodes; i++) idx[i] = i;
+        for (int i = 0; i < ncodes; i++) idx[i] = i, ok.n[i] = codes[i]->n;
         std::stable_sort(idx, idx + ncodes, [&](int x, int y) { return codes[x]->n > codes[y]->n; });
-        for (int r = 0; r < ncodes; r++) rk.rank[idx[r]] = (uint8_t)r;
-        uint32_t *order = reinterpret_cast<uint32_t *>(ws + head - order_bytes);
-        hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(kOrderThreads), 0, st, frame_code, (uint32_t)nframes, rk,
-                           order);
+        for (int r = 0; r < ncodes; r++) ok.rank[idx[r]] = (uint8_t)r;
+        ok.last = idx[ncodes - 1];
+        char *ob = ws + head - order_bytes;
+        uint32_t *order = reinterpret_cast<uint32_t *>(ob);
+        float *ease = reinterpret_cast<float *>(ob + ((nframes * sizeof(uint32_t) + 255) & ~(size_t)255));
+        const dim3 eg((unsigned)((nframes + 3) / 4));
+        if (f64)
+            hipLaunchKernelGGL(k_frame_ease<double>, eg, dim3(256), 0, st, frame_code, frame_offset,
+                               (uint32_t)nframes, llr_len, static_cast<const double *>(llr_ch), ok, ease);
+        else
+            hipLaunchKernelGGL(k_frame_ease<float>, eg, dim3(256), 0, st, frame_code, frame_offset,
+                               (uint32_t)nframes, llr_len, static_cast<const float *>(llr_ch), ok, ease);
+        hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(kOrderThreads), 0, st, frame_code, ease,
+                           (uint32_t)nframes, ok, order);
         a.order = order;
     }
     const int tok = prof_start(PK_BATCHED, st);

@@ -192,3 +192,34 @@ def test_tuned_shape_gives_identical_results(sg):
         assert int(out["status"][0]) == 0
         for key in ("success", "half_iters", "sum_queries", "sum_max_queries", "hard"):
             np.testing.assert_array_equal(out[key], ref[key], err_msg=key)
+
+
+@pytest.mark.parametrize("last_present", [True, False])
+def test_batched_frame_order_cases(sg, last_present):
+    """Frames are taken in an order of the library's choosing (longest code first, the shortest
+    code's frames by their mean |L|): with more frames than one pass of the order kernel covers,
+    two codes of equal length (the later one is taken last), and invalid descriptors among them,
+    every valid frame still gets the plain path's result.  Without last_present, the code taken
+    last has no frames in the batch."""
+    nks = [(64, 57), (32, 26), (32, 26)]
+    codes, cidx, eb, offs, llr, cw = mixed(3000, seed=31, nks=nks)
+    cidx = cidx.copy()
+    offs = offs.copy()
+    if not last_present:
+        cidx[cidx == 2] = 1          # same length, so the blocks stay where they are
+    bad = np.array([3, 1500, 2999])
+    cidx[bad[0]] = 9                 # no such code
+    offs[bad[1]] = llr.shape[0] - 5  # block runs past the buffer
+    cidx[bad[2]] = 200
+    print(f"[gpu] batched order cases, last code present={last_present}", flush=True)
+    b = run_batched(sg, codes, cidx, offs, llr, f32=True, qcap=1000, iters=2)
+    assert int(b["status"][0]) & 2
+    good = np.ones(cidx.shape[0], bool)
+    good[bad] = False
+    assert np.all(b["success"][bad] == 0) and np.all(b["half_iters"][bad] == 0)
+    p = run_plain_per_code(sg, codes, np.where(good, cidx, 255), offs, llr, f32=True, qcap=1000, iters=2)
+    for key in ("success", "half_iters", "sum_queries", "sum_max_queries"):
+        np.testing.assert_array_equal(b[key][good], p[key][good], err_msg=key)
+    for f in np.nonzero(good)[0]:
+        nn = codes[cidx[f]].n ** 2
+        np.testing.assert_array_equal(b["hard"][offs[f]:offs[f] + nn], p["hard"][offs[f]:offs[f] + nn])
