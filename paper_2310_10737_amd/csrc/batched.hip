@@ -495,15 +495,15 @@ __global__ void k_batched_init(uint32_t *counters, CodeTable table, DevCode *dst
 // into `levels` equal steps.  Descriptors that name no code or a block outside llr_ch,
 // and frames whose sample holds a NaN, go last.
 constexpr int kEaseSample = 1024;
-constexpr int kOrderThreads = 256;
-constexpr int kOrderBins = 48;   // one per code, plus the last code's extra levels and the invalid frames
+constexpr int kOrderThreads = 512;
+constexpr int kOrderBins = 24;   // one per code, plus the last code's extra levels and the invalid frames
 
 struct OrderKeys {
     uint8_t rank[kMaxCodes];   // rank of each code index by length, longest first
     int n[kMaxCodes];          // length of each code index
     int ncodes;
     int last;                  // index of the code of rank ncodes - 1, whose frames are ordered by ease
-    int levels;                // ease levels: ncodes + levels <= kOrderBins
+    int levels;                // ease levels of the last code: ncodes + levels <= kOrderBins
 };
 
 template <typename T>
@@ -523,7 +523,15 @@ __global__ __launch_bounds__(256) void k_frame_ease(const uint8_t *frame_code, c
         valid = off <= llr_len && llr_len - off >= len;
         if (valid && c == (uint32_t)ok.last) {
             m = len < (uint64_t)kEaseSample ? (uint32_t)len : (uint32_t)kEaseSample;
-            for (uint32_t i = lane; i < m; i += kWave) s += fabsf((float)llr[off + i]);
+            for (uint32_t i0 = 0; i0 < m; i0 += 4 * kWave) {   // four loads in flight
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t i = i0 + u * kWave + lane;
+                    v[u] = i < m ? fabsf((float)llr[off + i]) : 0.f;
+                }
+                s += (v[0] + v[1]) + (v[2] + v[3]);
+            }
         }
     }
     for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d);
@@ -533,12 +541,11 @@ __global__ __launch_bounds__(256) void k_frame_ease(const uint8_t *frame_code, c
 __global__ __launch_bounds__(kOrderThreads) void k_batched_order(const uint8_t *frame_code, const float *ease,
                                                                  uint32_t nframes, OrderKeys ok, uint32_t *order) {
     constexpr int kWaves = kOrderThreads / kWave;
-    constexpr int kBatch = 8;   // frames whose loads a thread has in flight together
+    constexpr int kBatch = 16;   // frames whose loads a thread has in flight together
     __shared__ uint32_t cnt[kOrderBins][kOrderThreads];   // frames per bin and thread, then positions
     __shared__ uint32_t wsum[kOrderBins][kWaves];
     __shared__ uint32_t base[kOrderBins];
     __shared__ float wlo[kWaves], whi[kWaves];
-    __shared__ float lo_s, step_s;
     __shared__ uint32_t rank_s[kMaxCodes];
     const uint32_t t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
     const int nc = ok.ncodes, levels = ok.levels, nbins = nc + levels;
@@ -571,17 +578,12 @@ __global__ __launch_bounds__(kOrderThreads) void k_batched_order(const uint8_t *
     for (int b = 0; b < nbins; b++) cnt[b][t] = 0u;
     if (t < (uint32_t)nc) rank_s[t] = ok.rank[t];
     __syncthreads();
-    if (t == 0) {
-        float l = INFINITY, h = -INFINITY;
-        for (int w = 0; w < kWaves; w++) l = fminf(l, wlo[w]), h = fmaxf(h, whi[w]);
-        lo_s = l;
-        step_s = h > l ? (float)levels / (h - l) : 0.f;
-    }
-    __syncthreads();
+    for (int w = 0; w < kWaves; w++) lo = fminf(lo, wlo[w]), hi = fmaxf(hi, whi[w]);
+    const float step = hi > lo ? (float)levels / (hi - lo) : 0.f;
     auto bin = [&](uint32_t c, float e) -> uint32_t {
         if (c >= (uint32_t)nc || !(e >= 0.f)) return (uint32_t)(nbins - 1);
         if (c != last) return rank_s[c];
-        const float r = (e - lo_s) * step_s;
+        const float r = (e - lo) * step;
         const int lv = r < (float)levels ? (int)fmaxf(r, 0.f) : levels - 1;   // NaN lands on the last level
         return (uint32_t)(nc - 1 + lv);
     };
@@ -783,7 +785,7 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     {
         OrderKeys ok{};
         ok.ncodes = ncodes;
-        ok.levels = kOrderBins - ncodes < 32 ? kOrderBins - ncodes : 32;
+        ok.levels = kOrderBins - ncodes;
         int idx[kMaxCodes];
         for (int i = 0; i < ncodes; i++) idx[i] = i, ok.n[i] = codes[i]->n;
         std::stable_sort(idx, idx + ncodes, [&](int x, int y) { return codes[x]->n > codes[y]->n; });
