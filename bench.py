@@ -35,6 +35,7 @@ timed form is given in the config.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -750,6 +751,11 @@ def bench_serve(args, sg, np, torch, synth):
         if not batch and not wth.is_alive() and "r" not in warm:
             raise SystemExit("the warm-up replay failed")
     wth.join()
+    # the poll loop below keeps up to R results alive; a full collection over them (and over
+    # whatever earlier workloads left) can hold the loop long enough to back up the server's
+    # completions, so the collector is paused for the timed replay
+    gc.collect()
+    gc.disable()
     st0 = srv.stats()
     results = []
     t0 = sg.sogrand_clock_ns() + 20_000_000
@@ -772,6 +778,7 @@ def bench_serve(args, sg, np, torch, synth):
             print(f"[serve] {len(results)}/{R} results", file=sys.stderr, flush=True)
             last_print = time.time()
     th.join()
+    gc.enable()
     st1 = srv.stats()
     srv.close()
     tags = np.array([r["user_tag"] for r in results])
