@@ -545,9 +545,12 @@ def bench_mixed(args, sg, np, torch, synth):
 def bench_headline(args, sg, np, torch, synth):
     """The metric's own line: the mixed stream (value), the served form (latency) and the
     [64,57]^2 forms, each under its own config."""
-    line = bench_mixed(args, sg, np, torch, synth)
-    torch.cuda.empty_cache()
+    # the served form first, as a serving process would start: its four lanes' streams then get
+    # hardware queues of their own (HIP gives a process four; once other streams hold one, two
+    # lanes share a queue and their steps serialise: 0.20 ms mean steps against 0.15)
     srv = bench_serve(args, sg, np, torch, synth)
+    torch.cuda.empty_cache()
+    line = bench_mixed(args, sg, np, torch, synth)
     torch.cuda.empty_cache()
     line["served"] = {k: srv[k] for k in ("value", "unit", "config", "p50_frame_latency_ms", "p99_frame_latency_ms",
                                           "offered_info_bits_per_s", "p99_frame_latency_ms_middle_80pct_arrivals",

@@ -333,7 +333,14 @@ void sogrand_sched_table_clear(void);
    A slot holds the frame's channel LLRs, a-priori LLRs, hard decision and
    line syndromes; its size is set by the code length rounded up to 32, 64 or
    128.  A host copy of equal size (pinned memory) carries the LLRs in and the
-   hard decisions out.  The server decodes on the device current at creation. */
+   hard decisions out.  The server decodes on the device current at creation.
+
+   The lanes' steps run concurrently only if their streams sit on different
+   hardware queues.  HIP gives a process four by default (GPU_MAX_HW_QUEUES), and
+   streams created once others hold queues share them: create the server before
+   the process's other streams (including the default stream's first use), or
+   raise GPU_MAX_HW_QUEUES.  On an MI355X a server created after other GPU work
+   with four queues ran its steps at 0.20 ms on average instead of 0.15. */
 typedef struct sogrand_server sogrand_server_t;
 
 typedef struct {
