@@ -266,7 +266,10 @@ void sogrand_sched_default(sogrand_sched_t *s);
    shortest code, those with the smallest mean |L_Ch| over their first 1024
    elements first (a sort on the device), so that the end of the launch is left
    to short, easy frames; the order changes no result.  sched NULL = the shape recorded for this kind of batch by
-   sogrand_sched_tune or sogrand_sched_table_load, else the default.  Errors:
+   sogrand_sched_tune or sogrand_sched_table_load, else the default adjusted to the
+   batch's size: up to one frame per compute unit, 16-wave workgroups of one frame
+   taking 2 lines per steal; up to eight frames per compute unit, one frame per
+   workgroup.  Errors:
    EINVAL, ENOMEM, EDEVICE. */
 int sogrand_decode_batched(const sogrand_code_t *const *codes, int ncodes, const sogrand_params_t *params,
                            size_t nframes, const uint8_t *frame_code, const uint64_t *frame_offset,

@@ -710,12 +710,16 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
         if (!codes[i]) return fail(SOGRAND_EINVAL, "codes[%d] is NULL", i);
     sogrand_sched_t sc;
     sogrand_sched_default(&sc);
+    bool chosen = sched != nullptr;
     if (sched) {
         sc = *sched;
     } else {
         std::lock_guard<std::mutex> g(g_tuned_mu);
         const auto it = g_tuned.find(batch_kind(topo, codes, ncodes, params));
-        if (it != g_tuned.end()) sc = it->second;
+        if (it != g_tuned.end()) {
+            sc = it->second;
+            chosen = true;
+        }
     }
     SG_TRY(check_sched(&sc));
     BatchArgs a{};
@@ -728,6 +732,17 @@ static int decode_batched(int topo, const sogrand_code_t *const *codes, int ncod
     int dev = 0, cus = 0;
     SG_HIP(hipGetDevice(&dev));
     SG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (!chosen) {
+        if (nframes <= (size_t)cus) {
+            // a small batch: one frame per workgroup, of 16 waves, so that it spreads over as
+            // many compute units as it has frames
+            sc.waves_per_group = 16;
+            sc.frames_per_group = 1;
+            sc.steal_chunk = 2;
+        } else if (nframes <= 8 * (size_t)cus) {
+            sc.frames_per_group = 1;
+        }
+    }
     const bool f64 = params->precision == SOGRAND_F64;
     const BatchedKernel kern = f64 ? batched_kernel<double>(nmax, params->list_bler_stop > 0.0, sc.waves_per_group, topo)
                                    : batched_kernel<float>(nmax, params->list_bler_stop > 0.0, sc.waves_per_group, topo);
