@@ -728,28 +728,37 @@ int sogrand_serve_poll(sogrand_server_t *s, sogrand_result_t *results, size_t ma
     if (!s || !results || !n_results || max_results == 0)
         return fail(SOGRAND_EINVAL, "server, results, n_results and max_results > 0 are required");
     *n_results = 0;
-    std::unique_lock<std::mutex> lk(s->mu);
-    if (s->done.empty()) {
-        if (s->in_flight == 0) return SOGRAND_ENOTFOUND;
-        if (timeout_ns == 0) return SOGRAND_ETIMEDOUT;
-        auto ready = [&] { return !s->done.empty() || s->in_flight == 0; };
-        if (timeout_ns < 0) s->cv_done.wait(lk, ready);
-        else s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready);
-        if (s->done.empty()) return s->in_flight == 0 ? SOGRAND_ENOTFOUND : SOGRAND_ETIMEDOUT;
+    // the finished frames are taken under the lock and copied out after it, so that the
+    // lanes, which take the lock between steps, never wait on the caller's copies
+    std::vector<sogrand_server::Done> got;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->done.empty()) {
+            if (s->in_flight == 0) return SOGRAND_ENOTFOUND;
+            if (timeout_ns == 0) return SOGRAND_ETIMEDOUT;
+            auto ready = [&] { return !s->done.empty() || s->in_flight == 0; };
+            if (timeout_ns < 0) s->cv_done.wait(lk, ready);
+            else s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready);
+            if (s->done.empty()) return s->in_flight == 0 ? SOGRAND_ENOTFOUND : SOGRAND_ETIMEDOUT;
+        }
+        const size_t k = s->done.size() < max_results ? s->done.size() : max_results;
+        got.reserve(k);
+        for (size_t i = 0; i < k; i++) {
+            got.push_back(std::move(s->done.front()));
+            s->done.pop_front();
+        }
     }
-    size_t k = 0, off = 0;
-    while (k < max_results && !s->done.empty()) {
-        sogrand_server::Done &d = s->done.front();
+    size_t off = 0;
+    for (size_t k = 0; k < got.size(); k++) {
+        const sogrand_server::Done &d = got[k];
         results[k] = d.r;
         results[k].hard_offset = off;
         if (hard_out_host && !d.hard.empty()) std::memcpy(hard_out_host + off, d.hard.data(), d.hard.size());
         if (llr_app_out_host && !d.app.empty())
             std::memcpy(static_cast<char *>(llr_app_out_host) + off * s->esz, d.app.data(), d.app.size());
         off += (size_t)d.r.n * d.r.n;
-        s->done.pop_front();
-        k++;
     }
-    *n_results = k;
+    *n_results = got.size();
     return SOGRAND_OK;
 }
 
