@@ -170,6 +170,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 // memory, and for a finished frame its hard decision (from the last pass's line
 // masks: bit c of row j or bit j of column c is element [j][c]) and, when exported,
 // its L_APP into the host copy.
+// OR of v over the wave, in every lane.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+    v |= xor_lane<1>(v);
+    v |= xor_lane<2>(v);
+    v |= xor_lane<4>(v);
+    v |= xor_lane<8>(v);
+    v |= xor_lane<16>(v);
+    v |= xor_lane<32>(v);
+    return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -181,31 +192,39 @@ __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
     const char *slot = a.arena + d.slot;
     const uint64_t *mk = reinterpret_cast<const uint64_t *>(slot + sl.masks);
     const uint32_t *hcol = load_uniform(&a.codes[d.code].hcol);
-    // the line masks and H columns are staged in LDS with coalesced loads, so that the
-    // syndrome loops below read them without a dependent memory access per bit
+    // The frame is a product codeword iff every line of the last pass and every line across
+    // it has syndrome zero.  Bit-sliced over the parity bits p: with Hp the set of positions
+    // whose H column has bit p, line x's syndrome bit p is the parity of (line x AND Hp), and
+    // bit p of the cross lines' syndromes, as a vector over them, is the XOR of the lines l
+    // in Hp.  Lane t holds lines t and t + 64 and the H columns of positions t and t + 64.
     __shared__ uint64_t mk_s[kWavesPerBlock][2 * SOGRAND_NMAX];
-    __shared__ uint32_t hc_s[kWavesPerBlock][SOGRAND_NMAX];
     const int wave = threadIdx.x / kWave;
-    for (int t = lane; t < 2 * n; t += kWave) mk_s[wave][t] = mk[t];
-    for (int t = lane; t < n; t += kWave) hc_s[wave][t] = gptr(hcol)[t];
-    wave_sync();
-    bool bad = false;
-    for (int b = 0; b < 2; b++) {
-        const int x = lane + kWave * b;
-        if (x >= n) continue;
-        const uint64_t m0 = mk_s[wave][x * 2], m1 = mk_s[wave][x * 2 + 1];
-        uint32_t s = 0;
-        for (int j = 0; j < n; j++) {
-            const uint64_t bit = j < 64 ? (m0 >> j) & 1ull : (m1 >> (j - 64)) & 1ull;
-            if (bit) s ^= hc_s[wave][j];
-        }
-        uint32_t t = 0;
-        for (int l = 0; l < n; l++) {
-            const uint64_t w = mk_s[wave][l * 2 + (x >> 6)];
-            if ((w >> (x & 63)) & 1ull) t ^= hc_s[wave][l];
-        }
-        bad |= (s != 0u) || (t != 0u);
+    const bool v0 = lane < n, v1 = lane + kWave < n;
+    const uint64_t a0 = v0 ? mk[lane * 2] : 0ull, a1 = v0 ? mk[lane * 2 + 1] : 0ull;
+    const uint64_t b0 = v1 ? mk[(lane + kWave) * 2] : 0ull, b1 = v1 ? mk[(lane + kWave) * 2 + 1] : 0ull;
+    const uint32_t h0 = v0 ? gptr(hcol)[lane] : 0u, h1 = v1 ? gptr(hcol)[lane + kWave] : 0u;
+    if (v0) {
+        mk_s[wave][lane * 2] = a0;
+        mk_s[wave][lane * 2 + 1] = a1;
     }
+    if (v1) {
+        mk_s[wave][(lane + kWave) * 2] = b0;
+        mk_s[wave][(lane + kWave) * 2 + 1] = b1;
+    }
+    const uint32_t used = __builtin_amdgcn_readfirstlane(wave_or(h0 | h1));   // the parity bits present
+    bool bad = false;
+    for (int p = 0; p < 32; p++) {
+        if (!((used >> p) & 1u)) continue;
+        const bool i0 = (h0 >> p) & 1u, i1 = (h1 >> p) & 1u;
+        const uint64_t P0 = __ballot(i0), P1 = __ballot(i1);
+        bad |= ((__popcll(a0 & P0) + __popcll(a1 & P1)) & 1) != 0;
+        bad |= ((__popcll(b0 & P0) + __popcll(b1 & P1)) & 1) != 0;
+        const uint64_t c0 = (i0 ? a0 : 0ull) ^ (i1 ? b0 : 0ull), c1 = (i0 ? a1 : 0ull) ^ (i1 ? b1 : 0ull);
+        const uint32_t x = wave_xor((uint32_t)c0) | wave_xor((uint32_t)(c0 >> 32)) | wave_xor((uint32_t)c1) |
+                           wave_xor((uint32_t)(c1 >> 32));
+        bad |= x != 0u;
+    }
+    wave_sync();
     const bool valid = __ballot(bad) == 0ull;
     const bool finished = (valid && a.early_stop) || d.h == (uint32_t)(2 * a.max_iter);
     if (finished) {
@@ -224,9 +243,10 @@ __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
             const uint64_t *rm = mk_s[wave];
             if (!rows) {
                 for (int j = 0; j < n; j++) {
-                    const int h = j >> 6, sh = j & 63;
-                    const uint64_t lo = __ballot(lane < n && ((mk_s[wave][lane * 2 + h] >> sh) & 1ull));
-                    const uint64_t hi = __ballot(lane + kWave < n && ((mk_s[wave][(lane + kWave) * 2 + h] >> sh) & 1ull));
+                    const int sh = j & 63;
+                    const uint64_t ca = j < 64 ? a0 : a1, cb = j < 64 ? b0 : b1;   // columns lane, lane + 64
+                    const uint64_t lo = __ballot((ca >> sh) & 1ull);
+                    const uint64_t hi = __ballot((cb >> sh) & 1ull);
                     if (lane == 0) {
                         rm_s[wave][j * 2] = lo;
                         rm_s[wave][j * 2 + 1] = hi;
