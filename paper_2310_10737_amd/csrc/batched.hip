@@ -146,6 +146,37 @@ __device__ void slot_refill(const BatchArgs &a, SlotLds &sl) {
 template <int TOPO>
 __device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, WaveLds &S, int lane, int h) {
     const int n = sl.n;
+    if constexpr (TOPO == kProduct) {
+        // Bit-sliced over the parity bits p: with Hp the positions whose H column has bit p,
+        // line x's syndrome bit p is the parity of (line x AND Hp), and bit p of the cross
+        // lines' syndromes, as a vector over them, is the XOR of the lines in Hp.  Lane t
+        // holds lines t and t + 64 and the H columns of positions t and t + 64.
+        const bool v0 = lane < n, v1 = lane + kWave < n;
+        const uint64_t a0 = v0 ? sl.masks[lane][0] : 0ull, a1 = v0 ? sl.masks[lane][1] : 0ull;
+        const uint64_t b0 = v1 ? sl.masks[lane + kWave][0] : 0ull, b1 = v1 ? sl.masks[lane + kWave][1] : 0ull;
+        const uint32_t h0 = v0 ? gptr(c.hcol)[lane] : 0u, h1 = v1 ? gptr(c.hcol)[lane + kWave] : 0u;
+        uint32_t used = h0 | h1;
+        used |= xor_lane<1>(used);
+        used |= xor_lane<2>(used);
+        used |= xor_lane<4>(used);
+        used |= xor_lane<8>(used);
+        used |= xor_lane<16>(used);
+        used |= xor_lane<32>(used);
+        used = __builtin_amdgcn_readfirstlane(used);   // the parity bits present
+        bool bad = false;
+#pragma unroll 1
+        for (int p = 0; p < 32; p++) {
+            if (!((used >> p) & 1u)) continue;
+            const bool i0 = (h0 >> p) & 1u, i1 = (h1 >> p) & 1u;
+            const uint64_t P0 = __ballot(i0), P1 = __ballot(i1);
+            bad |= ((__popcll(a0 & P0) + __popcll(a1 & P1)) & 1) != 0;
+            bad |= ((__popcll(b0 & P0) + __popcll(b1 & P1)) & 1) != 0;
+            const uint64_t c0 = (i0 ? a0 : 0ull) ^ (i1 ? b0 : 0ull), c1 = (i0 ? a1 : 0ull) ^ (i1 ? b1 : 0ull);
+            bad |= (wave_xor((uint32_t)c0) | wave_xor((uint32_t)(c0 >> 32)) | wave_xor((uint32_t)c1) |
+                    wave_xor((uint32_t)(c1 >> 32))) != 0u;
+        }
+        return __ballot(bad) == 0ull;
+    }
     uint32_t *hc = S.zmask;
     for (int t = lane; t < n; t += kWave) hc[t] = gptr(c.hcol)[t];
     wave_sync();
