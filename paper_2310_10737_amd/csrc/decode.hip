@@ -303,7 +303,35 @@ __global__ __launch_bounds__(kBlock) void k_product_check(ProductArgs a, int h, 
     const uint64_t *mk = mk_s[wave];
     const uint32_t *hcol = hc_s[wave];
     bool bad = false;
-    for (int b = 0; b < 2; b++) {
+    if (a.topo == kProduct) {
+        // Bit-sliced over the parity bits p: with Hp the positions whose H column has bit p,
+        // line x's syndrome bit p is the parity of (line x AND Hp), and bit p of the cross
+        // lines' syndromes, as a vector over them, is the XOR of the lines in Hp.  Lane t
+        // holds lines t and t + 64 and the H columns of positions t and t + 64.
+        const bool v0 = lane < n, v1 = lane + kWave < n;
+        const uint64_t a0 = v0 ? mk[lane * 2] : 0ull, a1 = v0 ? mk[lane * 2 + 1] : 0ull;
+        const uint64_t b0 = v1 ? mk[(lane + kWave) * 2] : 0ull, b1 = v1 ? mk[(lane + kWave) * 2 + 1] : 0ull;
+        const uint32_t h0 = v0 ? hcol[lane] : 0u, h1 = v1 ? hcol[lane + kWave] : 0u;
+        uint32_t used = h0 | h1;
+        used |= xor_lane<1>(used);
+        used |= xor_lane<2>(used);
+        used |= xor_lane<4>(used);
+        used |= xor_lane<8>(used);
+        used |= xor_lane<16>(used);
+        used |= xor_lane<32>(used);
+        used = __builtin_amdgcn_readfirstlane(used);   // the parity bits present
+        for (int p = 0; p < 32; p++) {
+            if (!((used >> p) & 1u)) continue;
+            const bool i0 = (h0 >> p) & 1u, i1 = (h1 >> p) & 1u;
+            const uint64_t P0 = __ballot(i0), P1 = __ballot(i1);
+            bad |= ((__popcll(a0 & P0) + __popcll(a1 & P1)) & 1) != 0;
+            bad |= ((__popcll(b0 & P0) + __popcll(b1 & P1)) & 1) != 0;
+            const uint64_t c0 = (i0 ? a0 : 0ull) ^ (i1 ? b0 : 0ull), c1 = (i0 ? a1 : 0ull) ^ (i1 ? b1 : 0ull);
+            bad |= (wave_xor((uint32_t)c0) | wave_xor((uint32_t)(c0 >> 32)) | wave_xor((uint32_t)c1) |
+                    wave_xor((uint32_t)(c1 >> 32))) != 0u;
+        }
+    }
+    for (int b = 0; b < 2 && a.topo != kProduct; b++) {
         const int x = lane + kWave * b;
         if (x >= n) continue;
         // x as a line of the last pass: XOR of the columns of its set bits
