@@ -91,18 +91,20 @@ struct ServeArgs {
     int early_stop;
     int app;                  // keep each frame's L_APP and export it with the result
     ProfCounters *prof;
+    // the pass launch covers the three word widths (32, 64, 128 bits): per width, its
+    // frames' descriptors, counts and query sums, and its first workgroup
+    const ServeDesc *wdesc[3];
+    uint32_t wnact[3];
+    uint32_t wlines[3];
+    unsigned long long *wqsum[3];
+    uint32_t wblock0[3];
 };
 
-// One wave per line of one word width.  Every frame of the launch runs the
-// half-iteration its descriptor names (rows for odd h).
+// One wave per line: line gl of the launch's frames of one word width (a.desc, a.nact,
+// a.nlines).  Every frame runs the half-iteration its descriptor names (rows for odd h).
 template <typename T, int NS, bool STOP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_serve_pass(ServeArgs a) {
+__device__ __forceinline__ void serve_line(const ServeArgs &a, uint32_t gl, WaveLds &S, int lane) {
     constexpr int NB = Lanes<NS>::NB;
-    __shared__ WaveLds lds[kWavesPerBlock];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    WaveLds &S = lds[wave];
-    const uint32_t gl = (uint32_t)blockIdx.x * kWavesPerBlock + (uint32_t)wave;
     if (gl >= a.nlines) return;
     // the frame owning global line gl: the last descriptor whose line0 <= gl
     uint32_t lo = 0, hi = a.nact - 1;
@@ -163,6 +165,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         mk[line * 2 + 1] = hm[1];
         atomicAdd(&a.qsum[lo], (unsigned long long)st.Q);
     }
+}
+
+// The pass of a step: one launch for all word widths, so that the lines of short codes run
+// beside the long words of 128-bit ones instead of after them.  The 128-bit frames take the
+// first workgroups, then the 64-bit ones, then the 32-bit ones.
+template <typename T, bool STOP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_serve_pass(ServeArgs a) {
+    __shared__ WaveLds lds[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const uint32_t b = blockIdx.x;
+    const int w = b >= a.wblock0[0] ? 0 : (b >= a.wblock0[1] ? 1 : 2);
+    ServeArgs g = a;
+    g.desc = a.wdesc[w];
+    g.nact = a.wnact[w];
+    g.nlines = a.wlines[w];
+    g.qsum = a.wqsum[w];
+    const uint32_t gl = (b - a.wblock0[w]) * kWavesPerBlock + (uint32_t)wave;
+    if (w == 2) serve_line<T, 128, STOP>(g, gl, lds[wave], lane);
+    else if (w == 1) serve_line<T, 64, STOP>(g, gl, lds[wave], lane);
+    else serve_line<T, 32, STOP>(g, gl, lds[wave], lane);
 }
 
 // One wave per frame of the step: validity of the hard decision (every line of
@@ -392,18 +415,10 @@ namespace sg {
 static int width_class(int n) { return n <= 32 ? 0 : (n <= 64 ? 1 : 2); }
 static int class_width(int c) { return c == 0 ? 32 : (c == 1 ? 64 : 128); }
 
-template <typename T, bool STOP>
-static void launch_serve_pass_s(const ServeArgs &a, int wclass, hipStream_t st) {
-    const dim3 g((a.nlines + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (wclass == 0) hipLaunchKernelGGL((k_serve_pass<T, 32, STOP>), g, dim3(kBlock), 0, st, a);
-    else if (wclass == 1) hipLaunchKernelGGL((k_serve_pass<T, 64, STOP>), g, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_serve_pass<T, 128, STOP>), g, dim3(kBlock), 0, st, a);
-}
-
 template <typename T>
-static void launch_serve_pass(const ServeArgs &a, int wclass, hipStream_t st) {
-    if (a.pstop > 0.0) launch_serve_pass_s<T, true>(a, wclass, st);
-    else launch_serve_pass_s<T, false>(a, wclass, st);
+static void launch_serve_pass(const ServeArgs &a, uint32_t blocks, hipStream_t st) {
+    if (a.pstop > 0.0) hipLaunchKernelGGL((k_serve_pass<T, true>), dim3(blocks), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_serve_pass<T, false>), dim3(blocks), dim3(kBlock), 0, st, a);
 }
 
 }  // namespace sg
@@ -457,16 +472,19 @@ int sogrand_server::step(Lane &ln, std::vector<Req> &active) {
     a.early_stop = params.early_stop ? 1 : 0;
     a.app = app ? 1 : 0;
     a.prof = prof_counters(PK_SERVE);
-    for (int c = 0; c < 3; c++) {
-        const uint32_t cnt = gstart[c + 1] - gstart[c];
-        if (!cnt) continue;
-        ServeArgs g = a;
-        g.desc = ln.desc_dev + gstart[c];
-        g.nact = cnt;
-        g.nlines = glines[c];
-        g.qsum = ln.qsum + gstart[c];
-        if (esz == 8) launch_serve_pass<double>(g, c, ln.stream);
-        else launch_serve_pass<float>(g, c, ln.stream);
+    // one pass launch: the 128-bit frames' workgroups first, then the 64-bit and 32-bit ones
+    uint32_t blocks = 0;
+    for (int c = 2; c >= 0; c--) {
+        a.wdesc[c] = ln.desc_dev + gstart[c];
+        a.wnact[c] = gstart[c + 1] - gstart[c];
+        a.wlines[c] = glines[c];
+        a.wqsum[c] = ln.qsum + gstart[c];
+        a.wblock0[c] = blocks;
+        blocks += (glines[c] + kWavesPerBlock - 1) / kWavesPerBlock;
+    }
+    if (blocks) {
+        if (esz == 8) launch_serve_pass<double>(a, blocks, ln.stream);
+        else launch_serve_pass<float>(a, blocks, ln.stream);
     }
     ServeArgs ck = a;
     ck.desc = ln.desc_dev;
