@@ -328,7 +328,7 @@ void sogrand_sched_table_clear(void);
    four lanes: host threads with their own HIP streams that each advance their
    frames by one half-iteration per step (section "Iterative decoding").  In a
    step the row or column pass of all the lane's frames, whatever their codes,
-   runs in one set of launches, followed by the validity check.  Frames that
+   runs in one launch, followed by the validity check launch.  Frames that
    finish leave, and requests submitted meanwhile join the next lane to start a
    step, so new work overlaps with frames already in flight.  Each frame is
    decoded exactly as sogrand_decode_product decodes it alone.
