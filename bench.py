@@ -118,8 +118,8 @@ def cpu_model() -> str:
 
 
 def host_threads() -> int:
-    """Threads for the oracle: every core this process may run on, at most 16 (a GPU machine
-    allots 16 host cores to one GPU, whatever the affinity mask shows)."""
+    """Threads for the oracle: every core this process may run on, at most 16 (the host share
+    of one GPU on the machines measured here, whatever the affinity mask shows)."""
     return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
