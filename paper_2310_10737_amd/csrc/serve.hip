@@ -188,11 +188,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     else serve_line<T, 32, STOP>(g, gl, lds[wave], lane);
 }
 
-// One wave per frame of the step: validity of the hard decision (every line of
-// the last pass and every cross line a codeword), the frame's outcome into host
-// memory, and for a finished frame its hard decision (from the last pass's line
-// masks: bit c of row j or bit j of column c is element [j][c]) and, when exported,
-// its L_APP into the host copy.
 // OR of v over the wave, in every lane.
 __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
     v |= xor_lane<1>(v);
@@ -204,6 +199,11 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
     return v;
 }
 
+// One wave per frame of the step: validity of the hard decision (every line of
+// the last pass and every cross line a codeword), the frame's outcome into host
+// memory, and for a finished frame its hard decision (from the last pass's line
+// masks: bit c of row j or bit j of column c is element [j][c]) and, when exported,
+// its L_APP into the host copy.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_serve_check(ServeArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
