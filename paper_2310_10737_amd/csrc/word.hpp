@@ -191,65 +191,136 @@ __device__ __forceinline__ void eo_combine(double &E, double &O) {
     O = nO;
 }
 
-// v from lane (lane ^ (K-1)), the mirror image inside aligned blocks of K lanes:
-// quad_perm [3,2,1,0], row_half_mirror and row_mirror, composed with the permlane
-// swaps for blocks of 32 and 64 lanes
+// Compare-exchanges of the ascending network.  Each pair's lower lane keeps the
+// minimum and its upper lane the maximum.
+//
+// Where the lower and upper lanes of every pair are told apart by lane bits 2-5
+// (pairs 4, 8, 16 or 32 lanes apart, mirror images in blocks of 8, 16 or 32), the two
+// halves are written by two DPP instructions under complementary row or bank masks
+// (a row is 16 lanes, a bank 4 lanes of every row), so no select is needed: a
+// compare-exchange costs two VALU instructions, plus one permlane swap past 16 lanes.
+// Pairs 1 or 2 lanes apart and mirror images in blocks of 2 or 4 lanes differ in lane
+// bits 0-1, which no mask reaches: those take both results and a select.
+// Each asm block starts and ends with s_nop 1, the two wait states a DPP read needs
+// after a VALU write of its operand.
+
 // full-mask DPP permutation (every lane reads a lane of its own row)
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_perm(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 
-template <int K>
-__device__ __forceinline__ uint32_t flip_lane(uint32_t v) {
-    if constexpr (K == 2) {
-        return dpp_perm<0xB1>(v);
-    } else if constexpr (K == 4) {
-        return dpp_perm<0x1B>(v);
-    } else if constexpr (K == 8) {
-        return dpp_perm<0x141>(v);
-    } else if constexpr (K == 16) {
-        return dpp_perm<0x140>(v);
-    } else if constexpr (K == 32) {
-        return dpp_perm<0x140>(xor_lane<16>(v));
-    } else {
-        static_assert(K == 64, "block size");
-        return dpp_perm<0x140>(xor_lane<16>(xor_lane<32>(v)));
-    }
-}
-
-// compare-exchange in an ascending network: the lower position keeps the minimum
+// the median of k, p and m: min(k, p) where m = 0, max(k, p) where m = ~0
 __device__ __forceinline__ uint32_t cas32(uint32_t k, uint32_t p, bool lower) {
+    const uint32_t m = lower ? 0u : ~0u;
     const uint32_t mn = p < k ? p : k, mx = p < k ? k : p;
-    return lower ? mn : mx;
+    const uint32_t c = mx < m ? mx : m;
+    return mn > c ? mn : c;
 }
 
-// Bitonic network with ascending comparators only: for each block size K the
-// first step compares mirror images inside the block, the next ones compare
-// positions J = K/4, ..., 1 apart.
+// t = min(src0 through DPP, src1) under the first masks, max under the second
+#define SG_MINMAX_DPP(LO, HI)                                                       \
+    "s_nop 1\n\tv_min_u32_dpp %0, %1, %2 " LO "\n\tv_max_u32_dpp %0, %3, %4 " HI "\n\ts_nop 1"
+
+// partner lane ^ J
+template <int J>
+__device__ __forceinline__ uint32_t ce_xor(uint32_t k, int lane) {
+    uint32_t t;
+    if constexpr (J == 1 || J == 2) {
+        t = cas32(k, xor_lane<J>(k), (lane & J) == 0);
+    } else if constexpr (J == 4) {
+        asm(SG_MINMAX_DPP("row_shl:4 row_mask:0xf bank_mask:0x5", "row_shr:4 row_mask:0xf bank_mask:0xa")
+            : "=&v"(t) : "v"(k), "v"(k), "v"(k), "v"(k));
+    } else if constexpr (J == 8) {
+        asm(SG_MINMAX_DPP("row_shl:8 row_mask:0xf bank_mask:0x3", "row_shr:8 row_mask:0xf bank_mask:0xc")
+            : "=&v"(t) : "v"(k), "v"(k), "v"(k), "v"(k));
+    } else if constexpr (J == 16) {
+        // after the swap each lane holds its own key and its partner's, one in each register
+        const auto r = __builtin_amdgcn_permlane16_swap(k, k, false, false);
+        asm(SG_MINMAX_DPP("quad_perm:[0,1,2,3] row_mask:0x5 bank_mask:0xf",
+                          "quad_perm:[0,1,2,3] row_mask:0xa bank_mask:0xf")
+            : "=&v"(t) : "v"(r[0]), "v"(r[1]), "v"(r[0]), "v"(r[1]));
+    } else {
+        static_assert(J == 32, "distance");
+        const auto r = __builtin_amdgcn_permlane32_swap(k, k, false, false);
+        asm(SG_MINMAX_DPP("quad_perm:[0,1,2,3] row_mask:0x3 bank_mask:0xf",
+                          "quad_perm:[0,1,2,3] row_mask:0xc bank_mask:0xf")
+            : "=&v"(t) : "v"(r[0]), "v"(r[1]), "v"(r[0]), "v"(r[1]));
+    }
+    return t;
+}
+
+// partner lane ^ (K - 1), the mirror image inside aligned blocks of K lanes
+template <int K>
+__device__ __forceinline__ uint32_t ce_flip(uint32_t k, int lane) {
+    uint32_t t;
+    if constexpr (K == 2) {
+        t = cas32(k, dpp_perm<0xB1>(k), (lane & 1) == 0);
+    } else if constexpr (K == 4) {
+        t = cas32(k, dpp_perm<0x1B>(k), (lane & 2) == 0);
+    } else if constexpr (K == 8) {
+        asm(SG_MINMAX_DPP("row_half_mirror row_mask:0xf bank_mask:0x5", "row_half_mirror row_mask:0xf bank_mask:0xa")
+            : "=&v"(t) : "v"(k), "v"(k), "v"(k), "v"(k));
+    } else if constexpr (K == 16) {
+        asm(SG_MINMAX_DPP("row_mirror row_mask:0xf bank_mask:0x3", "row_mirror row_mask:0xf bank_mask:0xc")
+            : "=&v"(t) : "v"(k), "v"(k), "v"(k), "v"(k));
+    } else {
+        static_assert(K == 32, "block size");
+        // after the swap the even rows of r[0] and the odd rows of r[1] hold the lane's own
+        // key, the other register the key of the same position in the neighbouring row,
+        // which the row mirror turns into the partner's
+        const auto r = __builtin_amdgcn_permlane16_swap(k, k, false, false);
+        asm(SG_MINMAX_DPP("row_mirror row_mask:0x5 bank_mask:0xf", "row_mirror row_mask:0xa bank_mask:0xf")
+            : "=&v"(t) : "v"(r[1]), "v"(r[0]), "v"(r[0]), "v"(r[1]));
+    }
+    return t;
+}
+
+// complements the keys of the rows in RM (a descending block is held complemented
+// and sorted ascending)
+#define SG_NOT_ROWS(RM) "s_nop 1\n\tv_not_b32_dpp %0, %0 quad_perm:[0,1,2,3] row_mask:" RM " bank_mask:0xf\n\ts_nop 1"
+
+// Half-cleaners at distances J, J/2, ..., 1.
 template <int J, int NB>
 __device__ __forceinline__ void merge32(uint32_t (&k)[NB], int lane) {
     if constexpr (J >= 1) {
 #pragma unroll
-        for (int b = 0; b < NB; b++) k[b] = cas32(k[b], xor_lane<J>(k[b]), (lane & J) == 0);
+        for (int b = 0; b < NB; b++) k[b] = ce_xor<J>(k[b], lane);
         merge32<J / 2, NB>(k, lane);
     }
 }
 
 // 64 * NB keys, element e = lane + 64*slot, sorted ascending in place; with KMAX = 32
-// each half of the wave is sorted on its own
+// each half of the wave is sorted on its own.  Bitonic: blocks of K = 2 .. 32 lanes
+// begin with a compare of mirror images and continue with half-cleaners.  Blocks of 64
+// and 128 elements begin with a half-cleaner instead, which needs the second half
+// sorted descending: lanes 32-63 are held complemented from their 32-lane merge on
+// (so that it sorts them descending) and restored before the 64-lane merge, and the
+// second register is held complemented through its 64-lane merge.
 template <int K, int NB, int KMAX>
 __device__ __forceinline__ void sort32(uint32_t (&k)[NB], int lane) {
-    if constexpr (K <= 64 && K <= KMAX) {
+    if constexpr (K <= 32 && K <= KMAX) {
+        if constexpr (K == 32 && KMAX >= 64) {
 #pragma unroll
-        for (int b = 0; b < NB; b++) k[b] = cas32(k[b], flip_lane<K>(k[b]), (lane & (K / 2)) == 0);
+            for (int b = 0; b < NB; b++) asm(SG_NOT_ROWS("0xc") : "+v"(k[b]));
+        }
+#pragma unroll
+        for (int b = 0; b < NB; b++) k[b] = ce_flip<K>(k[b], lane);
         merge32<K / 4, NB>(k, lane);
         sort32<K * 2, NB, KMAX>(k, lane);
+    } else if constexpr (K == 64 && K <= KMAX) {
+        // the first register: ascending, then descending; the second: its lanes 0-31
+        // complemented too, so that its merge leaves it complemented and ascending
+        asm(SG_NOT_ROWS("0xc") : "+v"(k[0]));
+        if constexpr (NB == 2) asm(SG_NOT_ROWS("0x3") : "+v"(k[1]));
+        merge32<32, NB>(k, lane);
+        sort32<128, NB, KMAX>(k, lane);
     } else if constexpr (K == 128 && NB == 2) {
-        // mirror of element lane (slot 0) is element 127 - lane = slot 1 of lane 63 - lane
-        const uint32_t f0 = flip_lane<64>(k[0]), f1 = flip_lane<64>(k[1]);
-        k[0] = f1 < k[0] ? f1 : k[0];
-        k[1] = f0 > k[1] ? f0 : k[1];
+        // element e + 64 (the second register, now descending) against element e
+        const uint32_t d = ~k[1];
+        const uint32_t lo = d < k[0] ? d : k[0], hi = d < k[0] ? k[0] : d;
+        k[0] = lo;
+        k[1] = hi;
         merge32<32, NB>(k, lane);
     }
 }
