@@ -22,41 +22,36 @@ struct PairLds {
     uint8_t pi_r[33];                    // bit index of each rank
 };
 
-__device__ __forceinline__ uint32_t half_xor(uint32_t v) {
-    v ^= xor_lane<1>(v);
-    v ^= xor_lane<2>(v);
-    v ^= xor_lane<4>(v);
-    v ^= xor_lane<8>(v);
-    v ^= xor_lane<16>(v);
-    return v;
-}
+// Half-wave totals: the row prefix of the wave reductions (word.hpp) and the broadcast of
+// lane 15 into rows 1 and 3 leave each half's total in its last lane (31, 63); every lane
+// receives its own half's.
+#define SG_HALF_REDUCE(IN, OP)                                                         \
+    do {                                                                               \
+        v = v OP IN<0x111, 0xF, true>(v);   /* row_shr:1 */                            \
+        v = v OP IN<0x112, 0xF, true>(v);   /* row_shr:2 */                            \
+        v = v OP IN<0x114, 0xF, true>(v);   /* row_shr:4 */                            \
+        v = v OP IN<0x118, 0xF, true>(v);   /* row_shr:8 */                            \
+        v = v OP IN<0x142, 0xA, false>(v);  /* row_bcast:15 into rows 1 and 3 */       \
+    } while (0)
 
-__device__ __forceinline__ uint32_t half_add(uint32_t v) {
-    v += xor_lane<1>(v);
-    v += xor_lane<2>(v);
-    v += xor_lane<4>(v);
-    v += xor_lane<8>(v);
-    v += xor_lane<16>(v);
-    return v;
-}
-
-__device__ __forceinline__ double half_sum(double v) {
-    v += xor_lane_f64<1>(v);
-    v += xor_lane_f64<2>(v);
-    v += xor_lane_f64<4>(v);
-    v += xor_lane_f64<8>(v);
-    v += xor_lane_f64<16>(v);
-    return v;
-}
-
-// the value held by the first lane of the lane's half
-__device__ __forceinline__ double half_first(double v, int lane) {
-    const double a = readlane_f64(v, 0), b = readlane_f64(v, 32);
+__device__ __forceinline__ uint32_t half_pick_u(uint32_t v, int lane, int l0) {
+    const uint32_t a = __builtin_amdgcn_readlane(v, l0), b = __builtin_amdgcn_readlane(v, l0 + 32);
     return lane < 32 ? a : b;
 }
 
-__device__ __forceinline__ uint32_t half_first_u(uint32_t v, int lane) {
-    const uint32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 32);
+__device__ __forceinline__ uint32_t half_xor(uint32_t v, int lane) {
+    SG_HALF_REDUCE(dpp_in, ^);
+    return half_pick_u(v, lane, 31);
+}
+
+__device__ __forceinline__ uint32_t half_add(uint32_t v, int lane) {
+    SG_HALF_REDUCE(dpp_in, +);
+    return half_pick_u(v, lane, 31);
+}
+
+__device__ __forceinline__ double half_sum(double v, int lane) {
+    SG_HALF_REDUCE(dpp_in_f64, +);
+    const double a = readlane_f64(v, 31), b = readlane_f64(v, 63);
     return lane < 32 ? a : b;
 }
 
@@ -105,7 +100,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
     const int ybit = valid && lam < 0.0;
     const uint64_t yb = __ballot(ybit);
     const int par = __popc(upper ? (uint32_t)(yb >> 32) : (uint32_t)yb) & 1;
-    const uint32_t s0 = half_xor(ybit ? gptr(c.hcol)[hl] : 0u);
+    const uint32_t s0 = half_xor(ybit ? gptr(c.hcol)[hl] : 0u, lane);
     const double a = fabs(lam);
     const uint64_t key = valid ? (uint64_t)__double_as_longlong(a) : ~0ull;
     const double rho = valid ? exp_neg<TABLE>(a) : 0.0;
@@ -120,7 +115,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
         cnt += (k0 < key) ? 1u : 0u;
         cnt += (k1 < key) ? 1u : 0u;
     }
-    const uint32_t tot = half_first_u(half_add(valid ? cnt : 0u), lane);
+    const uint32_t tot = half_add(valid ? cnt : 0u, lane);
     const bool exact_pass = tot != (uint32_t)(n * (n - 1) / 2);
     if (exact_pass) {
         for (int j = 0; j < n; j++) {
@@ -154,10 +149,14 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
         E = e2;
         O = o2;
     }
-    eo_combine<1>(E, O);
-    eo_combine<2>(E, O);
-    E = half_first(E, lane);
-    O = half_first(O, lane);
+    eo_prefix<1>(E, O);
+    eo_prefix<2>(E, O);
+    {
+        const double e0 = readlane_f64(E, 3), e1 = readlane_f64(E, 35);
+        const double o0 = readlane_f64(O, 3), o1 = readlane_f64(O, 35);
+        E = lane < 32 ? e0 : e1;
+        O = lane < 32 ? o0 : o1;
+    }
 
     // 4. query loop: each half tests 32 patterns of its word's class schedule per round
     const int cls = c.even ? par : 0;
@@ -223,7 +222,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
         // tested nonzero-pattern mass before this round, for the list-BLER stop
         double s_before = 0.0;
         if constexpr (STOP) {
-            s_before = half_first(half_sum(s_lane), lane);
+            s_before = half_sum(s_lane, lane);
             const double tested = half_scan_add((act && (e.x & 0xffu) != 0u) ? tau : 0.0, hl);
             S.key_b[hl] = (uint64_t)__double_as_longlong(tested);
         }
@@ -288,7 +287,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
         }
     }
 
-    const double Snz = half_first(half_sum(s_lane), lane);
+    const double Snz = half_sum(s_lane, lane);
 
     // 5. Corollary 1 inside the parity class (as decode_word)
     wave_sync();
@@ -334,7 +333,7 @@ __device__ __forceinline__ WordStats decode_pair(const DevCode &c, int L, uint32
 #ifdef SG_PHASE_CLOCKS
     for (int q = 0; q < kPhases; q++) st.phase[q] = 0u;   // pairs are not timed by phase
 #endif
-    if (count) st.ranks = half_first_u(half_add(w_lane), lane);
+    if (count) st.ranks = half_add(w_lane, lane);
     return st;
 }
 

@@ -114,41 +114,53 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
     }
 }
 
-template <int M>
-__device__ __forceinline__ double xor_lane_f64(double v) {
-    const uint64_t u = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = xor_lane<M>((uint32_t)u), hi = xor_lane<M>((uint32_t)(u >> 32));
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    uint64_t u = (uint64_t)__double_as_longlong(v);
+    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
+    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// Wave reductions: a prefix over each row of 16 lanes by DPP row shifts that read zero
+// past the row's start (1, 2, 4, 8), then the row broadcasts (lane 15 of rows 0 and 2
+// into rows 1 and 3, lane 31 into rows 2 and 3), leave the total in lane 63, which
+// readlane makes wave-uniform: six DPP steps, against the exchange of every lane with
+// its partner at six distances.  Zero is the identity of each operation.
+template <int CTRL, int ROWS, bool ZERO>
+__device__ __forceinline__ uint32_t dpp_in(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, ZERO);
+}
+
+template <int CTRL, int ROWS, bool ZERO>
+__device__ __forceinline__ double dpp_in_f64(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = dpp_in<CTRL, ROWS, ZERO>((uint32_t)u), hi = dpp_in<CTRL, ROWS, ZERO>((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+#define SG_WAVE_REDUCE(IN, OP)                                                         \
+    do {                                                                               \
+        v = v OP IN<0x111, 0xF, true>(v);   /* row_shr:1 */                            \
+        v = v OP IN<0x112, 0xF, true>(v);   /* row_shr:2 */                            \
+        v = v OP IN<0x114, 0xF, true>(v);   /* row_shr:4 */                            \
+        v = v OP IN<0x118, 0xF, true>(v);   /* row_shr:8 */                            \
+        v = v OP IN<0x142, 0xA, false>(v);  /* row_bcast:15 into rows 1 and 3 */       \
+        v = v OP IN<0x143, 0xC, false>(v);  /* row_bcast:31 into rows 2 and 3 */       \
+    } while (0)
+
 __device__ __forceinline__ uint32_t wave_xor(uint32_t v) {
-    v ^= xor_lane<1>(v);
-    v ^= xor_lane<2>(v);
-    v ^= xor_lane<4>(v);
-    v ^= xor_lane<8>(v);
-    v ^= xor_lane<16>(v);
-    v ^= xor_lane<32>(v);
-    return v;
+    SG_WAVE_REDUCE(dpp_in, ^);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
 }
 
 __device__ __forceinline__ uint32_t wave_add(uint32_t v) {
-    v += xor_lane<1>(v);
-    v += xor_lane<2>(v);
-    v += xor_lane<4>(v);
-    v += xor_lane<8>(v);
-    v += xor_lane<16>(v);
-    v += xor_lane<32>(v);
-    return v;
+    SG_WAVE_REDUCE(dpp_in, +);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-    v += xor_lane_f64<1>(v);
-    v += xor_lane_f64<2>(v);
-    v += xor_lane_f64<4>(v);
-    v += xor_lane_f64<8>(v);
-    v += xor_lane_f64<16>(v);
-    v += xor_lane_f64<32>(v);
-    return v;
+    SG_WAVE_REDUCE(dpp_in_f64, +);
+    return readlane_f64(v, kWave - 1);
 }
 
 // inclusive prefix sum over lanes: lane l gets v(0) + ... + v(l), added in lane order
@@ -165,25 +177,14 @@ __device__ __forceinline__ double wave_scan_add(double v, int lane) {
     return v;
 }
 
-__device__ __forceinline__ double bcast0(double v) {
-    uint64_t u = (uint64_t)__double_as_longlong(v);
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    uint64_t u = (uint64_t)__double_as_longlong(v);
-    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
-    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
 // parity-class masses of two disjoint bit sets combined (see decode_word step 3):
-// E = E1 + E2 (1 + E1) + O1 O2 and O = O1 (1 + E2) + O2 (1 + E1), sums of positive terms
+// E = E1 + E2 (1 + E1) + O1 O2 and O = O1 (1 + E2) + O2 (1 + E1), sums of positive terms.
+// The second set is that of lane - M in the same row, or the empty set past the row's
+// start (E2 = O2 = 0, which leaves E and O exactly as they are): after M = 1, 2, 4, ...,
+// lane t holds the masses of the union of the sets of lanes 0 .. t of its row.
 template <int M>
-__device__ __forceinline__ void eo_combine(double &E, double &O) {
-    const double E2 = xor_lane_f64<M>(E), O2 = xor_lane_f64<M>(O);
+__device__ __forceinline__ void eo_prefix(double &E, double &O) {
+    const double E2 = dpp_in_f64<0x110 + M, 0xF, true>(E), O2 = dpp_in_f64<0x110 + M, 0xF, true>(O);
     const double t1 = 1.0 + E, t2 = 1.0 + E2;
     const double nE = fma(O, O2, fma(E2, t1, E));
     const double nO = fma(O, t2, O2 * t1);
@@ -754,8 +755,8 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
 
     // 3. parity-class masses: adding bit i maps (E, O) to (E + O rho_i, O + (1 + E) rho_i);
     //    two disjoint bit sets combine as E = E1 + E2 + E1 E2 + O1 O2, O = O1 + O2 + E1 O2 + O1 E2.
-    //    Lane t folds ranks 8t+1 .. 8t+8 in turn, then NS/8 lanes combine pairwise (lanes
-    //    past NS/8 repeat the last group; their sums are never combined into lane 0's).
+    //    Lane t folds ranks 8t+1 .. 8t+8 in turn, then lane NS/8 - 1 gathers the NS/8 groups
+    //    by a prefix over its row (lanes past NS/8 repeat the last group; they never enter it).
     const int grp = lane < NS / 8 ? lane : NS / 8 - 1;
     double E = 0.0, O = rho_at(S, 8 * grp + 1);   // the first rank from (0, 0): (0, rho)
 #pragma unroll
@@ -766,12 +767,12 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         E = e2;
         O = o2;
     }
-    eo_combine<1>(E, O);
-    eo_combine<2>(E, O);
-    if constexpr (NS >= 64) eo_combine<4>(E, O);
-    if constexpr (NS >= 128) eo_combine<8>(E, O);
-    E = bcast0(E);
-    O = bcast0(O);
+    eo_prefix<1>(E, O);
+    eo_prefix<2>(E, O);
+    if constexpr (NS >= 64) eo_prefix<4>(E, O);
+    if constexpr (NS >= 128) eo_prefix<8>(E, O);
+    E = readlane_f64(E, NS / 8 - 1);
+    O = readlane_f64(O, NS / 8 - 1);
     SG_CLOCK(t3);
 
     // 4. query loop over the schedule of the word's parity class; the next chunk's
@@ -870,7 +871,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
                 // for the list so far, with the mass tested up to and including the hit (class
                 // mass relative to p(0|r), nonzero patterns only)
                 const double T = c.even ? (par ? O : E) : (E + O);
-                const double s_before = bcast0(wave_sum(s_lane));
+                const double s_before = wave_sum(s_lane);
                 const double tested = wave_scan_add((act && (e.x & 0xffu) != 0u) ? tau : 0.0, lane);
                 wave_sync();
                 uint64_t mm = m;
@@ -904,7 +905,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         Q = limit < nb ? limit : nb;
     }
 
-    const double Snz = bcast0(wave_sum(s_lane));
+    const double Snz = wave_sum(s_lane);
     SG_CLOCK(t4);
 
     // 5. Corollary 1 inside the parity class: not-found mass M = (class mass) - (tested mass),
