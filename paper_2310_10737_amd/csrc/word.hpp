@@ -492,6 +492,15 @@ struct Coef {
     }
 };
 
+// p x + c as one three-operand FMA with c in a scalar register pair.  Left to itself the
+// compiler picks the two-operand form, whose addend is the destination, and copies c into
+// it with two VALU moves per step.
+__device__ __forceinline__ double fma_sc(double p, double x, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(x), "s"(c));
+    return r;
+}
+
 // e^{-a}, a >= 0, by Tang's table-driven method (ACM TOMS 15(2), 1989): a = N ln2/64 + r
 // with |r| <= ln2/128 (Cody-Waite, two-part ln2/64), N = 64k + j, and
 // e^{-a} = 2^{-k} 2^{-j/64} e^{-r}, with e^{-r} from its degree-6 Taylor polynomial
@@ -526,7 +535,7 @@ __device__ __forceinline__ double log_mant(double m) {
     const Coef<TABLE> t;
     double p = t[kLogAt];
 #pragma unroll
-    for (int j = 1; j < kLogTerms; j++) p = fma(p, u, t[kLogAt + j]);
+    for (int j = 1; j < kLogTerms; j++) p = fma_sc(p, u, t[kLogAt + j]);
     p = fma(p, u, 1.0);
     return fma(p, u, cl.y);
 }
