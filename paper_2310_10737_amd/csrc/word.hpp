@@ -508,7 +508,7 @@ __device__ __forceinline__ double fma_sc(double p, double x, double c) {
 template <bool TABLE>
 __device__ __forceinline__ double exp_neg(double a) {
     const Coef<TABLE> t;
-    const double ac = a < 1100.0 ? a : 1100.0;
+    const double ac = fmin(a, 1100.0);
     const double N = rint(ac * t[k64InvLn2At]);
     double r = fma(-N, t[kLn2d64HiAt], ac);
     r = fma(-N, t[kLn2d64LoAt], r);
@@ -808,26 +808,33 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     uint32_t Q = 0;
     double s_lane = 0.0;   // this lane's share of the tested nonzero-pattern mass (relative to p(0|r))
     uint32_t w_lane = 0;   // this lane's share of the tested pattern weights (counting only)
-    // patterns of the next two chunks are in flight while a chunk is tested; the schedule
+    // The chunks' weight bounds are wave-uniform and the table is not written while
+    // kernels decode: read through the constant address space they are scalar loads, and
+    // the branches on them scalar branches.  Each chunk's patterns are addressed as a
+    // scalar base plus the lane's offset.
+    typedef const __attribute__((address_space(4))) uint32_t cu32;
+    const cu32 *wms = (const cu32 *)wm;
+    // Patterns of the next two chunks are in flight while a chunk is tested; the schedule
     // ends in two chunks of zero patterns, so whole chunks load without per-lane bounds
-    // (a lane at or past `limit` tests whatever it loaded but never counts)
-    uint4 e_next = gload(tab, lane), e_next2 = gload(tab, kWave + lane);
-    uint32_t wm_next = wm[0];
-    uint32_t wm_next2 = limit > (uint32_t)kWave ? wm[1] : 0u;
+    // (a lane at or past `limit` tests whatever it loaded but never counts).
+    uint4 e_next = gload(tab, lane), e_next2 = gload(tab + kWave, lane);
+    uint32_t wm_next = wms[0];
+    uint32_t wm_next2 = limit > (uint32_t)kWave ? wms[1] : 0u;
     for (uint32_t base = 0; base < limit; base += kWave) {
         const uint4 e = e_next;
-        // wave-uniform; in the persistent kernels its load is a vector load, so the branches on it
-        // would otherwise be taken per lane under exec masks
-        const uint32_t wmx = __builtin_amdgcn_readfirstlane(wm_next);
+        const uint32_t wmx = wm_next;
         const uint32_t nb = base + kWave;
         e_next = e_next2;
         wm_next = wm_next2;
         const uint32_t nb2 = nb + kWave;
         if (nb2 < limit) {
-            e_next2 = gload(tab, nb2 + lane);
-            wm_next2 = wm[nb2 >> 6];
+            e_next2 = gload(tab + nb2, lane);
+            wm_next2 = wms[nb2 >> 6];
         }
-        const bool act = base + (uint32_t)lane < limit;
+        // lanes below the limit (all of them but in the last chunk), as a scalar mask
+        const uint32_t left = limit - base;
+        const uint64_t actm = left >= (uint32_t)kWave ? ~0ull : (1ull << left) - 1ull;
+        const bool act = __builtin_amdgcn_inverse_ballot_w64(actm);
         uint32_t s = s0;
         double tau = 1.0;
         // ranks in straight-line pairs (rank 0 pads: hs 0, rho 1), so that both
@@ -850,10 +857,10 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
                 }
             }
         }
-        const bool hit = act && s == 0u;
-        const uint64_t m = __ballot(hit);
+        const uint64_t m = __ballot(s == 0u) & actm;
         int cut = kWave - 1;
         if (m != 0ull) {
+            const bool hit = __builtin_amdgcn_inverse_ballot_w64(m);
             // every hit that still fits in the list writes its own entry (slot = hits so far
             // plus the hits of lower lanes); with the list-BLER stop, entries past the stop
             // are written too and ignored
@@ -904,9 +911,13 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
                 }
             }
         }
-        const bool nonzero = (e.x & 0xffu) != 0u;
-        if (act && nonzero && lane <= cut) s_lane += tau;
-        if (count && act && lane <= cut) w_lane += pattern_weight(e);
+        // the tested lanes: below the limit and up to the cut; the mass leaves out the zero
+        // pattern, which only the first query of a class can be
+        const uint64_t upto = actm & (cut == kWave - 1 ? ~0ull : (2ull << cut) - 1ull);
+        uint64_t take = upto;
+        if (base == 0u) take &= __ballot((e.x & 0xffu) != 0u);
+        if (__builtin_amdgcn_inverse_ballot_w64(take)) s_lane += tau;
+        if (count && __builtin_amdgcn_inverse_ballot_w64(upto)) w_lane += pattern_weight(e);
         if (found >= L || stopped) {
             Q = base + (uint32_t)cut + 1u;
             break;
