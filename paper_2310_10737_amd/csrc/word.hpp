@@ -328,7 +328,10 @@ __device__ __forceinline__ void sort32(uint32_t (&k)[NB], int lane) {
 
 // v from lane + 1 (lane 63 reads lane 0)
 __device__ __forceinline__ uint32_t next_lane(uint32_t v) {
-    return (uint32_t)__shfl((int)v, (int)((threadIdx.x + 1) & (kWave - 1)));
+    // DPP wave_shl:1 moves every lane's value to the lane below; lane 63 reads zero
+    const uint32_t w = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, true);
+    const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+    return (threadIdx.x & (kWave - 1)) == kWave - 1 ? first : w;
 }
 
 // The same pointer in the global address space.  Pointers that reach a kernel through
