@@ -10,8 +10,8 @@
 // One 64-lane wavefront decodes one component word:
 //   1. hard decision y, its syndrome s0 = XOR of the H columns where y = 1 and
 //      its parity (section "Background on GRAND": H c = 0; even-code parity);
-//   2. reliability ranks of (|lambda|, index): counting smaller keys, or a bitonic
-//      network across lanes over 32-bit keys with an exact fallback;
+//   2. reliability ranks of (|lambda|, index): a bitonic network across lanes over
+//      32-bit keys, with an exact counting fallback for near-ties;
 //   3. rho_i = exp(-|lambda_i|), so that p(z|r) = p(0|r) prod_{i in z} rho_i
 //      (the bookkeeping of section "GRAND per block SO": p(z) from p(0) in w(z)
 //      operations), and the parity-class masses E, O (sums of prod rho over
@@ -33,7 +33,7 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 // query loop reads both with one LDS instruction into an aligned register pair.
 struct WaveLds {
     uint4 ent_r[SOGRAND_NMAX + 4];       // by rank (1..n): rho (x, y), H column (z); [0]: rho 1, H 0
-    uint64_t key_b[SOGRAND_NMAX + 2];    // |lambda| bit patterns by bit index, padded with ~0
+    uint64_t key_b[SOGRAND_NMAX + 2];    // |lambda| bit patterns by bit index (the exact ranking pass)
     double tau_l[SOGRAND_LIST_MAX];      // prod rho of each found pattern
     uint4 pat_l[SOGRAND_LIST_MAX];       // found patterns (ranks)
     uint32_t q_l[SOGRAND_LIST_MAX];      // query number of each found codeword
@@ -618,33 +618,6 @@ __device__ __forceinline__ void put_rho(LDS &S, int r, double v) {
 // index (non-negative doubles order like their bit patterns), ties by bit index.
 // Returns whether the exact tie-resolving pass ran.
 //
-// By counting: a lane's rank is the number of smaller keys.  The ranks sum to
-// n(n-1)/2 unless equal keys exist, and then each group of equal keys is ordered
-// by bit index.
-__device__ __forceinline__ bool ranks_by_count(uint64_t key, bool valid, int n, WaveLds &S, int lane,
-                                               int &myrank) {
-    bool exact_pass = false;
-    S.key_b[lane] = key;
-    if (lane < 2) S.key_b[kWave + lane] = ~0ull;
-    wave_sync();
-    uint32_t cnt = 0;
-    for (int j = 0; j < n; j += 2) {
-        const uint64_t k0 = S.key_b[j], k1 = S.key_b[j + 1];
-        cnt += (k0 < key) ? 1u : 0u;
-        cnt += (k1 < key) ? 1u : 0u;
-    }
-    const uint32_t tot = __builtin_amdgcn_readfirstlane(wave_add(valid ? cnt : 0u));
-    if (tot != (uint32_t)(n * (n - 1) / 2)) {
-        exact_pass = true;
-        for (int j = 0; j < n; j++) {
-            const uint64_t kj = S.key_b[j];
-            cnt += (kj == key && j < lane) ? 1u : 0u;
-        }
-    }
-    myrank = valid ? (int)cnt + 1 : 0;
-    return exact_pass;
-}
-
 // By a bitonic network over 32-bit keys: |lambda| rounded to binary32 (a monotone
 // map) with its low IB bits replaced by the bit index, so the keys are distinct.  If
 // two neighbours of the sorted order agree above bit IB, the rounding or the
@@ -736,15 +709,9 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     const int par = ycount & 1;
     SG_CLOCK(t1);
 
-    // 2. reliability ranks (|lambda| ascending, ties by bit index).  The plain kernels
-    //    count smaller keys for words of up to 64 bits: two VALU operations per key, with
-    //    the keys read back from LDS, whose latency their full occupancy hides.  The
-    //    persistent and served kernels, which hold fewer waves per SIMD, and all words
-    //    of 128 bits use a sorting network instead.
+    // 2. reliability ranks (|lambda| ascending, ties by bit index) by the sorting network
     int myrank[NB];
-    bool exact_pass;
-    if constexpr (NB == 1 && !TABLE) exact_pass = ranks_by_count(key[0], valid[0], n, S, lane, myrank[0]);
-    else exact_pass = ranks_by_network<NS, NB>(key, valid, n, S, lane, myrank);
+    const bool exact_pass = ranks_by_network<NS, NB>(key, valid, n, S, lane, myrank);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         const int i = lane + kWave * b;
