@@ -219,7 +219,7 @@ __device__ __forceinline__ bool slot_valid(const SlotLds &sl, const DevCode &c, 
 // of the second otherwise.  Frame positions are variable nodes: bit i of a
 // product row is line*n + i, of a column i*n + line; bit i of a QC-GLDPC word is
 // i*n + line in the first block row and i*n + (line + i) mod n in the second.
-template <typename T, int NS, bool STOP, int TOPO>
+template <typename T, int NS, bool STOP, int TOPO, bool LDSLOG>
 __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl, const DevCode &c,
                                                 const DevCode *cdev, int frame,
                                                 int h, int line, T *la, WaveLds &S, int lane) {
@@ -244,7 +244,7 @@ __device__ __forceinline__ WordStats batch_line(const BatchArgs &a, SlotLds &sl,
         lam[b] = i < n ? (double)ch[pos[b]] + (h > 1 ? (double)la[pos[b]] : 0.0) : 0.0;
     }
     double lapp[NB];
-    const WordStats st = decode_word<NS, true, STOP>(c, cdev, a.L, a.qcap, a.pstop, lam, S, lapp, lane,
+    const WordStats st = decode_word<NS, true, STOP, LDSLOG>(c, cdev, a.L, a.qcap, a.pstop, lam, S, lapp, lane,
                                                      a.prof != nullptr);
     uint64_t hm[2] = {0ull, 0ull};
 #pragma unroll
@@ -363,6 +363,9 @@ void k_batched(BatchArgs a) {
             slot_refill(a, sls[s]);
             slot_publish(sls[s]);
         }
+    // the 128-bit instantiations (6 waves per SIMD) read the logarithm's table from LDS; at the
+    // 64-bit one's 8 waves the table reads added to the query loop's LDS traffic cost more
+    if constexpr (NSMAX == 128) fill_log_table();
     __syncthreads();
     T *la_base = static_cast<T *>(a.la) + (size_t)blockIdx.x * nslots * a.nmax * a.nmax;
     uint32_t idle = 0;
@@ -439,8 +442,8 @@ void k_batched(BatchArgs a) {
             for (int line = first; line < last; line++) {
                 WordStats st;
                 SG_CLOCK(l0);
-                if (NSMAX == 64 || n <= 64) st = batch_line<T, 64, STOP, TOPO>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
-                else st = batch_line<T, 128, STOP, TOPO>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
+                if (NSMAX == 64 || n <= 64) st = batch_line<T, 64, STOP, TOPO, NSMAX == 128>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
+                else st = batch_line<T, 128, STOP, TOPO, NSMAX == 128>(a, sl, c, a.codes + code, frame, h, line, la, S, lane);
 #ifdef SG_PHASE_CLOCKS
                 SG_CLOCK(l1);
                 uint32_t inner = 0;

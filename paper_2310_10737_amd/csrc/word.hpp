@@ -528,12 +528,20 @@ __device__ __forceinline__ double exp_neg(double a) {
 // the centre of m's interval of width 1/256 (m's leading 8 mantissa bits and a 1 after
 // them), f = m - F is exact, u = f / F (|u| < 2^-8), and ln m = ln F + ln(1 + u), the
 // latter from its degree-7 series (truncation below 2^-67)
-template <bool TABLE>
+// The persistent kernel's workgroups keep a copy of the table of interval centres in LDS
+// (filled once per workgroup by fill_log_table), read by log_mant<TABLE, true>.
+static __shared__ double2 sLogCentre[128];
+
+__device__ __forceinline__ void fill_log_table() {
+    for (int i = (int)threadIdx.x; i < 128; i += (int)blockDim.x) sLogCentre[i] = kLogCentre[i];
+}
+
+template <bool TABLE, bool LDSLOG = false>
 __device__ __forceinline__ double log_mant(double m) {
     const uint64_t bits = (uint64_t)__double_as_longlong(m);
     const uint32_t hi = (uint32_t)(bits >> 32);
     const double F = __longlong_as_double((long long)((uint64_t)((hi & 0xffffe000u) | 0x1000u) << 32));
-    const double2 cl = kLogCentre[(hi >> 13) & 127u];
+    const double2 cl = LDSLOG ? sLogCentre[(hi >> 13) & 127u] : kLogCentre[(hi >> 13) & 127u];
     const double u = (m - F) * cl.x;
     const Coef<TABLE> t;
     double p = t[kLogAt];
@@ -545,13 +553,13 @@ __device__ __forceinline__ double log_mant(double m) {
 
 // ln(N0 / N1) for N0, N1 >= 0 not both zero: N = m 2^e with m in [1/2, 1); the
 // exponents' difference is added as a multiple of ln 2
-template <bool TABLE>
+template <bool TABLE, bool LDSLOG = false>
 __device__ __forceinline__ double log_ratio(double n0, double n1) {
     const double m0 = __builtin_amdgcn_frexp_mant(n0), m1 = __builtin_amdgcn_frexp_mant(n1);
     const int e0 = __builtin_amdgcn_frexp_exp(n0), e1 = __builtin_amdgcn_frexp_exp(n1);
     const double de = (double)(e0 - e1);
     const Coef<TABLE> t;
-    double la = fma(de, t[kLn2HiAt], fma(de, t[kLn2LoAt], log_mant<TABLE>(m0) - log_mant<TABLE>(m1)));
+    double la = fma(de, t[kLn2HiAt], fma(de, t[kLn2LoAt], log_mant<TABLE, LDSLOG>(m0) - log_mant<TABLE, LDSLOG>(m1)));
     if (n1 == 0.0) la = 1000.0;
     if (n0 == 0.0) la = -1000.0;
     return la;
@@ -678,7 +686,7 @@ __device__ __forceinline__ bool ranks_by_network(const uint64_t (&key)[NB], cons
 // Decodes one word held as lam[slot] at bit index lane + 64*slot (< n).
 // Writes the APP LLRs of the lane's bits into lapp; the list is left in S.
 // STOP: the list-BLER stop is compiled in (pstop > 0 selects it at launch).
-template <int NS, bool TABLE = false, bool STOP = false>
+template <int NS, bool TABLE = false, bool STOP = false, bool LDSLOG = false>
 __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode *cdev, int L, uint32_t qcap,
                                                  double pstop,
                                                  const double (&lam)[Lanes<NS>::NB], WaveLds &S,
@@ -952,7 +960,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        double la = log_ratio<TABLE>(N0[b], N1[b]);
+        double la = log_ratio<TABLE, LDSLOG>(N0[b], N1[b]);
         if (!(la <= 1000.0)) la = 1000.0;
         if (!(la >= -1000.0)) la = -1000.0;
         lapp[b] = la;
