@@ -508,7 +508,10 @@ __device__ __forceinline__ double fma_sc(double p, double x, double c) {
 // with |r| <= ln2/128 (Cody-Waite, two-part ln2/64), N = 64k + j, and
 // e^{-a} = 2^{-k} 2^{-j/64} e^{-r}, with e^{-r} from its degree-6 Taylor polynomial
 // (truncation below 2^-64 relative)
-template <bool TABLE>
+// The 128-bit persistent instantiations also keep 2^(-j/64) in LDS (fill_log_table).
+static __shared__ double sExp2Frac[64];
+
+template <bool TABLE, bool LDSLOG = false>
 __device__ __forceinline__ double exp_neg(double a) {
     const Coef<TABLE> t;
     const double ac = fmin(a, 1100.0);
@@ -521,7 +524,7 @@ __device__ __forceinline__ double exp_neg(double a) {
     for (int j = 1; j < kExpTerms; j++) p = fma(p, x, t[kExpAt + j]);
     p = fma(p, x, 1.0);
     const int Ni = (int)N;
-    return ldexp(kExp2Frac[Ni & 63] * p, -(Ni >> 6));
+    return ldexp((LDSLOG ? sExp2Frac[Ni & 63] : kExp2Frac[Ni & 63]) * p, -(Ni >> 6));
 }
 
 // ln m for m in [1/2, 1), by Tang's table-driven method (ACM TOMS 16(4), 1990): with F
@@ -532,8 +535,10 @@ __device__ __forceinline__ double exp_neg(double a) {
 // (filled once per workgroup by fill_log_table), read by log_mant<TABLE, true>.
 static __shared__ double2 sLogCentre[128];
 
+// copies the logarithm's and the exponential's tables into the workgroup's LDS
 __device__ __forceinline__ void fill_log_table() {
     for (int i = (int)threadIdx.x; i < 128; i += (int)blockDim.x) sLogCentre[i] = kLogCentre[i];
+    for (int i = (int)threadIdx.x; i < 64; i += (int)blockDim.x) sExp2Frac[i] = kExp2Frac[i];
 }
 
 template <bool TABLE, bool LDSLOG = false>
@@ -711,7 +716,7 @@ __device__ __forceinline__ WordStats decode_word(const DevCode &c, const DevCode
         ycount += __popcll(__ballot(ybit[b]));
         const double a = fabs(lam[b]);
         key[b] = valid[b] ? (uint64_t)__double_as_longlong(a) : ~0ull;
-        rho[b] = valid[b] ? exp_neg<TABLE>(a) : 0.0;
+        rho[b] = valid[b] ? exp_neg<TABLE, LDSLOG>(a) : 0.0;
     }
     const uint32_t s0 = wave_xor(spart);
     const int par = ycount & 1;
